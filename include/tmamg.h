@@ -1,0 +1,178 @@
+/*
+ * tmamg — DD-alpha-AMG solver for the twisted-mass clover Wilson operator
+ * on AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The operator (arXiv:1710.06198, Sec. 1 and Sec. 1.1) is
+ *     D(mu) = D + i mu Gamma5,
+ * with D the clover-improved Wilson operator in m0-normalisation:
+ *     D(mu) psi(x) = A(x) psi(x) + i mu g5 psi(x)
+ *        - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)],
+ *     A(x) = (m0 + 4) + c_sw (i/4) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *     m0 = 1/(2 kappa) - 4,
+ * chiral gamma basis (g5 = diag(1,1,-1,-1)), periodic space, antiperiodic
+ * time (optional).  The solver is the multigrid-preconditioned flexible
+ * Krylov method of Sec. 1.1, Eq. (1): post-smoothing by k sweeps of SAP,
+ * aggregation-based P from N_v adaptively built test vectors (Gamma5-
+ * compatible: Gamma5 P = P Gamma5,c), Galerkin D_c = P^dag D P and the
+ * coarse twisted-mass operator D_c(+-mu) = D_c +- i mu Gamma5,c with one P
+ * for both signs of mu.
+ *
+ * Buffers.  Every field pointer is DEVICE memory owned by the caller and
+ * valid for the duration of the call; the library copies what it keeps.
+ * Canonical layouts (complex128 = two doubles, x fastest):
+ *   gauge links   [4][T][Z][Y][X][3][3]      mu = 0..3 <-> x, y, z, t
+ *   spinor fields [n][T][Z][Y][X][4][3]      spin-colour index spin*3 + colour
+ *   force         [4][T][Z][Y][X][3][3]      traceless anti-Hermitian
+ *   coarse fields [n][Tc][Zc][Yc][Xc][d]     d = 2 N_v, index s*N_v + i
+ * Host pointers are marked "host".
+ *
+ * Ordering.  All work is ordered on the stream given at creation; every
+ * call returns after synchronising that stream (status and info are host
+ * values).  A context is not thread-safe.
+ *
+ * Errors.  Negative status: outputs undefined, tmamg_last_error() holds a
+ * message.  TMAMG_NOT_CONVERGED: x holds the best iterate and
+ * info.true_rel_resid its FP64 true residual.
+ */
+#ifndef TMAMG_H
+#define TMAMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmamg_ctx tmamg_ctx;
+
+typedef enum {
+  TMAMG_OK = 0,
+  TMAMG_NOT_CONVERGED = 1,
+  TMAMG_EINVAL = -1,     /* bad argument or parameter combination */
+  TMAMG_ENOMEM = -2,     /* device allocation failed */
+  TMAMG_EHIP = -3,       /* HIP runtime error */
+  TMAMG_ENUMERIC = -4,   /* NaN/Inf in input or breakdown */
+  TMAMG_ESTATE = -5      /* call order: e.g. solve before setup */
+} tmamg_status;
+
+enum { TMAMG_FP64 = 0, TMAMG_MIXED = 1 };                                          /* precision */
+enum { TMAMG_STORE_FP64 = 0, TMAMG_STORE_FP32 = 1, TMAMG_STORE_BF16 = 2, TMAMG_STORE_FP16 = 3 }; /* P, D_c */
+
+typedef struct {
+  int dims[4];          /* Lx, Ly, Lz, Lt */
+  int t_antiperiodic;   /* 1: fermion field antiperiodic in time */
+} tmamg_lattice;
+
+typedef struct {
+  int nlevels;          /* 1 (SAP only), 2 or 3 */
+  int agg[2][4];        /* aggregate shape per coarsening; agg[0] is also the fine SAP block */
+  int nv[2];            /* test vectors per coarsening (<= 64) */
+  int setup_iters;      /* adaptive setup iterations (v_i <- B v_i) */
+  int init_smooth;      /* smoother applications in the initial setup phase */
+  int sap_block1[4];    /* SAP block on the first coarse level (3 levels) */
+  int sap_sweeps[2];    /* k: SAP sweeps on the fine / first coarse level */
+  int mr_steps;         /* minimal-residual steps per SAP block solve */
+  int l2_iters;         /* FGMRES steps on the intermediate level (3 levels) */
+  double l2_tol;        /* its relative tolerance */
+  int coarsest_iters;   /* GMRES steps on the coarsest level */
+  double coarsest_tol;  /* its relative tolerance */
+  int restart;          /* outer FGMRES restart length (<= 127) */
+  int max_iter;         /* outer iteration limit (all cycles) */
+  int precision;        /* TMAMG_FP64 or TMAMG_MIXED */
+  int storage;          /* TMAMG_STORE_*: P and D_c storage in mixed precision */
+  double inner_tol;     /* mixed: relative reduction per FP32 inner cycle */
+  unsigned long long seed;  /* test-vector noise */
+} tmamg_params;
+
+typedef struct {
+  int status;              /* tmamg_status of the call */
+  int outer_iters;         /* FGMRES iterations summed over cycles */
+  int cycles;              /* restart cycles / reliable updates */
+  double true_rel_resid;   /* max over right-hand sides of ||b - D x|| / ||b|| (FP64) */
+  double t_setup_s;        /* last setup */
+  double t_solve_s;        /* this call */
+} tmamg_info;
+
+/* Fill *p with the defaults (2 levels, 4^4 aggregates, N_v = 12, 3 setup
+ * iterations, SAP k = 4 with 4 MR steps, FGMRES(30), FP64). */
+tmamg_status tmamg_default_params(tmamg_params* p);
+
+/* Create a context for one lattice.  hip_stream: a hipStream_t (NULL = the
+ * null stream).  Lattice extents must be multiples of agg[0] (and agg[1]
+ * on the coarse lattice); SAP needs an even number of blocks (or one) per
+ * dimension on every smoothed level.  *ctx is NULL on error. */
+tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream);
+
+/* Setup (Sec. 1.1 adaptive setup): copy the links U (device, canonical
+ * complex128), build the clover term for c_sw and m0 = 1/(2 kappa) - 4,
+ * then build the hierarchy at twisted mass mu: random test vectors,
+ * init_smooth smoother applications, setup_iters iterations of
+ * v_i <- B_MG v_i, Gram-Schmidt per aggregate and chirality (FP64), P and
+ * D_c.  Links must be SU(3) within 1e-6 (TMAMG_ENUMERIC otherwise). */
+tmamg_status tmamg_setup(tmamg_ctx* ctx, const void* U, double kappa, double csw, double mu);
+
+/* Setup update on new links U (same kappa, c_sw, mu): the existing test
+ * vectors are improved by `iters` further setup iterations (the paper
+ * updates with one iteration per physical-mass inversion). */
+tmamg_status tmamg_setup_update(tmamg_ctx* ctx, const void* U, int iters);
+
+/* Solve D(mu_r) x_r = b_r for r < nrhs, in one batch.  b, x: device,
+ * canonical spinors [nrhs].  mu_rhs: host [nrhs] signed twisted masses, or
+ * NULL for the setup mu on every right-hand side.  Stops when every
+ * ||b_r - D x_r|| / ||b_r|| <= tol (FP64 true residual). */
+tmamg_status tmamg_solve(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                         tmamg_info* info);
+
+/* Squared / shifted systems (D D^dag + sigma_r) x_r = b_r with one
+ * hierarchy: since D D^dag + sigma = D(mu') D(mu')^dag with
+ * mu' = sqrt(mu^2 + sigma), solve D(mu') w = b, then
+ * x = Gamma5 D(-mu')^-1 Gamma5 w (the two-step solve of Sec. 1.1).
+ * sigma: host [nrhs] (>= 0; sigma = 0 gives D D^dag). */
+tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
+                                 tmamg_info* info);
+
+/* Pseudofermion action S_f = phi^dag (D D^dag)^-1 phi at the setup mu and
+ * its force F_mu(x) = sum_a (dS/dw^a) T^a for U -> exp(w) U, T^a = i lambda^a/2
+ * (dS/dt = -2 sum tr(F w)); F is traceless anti-Hermitian.
+ * phi: device spinor [1]; F: device [4][T][Z][Y][X][3][3]; S: host. */
+tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info);
+
+/* The force for given X = (D D^dag)^-1 phi and Y = D^dag X (device spinors),
+ * without solves: F from the hopping and clover derivatives. */
+tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F);
+
+/* Operator hook for tests.  op: one of TMAMG_OP_*; level: 0 fine, 1, 2.
+ * in/out: device, canonical fields of that level, nrhs of them; mu_rhs host
+ * [nrhs] or NULL (setup mu). */
+enum {
+  TMAMG_OP_D64 = 0,       /* fine D(mu) in FP64 */
+  TMAMG_OP_D32 = 1,       /* fine D(mu) in FP32 (rounded in/out) */
+  TMAMG_OP_PROLONG = 2,   /* level -> level-1: out = P in (in: coarse field of level `level`) */
+  TMAMG_OP_RESTRICT = 3,  /* level -> level+1: out = P^dag in */
+  TMAMG_OP_DC = 4,        /* coarse D_c(mu) on level 1 or 2 */
+  TMAMG_OP_SAP = 5,       /* k SAP sweeps from zero on level 0 or 1: out ~ D^-1 in */
+  TMAMG_OP_PREC = 6       /* one multigrid cycle B_MG on level 0 or 1 */
+};
+tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
+                         const double* mu_rhs);
+
+/* Parity hooks.  set_test_vectors: the next setup starts from these N_v
+ * vectors of level `level` (device, canonical level fields) instead of noise.
+ * export: what = 0 copies P of coarsening `level` (N_v canonical fields of
+ * the finer level, complex128) to out; what = 1 copies D_c of level
+ * `level` (1 or 2) as complex128 [Vc][9][d][d] with blocks (self, +x, -x,
+ * +y, -y, +z, -z, +t, -t), each [column][row]. */
+tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void* v);
+tmamg_status tmamg_debug_export(tmamg_ctx* ctx, int what, int level, void* out);
+
+/* Sizes of level `level`: sites and dof per site (fine: 12). */
+tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int* dof);
+
+void tmamg_destroy(tmamg_ctx* ctx);
+
+/* Message for the last non-OK status of the calling thread. */
+const char* tmamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMAMG_H */

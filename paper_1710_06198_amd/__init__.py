@@ -1,0 +1,9 @@
+"""MI355X-native DD-alpha-AMG solver for the twisted-mass clover Wilson operator.
+
+The compute path is the HIP library libtmamg.so (include/tmamg.h); this
+package only marshals arguments to it (see binding.py) and builds it
+(build.py).
+"""
+from .binding import (Solver, Params, Info, default_params, load, TmamgError,  # noqa: F401
+                      FP64, MIXED, STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16,
+                      OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, EXPORTS)

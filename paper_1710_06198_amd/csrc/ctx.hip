@@ -1,0 +1,738 @@
+// Context, outer solvers and the C ABI entry points.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+using clk = std::chrono::steady_clock;
+
+// ------------------------------------------------------------------ Hier: typed hooks
+template <typename T, typename S>
+void Hier<T, S>::precond_d(const cplx<double>* v, cplx<double>* z, int nrhs, const double* mu) {
+  if constexpr (std::is_same<T, double>::value) precond(0, v, z, nrhs, mu);
+  else throw TmError{TMAMG_ESTATE, "FP64 cycle requested from an FP32 hierarchy"};
+}
+template <typename T, typename S>
+void Hier<T, S>::precond_f(const cplx<float>* v, cplx<float>* z, int nrhs, const double* mu) {
+  if constexpr (std::is_same<T, float>::value) precond(0, v, z, nrhs, mu);
+  else throw TmError{TMAMG_ESTATE, "FP32 cycle requested from an FP64 hierarchy"};
+}
+
+template <typename T, typename S>
+void Hier<T, S>::rebuild() {
+  if (nlev < 2) return;
+  build(0);
+  if (nlev >= 3) build(1);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::test_op(int op, int level, const void* in_, void* out_, int nrhs, const double* mu) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  ensure(nrhs);
+  const cplx<T>* in = static_cast<const cplx<T>*>(in_);
+  cplx<T>* out = static_cast<cplx<T>*>(out_);
+  auto need = [&](bool ok) { if (!ok) throw TmError{TMAMG_EINVAL, "operator not available on this level"}; };
+  switch (op) {
+    case TMAMG_OP_PROLONG:
+      need(level >= 1 && level < nlev);
+      if (level == 1) launch_prolong_fine<T, S>(c->fg, P0.p, nv0, in, out, nrhs, st);
+      else launch_prolong_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, in, out, nrhs, st);
+      break;
+    case TMAMG_OP_RESTRICT:
+      need(level >= 0 && level < nlev - 1);
+      if (level == 0) launch_restrict_fine<T, S>(c->fg, P0.p, nv0, in, out, nrhs, st);
+      else launch_restrict_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, in, out, nrhs, st);
+      break;
+    case TMAMG_OP_DC:
+      need(level >= 1 && level < nlev);
+      dc_apply(level, in, out, nrhs, mu);
+      break;
+    case TMAMG_OP_SAP: {
+      need(level == 0 || (level == 1 && nlev >= 3));
+      long n = level == 0 ? 12 * c->fg.V : g1.V * d1;
+      launch_fill_zero(out, (size_t)nrhs * n * sizeof(cplx<T>), st);
+      sap(level, in, out, nrhs, mu, p.sap_sweeps[level]);
+      break;
+    }
+    case TMAMG_OP_PREC:
+      need(level == 0 || (level == 1 && nlev >= 3));
+      precond(level, in, out, nrhs, mu);
+      break;
+    default:
+      throw TmError{TMAMG_EINVAL, "unknown operator"};
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::export_P(int level, cplx<double>* out) {
+  hipStream_t st = c->st;
+  if (level == 0) {
+    if (nlev < 2) throw TmError{TMAMG_EINVAL, "no coarsening"};
+    long n0 = 12 * c->fg.V;
+    DevArr<cplx<double>> tmp;
+    tmp.alloc((size_t)nv0 * n0);
+    launch_store_to64<S>(P0.p, tmp.p, (long)nv0 * n0, st);
+    launch_spinor_to_canonical<double>(c->fg, tmp.p, out, nv0, st);
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    if (nlev < 3) throw TmError{TMAMG_EINVAL, "no second coarsening"};
+    launch_store_to64<S>(P1.p, out, (long)nv1 * g1.V * d1, st);
+  }
+}
+template <typename T, typename S>
+void Hier<T, S>::export_Dc(int level, cplx<double>* out) {
+  if (level == 1 && nlev >= 2) launch_store_to64<S>(Dc1.p, out, (long)g1.V * 9 * d1 * d1, c->st);
+  else if (level == 2 && nlev >= 3) launch_store_to64<S>(Dc2.p, out, (long)g2.V * 9 * d2 * d2, c->st);
+  else throw TmError{TMAMG_EINVAL, "no such coarse level"};
+}
+
+template struct Hier<double, double>;
+template struct Hier<float, float>;
+template struct Hier<float, __hip_bfloat16>;
+template struct Hier<float, __half>;
+
+// ------------------------------------------------------------------ context
+static void check(bool ok, const std::string& msg) {
+  if (!ok) throw TmError{TMAMG_EINVAL, msg};
+}
+
+static bool even_or_one(int n) { return n == 1 || n % 2 == 0; }
+
+Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s) : lat(l), par(p), st(s) {
+  check(p.nlevels >= 0 && p.nlevels <= 3, "nlevels must be 0..3");
+  check(p.restart >= 1 && p.restart <= 127, "restart must be 1..127");
+  check(p.max_iter >= 1, "max_iter must be positive");
+  check(p.mr_steps >= 0 && p.sap_sweeps[0] >= 0 && p.sap_sweeps[1] >= 0, "negative smoother counts");
+  check(p.precision == TMAMG_FP64 || p.precision == TMAMG_MIXED, "precision");
+  if (p.precision == TMAMG_MIXED)
+    check(p.storage == TMAMG_STORE_FP32 || p.storage == TMAMG_STORE_BF16 || p.storage == TMAMG_STORE_FP16,
+          "mixed precision stores P and D_c in fp32, bf16 or fp16");
+  int bvol = 1;
+  for (int m = 0; m < 4; ++m) {
+    check(l.dims[m] >= 1 && p.agg[0][m] >= 1, "dims and aggregates must be positive");
+    check(l.dims[m] % p.agg[0][m] == 0, "lattice extents must be multiples of the first aggregate");
+    bvol *= p.agg[0][m];
+  }
+  check(bvol % 64 == 0 && bvol <= 256, "the fine aggregate/SAP block must hold 64, 128, 192 or 256 sites");
+  fg.V = 1;
+  for (int m = 0; m < 4; ++m) {
+    fg.L[m] = l.dims[m];
+    fg.B[m] = p.agg[0][m];
+    fg.NB[m] = l.dims[m] / p.agg[0][m];
+    fg.V *= l.dims[m];
+    check(even_or_one(fg.NB[m]), "SAP needs an even number of fine blocks (or one) per dimension");
+  }
+  fg.bvol = bvol;
+  fg.nblocks = (int)(fg.V / bvol);
+  fg.lstride[0] = 1;
+  fg.bstride[0] = 1;
+  for (int m = 1; m < 4; ++m) {
+    fg.lstride[m] = fg.lstride[m - 1] * fg.B[m - 1];
+    fg.bstride[m] = fg.bstride[m - 1] * fg.NB[m - 1];
+  }
+  if (p.nlevels >= 2) {
+    check(p.nv[0] >= 1 && p.nv[0] <= 64, "nv[0] must be 1..64");
+    check(p.coarsest_iters >= 1 && p.coarsest_iters <= 127, "coarsest_iters must be 1..127");
+  }
+  if (p.nlevels >= 3) {
+    check(p.nv[1] >= 1 && p.nv[1] <= 64, "nv[1] must be 1..64");
+    check(p.l2_iters >= 1 && p.l2_iters <= 127, "l2_iters must be 1..127");
+    int na = 1, nbs = 1;
+    for (int m = 0; m < 4; ++m) {
+      int L1 = fg.NB[m];
+      check(p.agg[1][m] >= 1 && L1 % p.agg[1][m] == 0, "coarse extents must be multiples of the second aggregate");
+      check(p.sap_block1[m] >= 1 && L1 % p.sap_block1[m] == 0, "coarse SAP block must tile the coarse lattice");
+      check(even_or_one(L1 / p.sap_block1[m]), "coarse SAP needs an even number of blocks (or one) per dimension");
+      na *= p.agg[1][m];
+      nbs *= p.sap_block1[m];
+    }
+    // LDS budgets of the coarse Gram-Schmidt / Galerkin and coarse SAP kernels (64 KB per workgroup)
+    check(na * p.nv[0] <= 768, "second aggregate too large (sites * nv[0] <= 768)");
+    check(nbs * 2 * p.nv[0] <= 4000, "coarse SAP block too large (sites * dof <= 4000)");
+  }
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&host_flags), 1024 * sizeof(int), hipHostMallocDefault));
+}
+
+Ctx::~Ctx() {
+  if (host_flags) (void)hipHostFree(host_flags);
+}
+
+__global__ void k_unitarity(const cplx<double>* U, long V, double* out) {
+  __shared__ double red[4];
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int mu = blockIdx.y;
+  double dev = 0;
+  if (s < V) {
+    cplx<double> u[3][3];
+    for (int k = 0; k < 9; ++k) u[k / 3][k % 3] = U[((long)mu * 9 + k) * V + s];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cplx<double> a = mk(0.0, 0.0);
+        for (int k = 0; k < 3; ++k) cfma(a, u[i][k], conj(u[j][k]));
+        if (i == j) a.re -= 1.0;
+        dev = fmax(dev, sqrt(norm2(a)));
+      }
+    if (!(dev == dev)) dev = 1e300;
+  }
+  for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.y * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Chiral blocks of sigma_{mu nu} = (i/2)[g_mu, g_nu] for the planes mu < nu
+// (order (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)); g_k = [[0, -i s_k], [i s_k, 0]],
+// g_4 = [[0, 1], [1, 0]].  sigma commutes with g5, so only the two 2x2
+// diagonal blocks (spins 0,1 and 2,3) are non-zero.
+void sigma_blocks(double re[6][2][2][2], double im[6][2][2][2]) {
+  using Cx = std::complex<double>;
+  Cx g[4][4][4] = {};
+  const Cx I(0, 1);
+  Cx sig[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        g[k][a][2 + b] = -I * sig[k][a][b];
+        g[k][2 + a][b] = I * sig[k][a][b];
+      }
+  for (int a = 0; a < 2; ++a) { g[3][a][2 + a] = 1; g[3][2 + a][a] = 1; }
+  int pl = 0;
+  for (int m = 0; m < 4; ++m)
+    for (int n = m + 1; n < 4; ++n, ++pl) {
+      Cx s4[4][4];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          Cx acc = 0;
+          for (int k = 0; k < 4; ++k) acc += g[m][i][k] * g[n][k][j] - g[n][i][k] * g[m][k][j];
+          s4[i][j] = 0.5 * I * acc;
+        }
+      for (int ch = 0; ch < 2; ++ch)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            re[pl][ch][a][b] = s4[2 * ch + a][2 * ch + b].real();
+            im[pl][ch][a][b] = s4[2 * ch + a][2 * ch + b].imag();
+          }
+    }
+}
+
+void Ctx::load_links(const cplx<double>* U) {
+  check(U != nullptr, "null link pointer");
+  links64.alloc((size_t)4 * 9 * fg.V);
+  bool mixed = par.precision == TMAMG_MIXED;
+  if (mixed) links32.alloc((size_t)4 * 9 * fg.V);
+  launch_convert_links(fg, U, links64.p, mixed ? links32.p : nullptr, lat.t_antiperiodic, st);
+  // unitarity check
+  unsigned nb = (unsigned)((fg.V + 255) / 256);
+  DevArr<double> dv;
+  dv.alloc((size_t)nb * 4);
+  hipLaunchKernelGGL(k_unitarity, dim3(nb, 4), dim3(256), 0, st, links64.p, fg.V, dv.p);
+  std::vector<double> h(nb * 4);
+  HIPCHK(hipMemcpyAsync(h.data(), dv.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double mx = 0;
+  for (double v : h) mx = std::max(mx, v);
+  if (!(mx <= 1e-6)) throw TmError{TMAMG_ENUMERIC, "links are not unitary (max |U U^dag - 1| = " + std::to_string(mx) + ")"};
+  // clover: A_s = (m0+4) + sum_{mu<nu} [c_sw (i/2) sigma_{mu nu}]_s Fhat_{mu nu}
+  CloverCoef cc{};
+  cc.diag = m0 + 4.0;
+  double sre[6][2][2][2], sim[6][2][2][2];
+  sigma_blocks(sre, sim);
+  for (int pl = 0; pl < 6; ++pl)
+    for (int ch = 0; ch < 2; ++ch)
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          // c_sw (i/2) (re + i im)
+          cc.re[pl][ch][a][b] = -0.5 * csw * sim[pl][ch][a][b];
+          cc.im[pl][ch][a][b] = 0.5 * csw * sre[pl][ch][a][b];
+        }
+  clov64.alloc((size_t)72 * fg.V);
+  if (mixed) clov32.alloc((size_t)72 * fg.V);
+  launch_clover_build(fg, links64.p, cc, clov64.p, mixed ? clov32.p : nullptr, st);
+  have_links = true;
+}
+
+void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
+  check(kappa_ > 0 && std::isfinite(kappa_), "kappa must be positive");
+  check(std::isfinite(csw_) && std::isfinite(mu_), "csw and mu must be finite");
+  auto t0 = clk::now();
+  kappa = kappa_;
+  csw = csw_;
+  mu = mu_;
+  m0 = 1.0 / (2.0 * kappa) - 4.0;
+  load_links(U);
+  if (par.precision == TMAMG_FP64) hier.reset(new Hier<double, double>(this));
+  else if (par.storage == TMAMG_STORE_FP32) hier.reset(new Hier<float, float>(this));
+  else if (par.storage == TMAMG_STORE_BF16) hier.reset(new Hier<float, __hip_bfloat16>(this));
+  else hier.reset(new Hier<float, __half>(this));
+  hier->setup(mu);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  have_setup = true;
+  t_setup = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+void Ctx::setup_update(const cplx<double>* U, int iters) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "setup_update before setup"};
+  check(iters >= 0, "iters must be >= 0");
+  auto t0 = clk::now();
+  load_links(U);
+  hier->rebuild();
+  for (int i = 0; i < iters; ++i) hier->setup_iteration();
+  HIPCHK(hipStreamSynchronize(st));
+  t_setup = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+void Ctx::ensure(int nrhs) {
+  if (nrhs <= cap) return;
+  cap = nrhs;
+  const long n = 12 * fg.V;
+  b64.alloc((size_t)cap * n);
+  x64.alloc((size_t)cap * n);
+  r64.alloc((size_t)cap * n);
+  t64.alloc((size_t)cap * n);
+  mu_dev.alloc(cap);
+  abstol_dev.alloc(cap);
+  red_partial.alloc(1024 * (size_t)cap);
+  red_out.alloc(cap);
+  bool flex = par.nlevels >= 1;
+  if (par.precision == TMAMG_FP64) {
+    K64.ensure(n, par.restart, cap, flex, st);
+  } else {
+    r32.alloc((size_t)cap * n);
+    e32.alloc((size_t)cap * n);
+    K32.ensure(n, par.restart, cap, flex, st);
+  }
+  if (hier) hier->ensure(cap);
+}
+
+std::vector<double> Ctx::norms(const cplx<double>* v, int nrhs) {
+  const long n = 12 * fg.V;
+  int NB = reduce_blocks(n);
+  launch_norm2(v, n, nrhs, red_partial.p, NB, nullptr, st);
+  launch_finalize_real(red_partial.p, nrhs, NB, red_out.p, st);
+  std::vector<double> h(nrhs);
+  HIPCHK(hipMemcpyAsync(h.data(), red_out.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (double& x : h) x = std::sqrt(x);
+  return h;
+}
+
+void Ctx::upload_mu(int nrhs, const double* mu_host) {
+  std::vector<double> m(nrhs, mu);
+  if (mu_host)
+    for (int r = 0; r < nrhs; ++r) {
+      check(std::isfinite(mu_host[r]), "non-finite twisted mass");
+      m[r] = mu_host[r];
+    }
+  HIPCHK(hipMemcpyAsync(mu_dev.p, m.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+}
+
+// b64 holds the right-hand sides (internal layout); x64 receives the solutions.
+// Outer loop: FP64 true residual r = b - D x at every restart (reliable update).
+// FP64 mode: FGMRES(m) cycles on r with the FP64 cycle.  Mixed mode: the
+// cycle's Krylov space, operator and multigrid run in FP32 (P, D_c in the
+// storage type) on r rounded to FP32, stopped at inner_tol * ||r|| (defect
+// correction); the correction is added to x in FP64.
+tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info) {
+  const long n = 12 * fg.V;
+  upload_mu(nrhs, mu_host);
+  launch_fill_zero(x64.p, (size_t)nrhs * n * sizeof(cplx<double>), st);
+  HIPCHK(hipMemcpyAsync(r64.p, b64.p, (size_t)nrhs * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  std::vector<double> bn = norms(b64.p, nrhs);
+  for (double v : bn)
+    if (!std::isfinite(v)) throw TmError{TMAMG_ENUMERIC, "right-hand side holds NaN/Inf"};
+  const bool mixed = par.precision == TMAMG_MIXED;
+  FineOp<double> o64 = op64();
+  FineOp<float> o32 = mixed ? op32() : FineOp<float>{};
+  const double* mu_d = mu_dev.p;
+  OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) { launch_dslash<double>(o64, in, out, nrhs, mu_d, st); };
+  OpFn<float> A32 = [&](const cplx<float>* in, cplx<float>* out) { launch_dslash<float>(o32, in, out, nrhs, mu_d, st); };
+  OpFn<double> M64 = [&](const cplx<double>* in, cplx<double>* out) { hier->precond_d(in, out, nrhs, mu_d); };
+  OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, nrhs, mu_d); };
+  const bool use_m = par.nlevels >= 1;
+  int iters = 0, cycles = 0;
+  tmamg_status status = TMAMG_NOT_CONVERGED;
+  double worst = 0;
+  std::vector<double> at(nrhs);
+  while (true) {
+    std::vector<double> rn = norms(r64.p, nrhs);
+    worst = 0;
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rn[r])) throw TmError{TMAMG_ENUMERIC, "residual became NaN/Inf"};
+      double rel = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
+      worst = std::max(worst, rel);
+      all &= rel <= tol;
+    }
+    if (all) { status = TMAMG_OK; break; }
+    if (iters >= par.max_iter) break;
+    int it;
+    if (!mixed) {
+      for (int r = 0; r < nrhs; ++r) at[r] = 0.9 * tol * bn[r];
+      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      it = krylov_cycle<double>(K64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nrhs,
+                                std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
+    } else {
+      for (int r = 0; r < nrhs; ++r) at[r] = std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]);
+      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_convert<double, float>(r64.p, r32.p, (long)nrhs * n, st);
+      launch_fill_zero(e32.p, (size_t)nrhs * n * sizeof(cplx<float>), st);
+      it = krylov_cycle<float>(K32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, nrhs,
+                               std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
+      launch_add_to64<float>(e32.p, x64.p, (long)nrhs * n, st);
+    }
+    iters += it;
+    cycles += 1;
+    // reliable update: r = b - D x in FP64
+    launch_dslash<double>(o64, x64.p, t64.p, nrhs, mu_d, st);
+    launch_xmy<double>(b64.p, t64.p, (long)nrhs * n, st);
+    std::swap(r64.p, t64.p);
+    if (it == 0 && cycles > 3) break;   // no progress possible
+  }
+  HIPCHK(hipGetLastError());
+  if (info) {
+    info->status = status;
+    info->outer_iters += iters;
+    info->cycles += cycles;
+    info->true_rel_resid = std::max(info->true_rel_resid, worst);
+  }
+  return status;
+}
+
+tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
+                        tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
+  check(b && x && nrhs >= 1, "bad solve arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  auto t0 = clk::now();
+  ensure(nrhs);
+  tmamg_info loc{};
+  launch_spinor_to_internal<double>(fg, b, b64.p, nrhs, st);
+  tmamg_status s = solve_core(nrhs, mu_host, tol, &loc);
+  launch_spinor_to_canonical<double>(fg, x64.p, x, nrhs, st);
+  HIPCHK(hipStreamSynchronize(st));
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
+tmamg_status Ctx::solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,
+                                tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
+  check(b && x && sigma && nrhs >= 1, "bad solve arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  auto t0 = clk::now();
+  ensure(nrhs);
+  std::vector<double> mup(nrhs), mum(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    check(std::isfinite(sigma[r]) && sigma[r] >= 0, "sigma must be finite and >= 0");
+    mup[r] = std::sqrt(mu * mu + sigma[r]);
+    mum[r] = -mup[r];
+  }
+  tmamg_info loc{};
+  launch_spinor_to_internal<double>(fg, b, b64.p, nrhs, st);
+  tmamg_status s1 = solve_core(nrhs, mup.data(), tol, &loc);
+  // x = Gamma5 D(-mu')^-1 Gamma5 w
+  launch_gamma5_fine<double>(fg, x64.p, b64.p, nrhs, st);
+  tmamg_status s2 = solve_core(nrhs, mum.data(), tol, &loc);
+  launch_gamma5_fine<double>(fg, x64.p, t64.p, nrhs, st);
+  launch_spinor_to_canonical<double>(fg, t64.p, x, nrhs, st);
+  HIPCHK(hipStreamSynchronize(st));
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
+  tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
+tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "force before setup"};
+  check(phi && F && S, "bad force arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  auto t0 = clk::now();
+  ensure(1);
+  tmamg_info loc{};
+  const long n = 12 * fg.V;
+  // Y = D(mu)^-1 phi
+  launch_spinor_to_internal<double>(fg, phi, b64.p, 1, st);
+  DevArr<cplx<double>> phi64, Y, X;
+  phi64.alloc(n);
+  Y.alloc(n);
+  X.alloc(n);
+  HIPCHK(hipMemcpyAsync(phi64.p, b64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  double mp = mu, mm = -mu;
+  tmamg_status s1 = solve_core(1, &mp, tol, &loc);
+  HIPCHK(hipMemcpyAsync(Y.p, x64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  // X = Gamma5 D(-mu)^-1 Gamma5 Y
+  launch_gamma5_fine<double>(fg, Y.p, b64.p, 1, st);
+  tmamg_status s2 = solve_core(1, &mm, tol, &loc);
+  launch_gamma5_fine<double>(fg, x64.p, X.p, 1, st);
+  // S = Re <phi, X>
+  int NB = reduce_blocks(n);
+  launch_multidot<double>(phi64.p, n, 1, X.p, n, 1, red_partial.p, NB, nullptr, st);
+  launch_finalize(red_partial.p, 1, 1, NB, red_out.p, 1, st);
+  double sv[2];
+  HIPCHK(hipMemcpyAsync(sv, red_out.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  launch_force(op64(), csw, X.p, Y.p, F, st);
+  HIPCHK(hipStreamSynchronize(st));
+  *S = sv[0];
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
+  tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
+void Ctx::force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F) {
+  if (!have_links) throw TmError{TMAMG_ESTATE, "force before setup"};
+  check(X && Y && F, "null pointer");
+  const long n = 12 * fg.V;
+  DevArr<cplx<double>> Xi, Yi;
+  Xi.alloc(n);
+  Yi.alloc(n);
+  launch_spinor_to_internal<double>(fg, X, Xi.p, 1, st);
+  launch_spinor_to_internal<double>(fg, Y, Yi.p, 1, st);
+  launch_force(op64(), csw, Xi.p, Yi.p, F, st);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host) {
+  check(in && out && nrhs >= 1, "bad apply arguments");
+  if (!have_links) throw TmError{TMAMG_ESTATE, "apply before setup"};
+  ensure(nrhs);
+  upload_mu(nrhs, mu_host);
+  const long n0 = 12 * fg.V;
+  if (op == TMAMG_OP_D64 || op == TMAMG_OP_D32) {
+    check(level == 0, "D acts on level 0");
+    launch_spinor_to_internal<double>(fg, in, b64.p, nrhs, st);
+    if (op == TMAMG_OP_D64) {
+      launch_dslash<double>(op64(), b64.p, t64.p, nrhs, mu_dev.p, st);
+    } else {
+      if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
+      DevArr<cplx<float>> a, b;
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * n0);
+      launch_convert<double, float>(b64.p, a.p, (long)nrhs * n0, st);
+      launch_dslash<float>(op32(), a.p, b.p, nrhs, mu_dev.p, st);
+      launch_convert<float, double>(b.p, t64.p, (long)nrhs * n0, st);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    launch_spinor_to_canonical<double>(fg, t64.p, out, nrhs, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "hierarchy not set up"};
+  long sites_in, sites_out;
+  int dof_in, dof_out;
+  int lin = level, lout = level;
+  if (op == TMAMG_OP_PROLONG) lout = level - 1;
+  if (op == TMAMG_OP_RESTRICT) lout = level + 1;
+  check(lin >= 0 && lin <= 2 && lout >= 0 && lout <= 2, "bad level");
+  tmamg_level_info(reinterpret_cast<const tmamg_ctx*>(this), lin, &sites_in, &dof_in);
+  tmamg_level_info(reinterpret_cast<const tmamg_ctx*>(this), lout, &sites_out, &dof_out);
+  check(sites_in > 0 && sites_out > 0, "level not present");
+  const long nin = sites_in * dof_in * nrhs, nout = sites_out * dof_out * nrhs;
+  DevArr<cplx<double>> i64, o64;
+  i64.alloc(nin);
+  o64.alloc(nout);
+  if (lin == 0) launch_spinor_to_internal<double>(fg, in, i64.p, nrhs, st);
+  else HIPCHK(hipMemcpyAsync(i64.p, in, nin * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  if (hier->is_double()) {
+    hier->test_op(op, level, i64.p, o64.p, nrhs, mu_dev.p);
+  } else {
+    DevArr<cplx<float>> i32, o32;
+    i32.alloc(nin);
+    o32.alloc(nout);
+    launch_convert<double, float>(i64.p, i32.p, nin, st);
+    hier->test_op(op, level, i32.p, o32.p, nrhs, mu_dev.p);
+    launch_convert<float, double>(o32.p, o64.p, nout, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (lout == 0) launch_spinor_to_canonical<double>(fg, o64.p, out, nrhs, st);
+  else HIPCHK(hipMemcpyAsync(out, o64.p, nout * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------ C ABI
+template <typename F>
+static tmamg_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const TmError& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return TMAMG_EINVAL;
+  }
+}
+
+static Ctx* C(tmamg_ctx* c) { return reinterpret_cast<Ctx*>(c); }
+static const Ctx* C(const tmamg_ctx* c) { return reinterpret_cast<const Ctx*>(c); }
+
+extern "C" {
+
+tmamg_status tmamg_default_params(tmamg_params* p) {
+  if (!p) { g_last_error = "null params"; return TMAMG_EINVAL; }
+  std::memset(p, 0, sizeof(*p));
+  p->nlevels = 2;
+  for (int m = 0; m < 4; ++m) { p->agg[0][m] = 4; p->agg[1][m] = 2; p->sap_block1[m] = 2; }
+  p->nv[0] = 12;
+  p->nv[1] = 32;
+  p->setup_iters = 3;
+  p->init_smooth = 2;
+  p->sap_sweeps[0] = 4;
+  p->sap_sweeps[1] = 2;
+  p->mr_steps = 4;
+  p->l2_iters = 10;
+  p->l2_tol = 0.1;
+  p->coarsest_iters = 100;
+  p->coarsest_tol = 0.1;
+  p->restart = 30;
+  p->max_iter = 2000;
+  p->precision = TMAMG_FP64;
+  p->storage = TMAMG_STORE_BF16;
+  p->inner_tol = 1e-3;
+  p->seed = 4001;
+  return TMAMG_OK;
+}
+
+tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream) {
+  return guarded([&]() {
+    check(ctx && lat && par, "null argument");
+    *ctx = nullptr;
+    Ctx* c = new Ctx(*lat, *par, reinterpret_cast<hipStream_t>(hip_stream));
+    *ctx = reinterpret_cast<tmamg_ctx*>(c);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_setup(tmamg_ctx* ctx, const void* U, double kappa, double csw, double mu) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->setup(static_cast<const cplx<double>*>(U), kappa, csw, mu);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_setup_update(tmamg_ctx* ctx, const void* U, int iters) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->setup_update(static_cast<const cplx<double>*>(U), iters);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_solve(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                         tmamg_info* info) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    return C(ctx)->solve(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, mu_rhs, tol,
+                         info);
+  });
+}
+
+tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
+                                 tmamg_info* info) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    return C(ctx)->solve_shifted(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, sigma,
+                                 tol, info);
+  });
+}
+
+tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    return C(ctx)->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info);
+  });
+}
+
+tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->force_from_fields(static_cast<const cplx<double>*>(X), static_cast<const cplx<double>*>(Y),
+                              static_cast<cplx<double>*>(F));
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
+                         const double* mu_rhs) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->apply(op, level, static_cast<const cplx<double>*>(in), static_cast<cplx<double>*>(out), nrhs, mu_rhs);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void* v) {
+  return guarded([&]() {
+    check(ctx != nullptr && v != nullptr, "null argument");
+    Ctx* c = C(ctx);
+    check(level == 0 || level == 1, "test vectors live on level 0 or 1");
+    check(c->par.nlevels >= level + 2, "no such coarsening");
+    if (level == 0) {
+      long n = 12 * c->fg.V;
+      c->inject0.alloc((size_t)c->par.nv[0] * n);
+      launch_spinor_to_internal<double>(c->fg, static_cast<const cplx<double>*>(v), c->inject0.p, c->par.nv[0], c->st);
+    } else {
+      long n = (long)c->fg.nblocks * 2 * c->par.nv[0];
+      c->inject1.alloc((size_t)c->par.nv[1] * n);
+      HIPCHK(hipMemcpyAsync(c->inject1.p, v, c->par.nv[1] * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_debug_export(tmamg_ctx* ctx, int what, int level, void* out) {
+  return guarded([&]() {
+    check(ctx != nullptr && out != nullptr, "null argument");
+    Ctx* c = C(ctx);
+    if (!c->have_setup) throw TmError{TMAMG_ESTATE, "export before setup"};
+    if (what == 0) c->hier->export_P(level, static_cast<cplx<double>*>(out));
+    else if (what == 1) c->hier->export_Dc(level, static_cast<cplx<double>*>(out));
+    else throw TmError{TMAMG_EINVAL, "what must be 0 (P) or 1 (D_c)"};
+    HIPCHK(hipStreamSynchronize(c->st));
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int* dof) {
+  return guarded([&]() {
+    check(ctx && sites && dof, "null argument");
+    const Ctx* c = C(ctx);
+    *sites = 0;
+    *dof = 0;
+    if (level == 0) { *sites = c->fg.V; *dof = 12; }
+    else if (level == 1 && c->par.nlevels >= 2) { *sites = c->fg.nblocks; *dof = 2 * c->par.nv[0]; }
+    else if (level == 2 && c->par.nlevels >= 3) {
+      long s = 1;
+      for (int m = 0; m < 4; ++m) s *= c->fg.NB[m] / c->par.agg[1][m];
+      *sites = s;
+      *dof = 2 * c->par.nv[1];
+    } else throw TmError{TMAMG_EINVAL, "no such level"};
+    return TMAMG_OK;
+  });
+}
+
+void tmamg_destroy(tmamg_ctx* ctx) {
+  try {
+    delete C(ctx);
+  } catch (...) {
+  }
+}
+
+const char* tmamg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

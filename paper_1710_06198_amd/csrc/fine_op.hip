@@ -1,0 +1,383 @@
+// Fine-level kernels: layout conversion, clover build, the twisted-mass
+// clover Wilson stencil and the SAP block solver.
+//
+// D(mu) psi(x) = A(x) psi(x) + i mu g5 psi(x)
+//   - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)]
+// (twisted-mass term of Sec. 1.1 on the clover-improved Wilson operator).
+#include "kernels.h"
+#include "su3.h"
+
+// ------------------------------------------------------------------ conversion
+__global__ void k_convert_links(FineGeom g, const cplx<double>* __restrict__ canon, cplx<double>* out64,
+                                cplx<float>* out32, int antiperiodic) {
+  long cs = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (cs >= g.V) return;
+  int mu = blockIdx.y;
+  int c[4];
+  long r = cs;
+  c[0] = (int)(r % g.L[0]); r /= g.L[0];
+  c[1] = (int)(r % g.L[1]); r /= g.L[1];
+  c[2] = (int)(r % g.L[2]);
+  c[3] = (int)(r / g.L[2]);
+  long s = fine_index(g, c);
+  double sign = (antiperiodic && mu == 3 && c[3] == g.L[3] - 1) ? -1.0 : 1.0;
+  const cplx<double>* src = canon + ((long)mu * g.V + cs) * 9;
+  for (int k = 0; k < 9; ++k) {
+    cplx<double> v = sign * src[k];
+    long o = ((long)mu * 9 + k) * g.V + s;
+    if (out64) out64[o] = v;
+    if (out32) out32[o] = mk<float>((float)v.re, (float)v.im);
+  }
+}
+
+void launch_convert_links(const FineGeom& g, const cplx<double>* canon, cplx<double>* out64, cplx<float>* out32,
+                          int antiperiodic, hipStream_t st) {
+  dim3 grid((unsigned)((g.V + 255) / 256), 4);
+  hipLaunchKernelGGL(k_convert_links, grid, dim3(256), 0, st, g, canon, out64, out32, antiperiodic);
+}
+
+template <typename T>
+__global__ void k_spinor_to_internal(FineGeom g, const cplx<double>* __restrict__ canon, cplx<T>* __restrict__ out) {
+  long cs = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (cs >= g.V) return;
+  long rhs = blockIdx.y;
+  int c[4];
+  long r = cs;
+  c[0] = (int)(r % g.L[0]); r /= g.L[0];
+  c[1] = (int)(r % g.L[1]); r /= g.L[1];
+  c[2] = (int)(r % g.L[2]);
+  c[3] = (int)(r / g.L[2]);
+  long s = fine_index(g, c);
+  const cplx<double>* src = canon + (rhs * g.V + cs) * 12;
+  cplx<T>* dst = out + rhs * 12 * g.V + s;
+  for (int k = 0; k < 12; ++k) dst[(long)k * g.V] = mk<T>((T)src[k].re, (T)src[k].im);
+}
+
+template <typename T>
+__global__ void k_spinor_to_canonical(FineGeom g, const cplx<T>* __restrict__ in, cplx<double>* __restrict__ canon) {
+  long cs = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (cs >= g.V) return;
+  long rhs = blockIdx.y;
+  int c[4];
+  long r = cs;
+  c[0] = (int)(r % g.L[0]); r /= g.L[0];
+  c[1] = (int)(r % g.L[1]); r /= g.L[1];
+  c[2] = (int)(r % g.L[2]);
+  c[3] = (int)(r / g.L[2]);
+  long s = fine_index(g, c);
+  const cplx<T>* src = in + rhs * 12 * g.V + s;
+  cplx<double>* dst = canon + (rhs * g.V + cs) * 12;
+  for (int k = 0; k < 12; ++k) {
+    cplx<T> v = src[(long)k * g.V];
+    dst[k] = mk<double>((double)v.re, (double)v.im);
+  }
+}
+
+template <typename T>
+void launch_spinor_to_internal(const FineGeom& g, const cplx<double>* canon, cplx<T>* out, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
+  hipLaunchKernelGGL(k_spinor_to_internal<T>, grid, dim3(256), 0, st, g, canon, out);
+}
+template <typename T>
+void launch_spinor_to_canonical(const FineGeom& g, const cplx<T>* in, cplx<double>* canon, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
+  hipLaunchKernelGGL(k_spinor_to_canonical<T>, grid, dim3(256), 0, st, g, in, canon);
+}
+template void launch_spinor_to_internal<double>(const FineGeom&, const cplx<double>*, cplx<double>*, int, hipStream_t);
+template void launch_spinor_to_internal<float>(const FineGeom&, const cplx<double>*, cplx<float>*, int, hipStream_t);
+template void launch_spinor_to_canonical<double>(const FineGeom&, const cplx<double>*, cplx<double>*, int, hipStream_t);
+template void launch_spinor_to_canonical<float>(const FineGeom&, const cplx<float>*, cplx<double>*, int, hipStream_t);
+
+// ------------------------------------------------------------------ clover (K2)
+__device__ long shifted_site(const FineGeom& g, const int c[4], int m1, int s1, int m2, int s2) {
+  int cc[4] = {c[0], c[1], c[2], c[3]};
+  if (s1) cc[m1] = (cc[m1] + s1 + g.L[m1]) % g.L[m1];
+  if (s2) cc[m2] = (cc[m2] + s2 + g.L[m2]) % g.L[m2];
+  return fine_index(g, cc);
+}
+
+// Q_{mu nu}(x) = sum of the four same-orientation plaquette leaves at x;
+// Fhat = (Q - Q^dag)/8 with its trace removed; A_s = (m0+4) + sum_{mu<nu}
+// [c_sw (i/2) sigma_{mu nu}]_s (x) Fhat_{mu nu}.
+__global__ void k_clover_build(FineGeom g, const cplx<double>* __restrict__ U, CloverCoef cc, double* clov64,
+                               float* clov32) {
+  long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  fine_coords(g, s, c);
+  cplx<double> A[2][6][6];
+  for (int ch = 0; ch < 2; ++ch)
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) A[ch][i][j] = mk(i == j ? cc.diag : 0.0, 0.0);
+  int p = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = mu + 1; nu < 4; ++nu, ++p) {
+      long x = s;
+      long xpm = shifted_site(g, c, mu, 1, nu, 0);
+      long xpn = shifted_site(g, c, nu, 1, mu, 0);
+      long xmm = shifted_site(g, c, mu, -1, nu, 0);
+      long xmn = shifted_site(g, c, nu, -1, mu, 0);
+      long xmmpn = shifted_site(g, c, mu, -1, nu, 1);
+      long xpmmn = shifted_site(g, c, mu, 1, nu, -1);
+      long xmmmn = shifted_site(g, c, mu, -1, nu, -1);
+      M3<double> Um_x = load_link(U, mu, x, g.V), Un_x = load_link(U, nu, x, g.V);
+      M3<double> Un_xpm = load_link(U, nu, xpm, g.V), Um_xpn = load_link(U, mu, xpn, g.V);
+      M3<double> Um_xmm = load_link(U, mu, xmm, g.V), Un_xmm = load_link(U, nu, xmm, g.V);
+      M3<double> Um_xmmpn = load_link(U, mu, xmmpn, g.V);
+      M3<double> Um_xmmmn = load_link(U, mu, xmmmn, g.V), Un_xmmmn = load_link(U, nu, xmmmn, g.V);
+      M3<double> Un_xmn = load_link(U, nu, xmn, g.V), Um_xmn = load_link(U, mu, xmn, g.V);
+      M3<double> Un_xpmmn = load_link(U, nu, xpmmn, g.V);
+      // l1 = Um(x) Un(x+mu) Um(x+nu)^dag Un(x)^dag
+      M3<double> l1 = m3_mul_ad(m3_mul_ad(m3_mul(Um_x, Un_xpm), Um_xpn), Un_x);
+      // l2 = Un(x) Um(x-mu+nu)^dag Un(x-mu)^dag Um(x-mu)
+      M3<double> l2 = m3_mul(m3_mul_ad(m3_mul_ad(Un_x, Um_xmmpn), Un_xmm), Um_xmm);
+      // l3 = Um(x-mu)^dag Un(x-mu-nu)^dag Um(x-mu-nu) Un(x-nu)
+      M3<double> l3 = m3_mul(m3_mul(m3_mul_da(Um_xmm, m3_dag(Un_xmmmn)), Um_xmmmn), Un_xmn);
+      // l4 = Un(x-nu)^dag Um(x-nu) Un(x+mu-nu) Um(x)^dag
+      M3<double> l4 = m3_mul_ad(m3_mul(m3_mul_da(Un_xmn, Um_xmn), Un_xpmmn), Um_x);
+      M3<double> q = m3_add(m3_add(l1, l2), m3_add(l3, l4));
+      cplx<double> F[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) F[i][j] = 0.125 * (q.e[i][j] - conj(q.e[j][i]));
+      cplx<double> tr = (1.0 / 3.0) * (F[0][0] + F[1][1] + F[2][2]);
+      for (int i = 0; i < 3; ++i) F[i][i] -= tr;
+      for (int ch = 0; ch < 2; ++ch)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            cplx<double> sg = mk(cc.re[p][ch][a][b], cc.im[p][ch][a][b]);
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) A[ch][a * 3 + i][b * 3 + j] += sg * F[i][j];
+          }
+    }
+  for (int ch = 0; ch < 2; ++ch) {
+    long base = (long)ch * 36;
+    for (int i = 0; i < 6; ++i) {
+      double v = A[ch][i][i].re;
+      if (clov64) clov64[(base + i) * g.V + s] = v;
+      if (clov32) clov32[(base + i) * g.V + s] = (float)v;
+    }
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        long k = base + 6 + 2 * herm_idx(i, j);
+        cplx<double> v = A[ch][i][j];
+        if (clov64) { clov64[k * g.V + s] = v.re; clov64[(k + 1) * g.V + s] = v.im; }
+        if (clov32) { clov32[k * g.V + s] = (float)v.re; clov32[(k + 1) * g.V + s] = (float)v.im; }
+      }
+  }
+}
+
+void launch_clover_build(const FineGeom& g, const cplx<double>* links64, const CloverCoef& cc, double* clov64,
+                         float* clov32, hipStream_t st) {
+  hipLaunchKernelGGL(k_clover_build, dim3((unsigned)((g.V + 127) / 128)), dim3(128), 0, st, g, links64, cc, clov64,
+                     clov32);
+}
+
+// ------------------------------------------------------------------ stencil (K1)
+template <typename T>
+TM_D void load_spinor(const cplx<T>* __restrict__ f, long s, long V, cplx<T>* p) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = f[(long)k * V + s];
+}
+
+// acc = (A + i mu g5) psi
+template <typename T>
+TM_D void site_diag(const FineOp<T>& op, long s, T mu, const cplx<T>* psi, cplx<T>* acc) {
+  const long V = op.g.V;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
+  clover_block_mv(op.clover + s, V, psi, acc);
+  clover_block_mv(op.clover + 36 * V + s, V, psi + 6, acc + 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    acc[k] += mu * times_i(psi[k]);
+    acc[6 + k] -= mu * times_i(psi[6 + k]);
+  }
+}
+
+template <int MU, typename T>
+TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, long s, const int c[4], cplx<T>* acc) {
+  const long V = op.g.V;
+  cplx<T> pn[12];
+  long sf = fine_neighbour(op.g, s, c, MU, +1);
+  load_spinor(in, sf, V, pn);
+  M3<T> u = load_link(op.links, MU, s, V);
+  hop_fwd<MU>(u, pn, acc);
+  long sb = fine_neighbour(op.g, s, c, MU, -1);
+  load_spinor(in, sb, V, pn);
+  M3<T> ub = load_link(op.links, MU, sb, V);
+  hop_bwd<MU>(ub, pn, acc);
+}
+
+// (D(mu) in)(s) for one right-hand side
+template <typename T>
+TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, long s, T mu, cplx<T>* acc) {
+  int c[4];
+  fine_coords(op.g, s, c);
+  cplx<T> psi[12];
+  load_spinor(in, s, op.g.V, psi);
+  site_diag(op, s, mu, psi, acc);
+  site_hops_dir<0>(op, in, s, c, acc);
+  site_hops_dir<1>(op, in, s, c, acc);
+  site_hops_dir<2>(op, in, s, c, acc);
+  site_hops_dir<3>(op, in, s, c, acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __restrict__ in,
+                                                cplx<T>* __restrict__ out, const double* __restrict__ mu_dev) {
+  const long V = op.g.V;
+  long s = blockIdx.x * 256L + threadIdx.x;
+  if (s >= V) return;
+  const int r = blockIdx.y;
+  const T mu = (T)mu_dev[r];
+  cplx<T> acc[12];
+  site_dslash(op, in + (long)r * 12 * V, s, mu, acc);
+  cplx<T>* o = out + (long)r * 12 * V + s;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[(long)k * V] = acc[k];
+}
+
+template <typename T>
+void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu_dev,
+                   hipStream_t st) {
+  dim3 grid((unsigned)((op.g.V + 255) / 256), nrhs);
+  hipLaunchKernelGGL(k_dslash<T>, grid, dim3(256), 0, st, op, in, out, mu_dev);
+}
+template void launch_dslash<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
+                                    hipStream_t);
+template void launch_dslash<float>(const FineOp<float>&, const cplx<float>*, cplx<float>*, int, const double*,
+                                   hipStream_t);
+
+template <typename T>
+__global__ void k_gamma5_fine(long V, const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out) {
+  long s = blockIdx.x * 256L + threadIdx.x;
+  if (s >= V) return;
+  long base = (long)blockIdx.y * 12 * V + s;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    cplx<T> v = in[base + (long)k * V];
+    out[base + (long)k * V] = k < 6 ? v : -v;
+  }
+}
+template <typename T>
+void launch_gamma5_fine(const FineGeom& g, const cplx<T>* in, cplx<T>* out, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((g.V + 255) / 256), nrhs);
+  hipLaunchKernelGGL(k_gamma5_fine<T>, grid, dim3(256), 0, st, g.V, in, out);
+}
+template void launch_gamma5_fine<double>(const FineGeom&, const cplx<double>*, cplx<double>*, int, hipStream_t);
+template void launch_gamma5_fine<float>(const FineGeom&, const cplx<float>*, cplx<float>*, int, hipStream_t);
+
+// ------------------------------------------------------------------ SAP (K3)
+// One workgroup per SAP block (one thread per site).  For every block B of
+// the given colour: r_B = eta_B - (D z)_B, then mr_steps of minimal residual
+// on the block-restricted operator D_B (hops leaving B dropped) from e = 0,
+// then z_B += e.  Blocks of one colour only neighbour blocks of the other
+// colour, so blocks of one launch never read what another writes.
+template <int MU, typename T>
+TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, long s, int loc, const int c[4], cplx<T>* acc) {
+  const FineGeom& g = op.g;
+  const int bv = g.bvol;
+  const int lc = c[MU] % g.B[MU];
+  const bool whole = g.NB[MU] == 1;    // block spans the periodic direction
+  cplx<T> pn[12];
+  // forward neighbour
+  int nl = -1;
+  if (lc < g.B[MU] - 1) nl = loc + g.lstride[MU];
+  else if (whole) nl = loc - (g.B[MU] - 1) * g.lstride[MU];
+  if (nl >= 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
+    M3<T> u = load_link(op.links, MU, s, g.V);
+    hop_fwd<MU>(u, pn, acc);
+  }
+  nl = -1;
+  if (lc > 0) nl = loc - g.lstride[MU];
+  else if (whole) nl = loc + (g.B[MU] - 1) * g.lstride[MU];
+  if (nl >= 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
+    long sb = s - loc + nl;
+    M3<T> ub = load_link(op.links, MU, sb, g.V);
+    hop_bwd<MU>(ub, pn, acc);
+  }
+}
+
+template <typename T>
+TM_D void block_reduce3(T& a, T& b, T& c, T* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  if (lane == 0) { red[w * 3] = a; red[w * 3 + 1] = b; red[w * 3 + 2] = c; }
+  __syncthreads();
+  a = 0; b = 0; c = 0;
+  for (int i = 0; i < nw; ++i) { a += red[i * 3]; b += red[i * 3 + 1]; c += red[i * 3 + 2]; }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
+                                                  const double* __restrict__ mu_dev, const int* __restrict__ blist,
+                                                  int mr_steps) {
+  extern __shared__ unsigned char smem_raw[];
+  const FineGeom& g = op.g;
+  const long V = g.V;
+  const int bv = g.bvol;
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* red = reinterpret_cast<T*>(lds + 12 * bv);
+  const int r = blockIdx.y;
+  const T mu = (T)mu_dev[r];
+  const int loc = threadIdx.x;
+  const long s = (long)blist[blockIdx.x] * bv + loc;
+  const cplx<T>* zr = z + (long)r * 12 * V;
+  int c[4];
+  fine_coords(g, s, c);
+  cplx<T> rho[12], e[12], q[12];
+  {
+    cplx<T> dz[12];
+    site_dslash(op, zr, s, mu, dz);
+    const cplx<T>* er = eta + (long)r * 12 * V + s;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) { rho[k] = er[(long)k * V] - dz[k]; e[k] = mk<T>(0, 0); }
+  }
+  for (int it = 0; it < mr_steps; ++it) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lds[k * bv + loc] = rho[k];
+    __syncthreads();
+    site_diag(op, s, mu, rho, q);
+    block_hops_dir<0>(op, lds, s, loc, c, q);
+    block_hops_dir<1>(op, lds, s, loc, c, q);
+    block_hops_dir<2>(op, lds, s, loc, c, q);
+    block_hops_dir<3>(op, lds, s, loc, c, q);
+    T qq = 0, qr_re = 0, qr_im = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      qq += norm2(q[k]);
+      cplx<T> t = cmulc(q[k], rho[k]);
+      qr_re += t.re;
+      qr_im += t.im;
+    }
+    block_reduce3(qq, qr_re, qr_im, red);
+    cplx<T> alpha = qq > (T)0 ? mk(qr_re / qq, qr_im / qq) : mk<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      cfma(e[k], alpha, rho[k]);
+      rho[k] -= alpha * q[k];
+    }
+  }
+  cplx<T>* zo = z + (long)r * 12 * V + s;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) zo[(long)k * V] += e[k];
+}
+
+template <typename T>
+void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
+                     const int* block_list, int nblk, int mr_steps, hipStream_t st) {
+  size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
+  dim3 grid(nblk, nrhs);
+  hipLaunchKernelGGL(k_sap_fine<T>, grid, dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list, mr_steps);
+}
+template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
+                                      const int*, int, int, hipStream_t);
+template void launch_sap_fine<float>(const FineOp<float>&, const cplx<float>*, cplx<float>*, int, const double*,
+                                     const int*, int, int, hipStream_t);

@@ -1,0 +1,177 @@
+// Host-side types of the solver library.
+#pragma once
+
+#include "kernels.h"
+#include "tmamg.h"
+
+#include <functional>
+#include <memory>
+#include <string>
+#include <type_traits>
+
+struct TmError {
+  tmamg_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                                  \
+  do {                                                                                             \
+    hipError_t e_ = (x);                                                                           \
+    if (e_ != hipSuccess)                                                                          \
+      throw TmError{TMAMG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+
+extern thread_local std::string g_last_error;
+
+template <typename X>
+struct DevArr {
+  X* p = nullptr;
+  size_t n = 0;
+  int count = 0;   // optional element count used by callers (e.g. block lists)
+  DevArr() = default;
+  DevArr(const DevArr&) = delete;
+  DevArr& operator=(const DevArr&) = delete;
+  ~DevArr() { release(); }
+  void alloc(size_t cnt) {
+    if (cnt == n && p) return;
+    release();
+    if (cnt == 0) return;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), cnt * sizeof(X));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw TmError{TMAMG_ENOMEM, "hipMalloc of " + std::to_string(cnt * sizeof(X)) + " bytes failed"};
+    }
+    n = cnt;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(X); }
+};
+
+template <typename T>
+using OpFn = std::function<void(const cplx<T>*, cplx<T>*)>;
+
+template <typename T>
+struct Krylov {
+  int m = 0, cap = 0, NB = 1;
+  long n = 0;
+  bool flex = false;
+  DevArr<cplx<T>> V, Z, w;
+  DevArr<double> H, cs, sn, g, c1, c2, nrm, inv, beta0, tol, y, partial;
+  DevArr<int> active, kdone, status;
+  void ensure(long n_, int m_, int nrhs, bool flex_, hipStream_t st);
+  KrylovDev dev() const;
+};
+
+template <typename T>
+int krylov_cycle(Krylov<T>& K, const OpFn<T>& A, const OpFn<T>* M, const cplx<T>* r0, cplx<T>* x, int nrhs,
+                 int maxit, double reltol, const double* abstol, bool host_check, int* host_flags, hipStream_t st);
+
+struct Ctx;
+
+struct HierBase {
+  virtual ~HierBase() {}
+  virtual void setup(double mu) = 0;
+  virtual void setup_iteration() = 0;
+  virtual void rebuild() = 0;
+  virtual void ensure(int nrhs) = 0;
+  virtual bool is_double() const = 0;
+  // typed entry points; only the matching precision is implemented
+  virtual void precond_d(const cplx<double>*, cplx<double>*, int, const double*) { throw TmError{TMAMG_ESTATE, "precision"}; }
+  virtual void precond_f(const cplx<float>*, cplx<float>*, int, const double*) { throw TmError{TMAMG_ESTATE, "precision"}; }
+  // test hook on internal buffers of the hierarchy precision
+  virtual void test_op(int op, int level, const void* in, void* out, int nrhs, const double* mu) = 0;
+  virtual void export_P(int level, cplx<double>* out) = 0;
+  virtual void export_Dc(int level, cplx<double>* out) = 0;
+  long stats_l2 = 0, stats_coarsest = 0;
+};
+
+template <typename T, typename S>
+struct Hier : HierBase {
+  using SPair = typename Store<S>::pair;
+  Ctx* c;
+  int nlev = 1;
+  FineOp<T> fop;
+  int nv0 = 0, nv1 = 0, d1 = 0, d2 = 0;
+  CoarseGeom g1{}, g2{};
+  DevArr<int> blist0[2], blist1[2];
+  DevArr<cplx<T>> tv0, tv1, tvtmp, tmp1;
+  DevArr<SPair> P0, P1, Dc1, Dc2;
+  DevArr<cplx<double>> P64;
+  DevArr<cplx<T>> rc1, ec1, rc2, ec2;
+  Krylov<T> K1, K2;
+  DevArr<double> red_partial, red_out, red_inv, mu_setup;
+  int cap = 0;
+
+  explicit Hier(Ctx* c_);
+  void build_colours(const int nb[4], DevArr<int> out[2]);
+  void ensure(int nrhs) override;
+  void dc_apply(int level, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu);
+  void sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
+  void precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, const double* mu);
+  void coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu);
+  void normalize(cplx<T>* v, long n, int nrhs);
+  void build(int l);
+  void galerkin_only(int l);
+  void setup(double mu) override;
+  void smooth_vectors(int l);
+  void setup_iteration() override;
+  void rebuild() override;
+  bool is_double() const override { return std::is_same<T, double>::value; }
+  void precond_d(const cplx<double>* v, cplx<double>* z, int nrhs, const double* mu) override;
+  void precond_f(const cplx<float>* v, cplx<float>* z, int nrhs, const double* mu) override;
+  void test_op(int op, int level, const void* in, void* out, int nrhs, const double* mu) override;
+  void export_P(int level, cplx<double>* out) override;
+  void export_Dc(int level, cplx<double>* out) override;
+};
+
+struct Ctx {
+  tmamg_lattice lat{};
+  tmamg_params par{};
+  hipStream_t st = nullptr;
+  FineGeom fg{};
+  DevArr<cplx<double>> links64;
+  DevArr<cplx<float>> links32;
+  DevArr<double> clov64;
+  DevArr<float> clov32;
+  double kappa = 0, m0 = 0, csw = 0, mu = 0;
+  bool have_links = false, have_setup = false;
+  std::unique_ptr<HierBase> hier;
+  DevArr<cplx<double>> inject0, inject1;
+  // solve workspace
+  Krylov<double> K64;
+  Krylov<float> K32;
+  DevArr<cplx<double>> b64, x64, r64, t64;
+  DevArr<cplx<float>> r32, e32;
+  DevArr<double> mu_dev, abstol_dev, red_partial, red_out;
+  int* host_flags = nullptr;
+  double t_setup = 0;
+  int cap = 0;
+
+  Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s);
+  ~Ctx();
+  FineOp<double> op64() const { FineOp<double> o; o.g = fg; o.links = links64.p; o.clover = clov64.p; return o; }
+  FineOp<float> op32() const { FineOp<float> o; o.g = fg; o.links = links32.p; o.clover = clov32.p; return o; }
+  void load_links(const cplx<double>* U);
+  void setup(const cplx<double>* U, double kappa, double csw, double mu);
+  void setup_update(const cplx<double>* U, int iters);
+  void ensure(int nrhs);
+  std::vector<double> norms(const cplx<double>* v, int nrhs);
+  tmamg_status solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info);
+  tmamg_status solve(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
+                     tmamg_info* info);
+  tmamg_status solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,
+                             tmamg_info* info);
+  tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info);
+  void force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F);
+  void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
+  void upload_mu(int nrhs, const double* mu_host);
+};
+
+// force kernels (K13-K15)
+void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, const cplx<double>* Y,
+                  cplx<double>* F_canon, hipStream_t st);

@@ -1,0 +1,375 @@
+// Host orchestration of the DD-alpha-AMG solver (Sec. 1.1 of arXiv:1710.06198):
+// the multigrid hierarchy, its cycle (Eq. (1): coarse-grid correction, then
+// k SAP sweeps), the adaptive setup, the flexible Krylov drivers, and the
+// mixed-precision defect correction around FP32 cycles.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+thread_local std::string g_last_error;
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_rsqrt(const double* in, double* out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] > 0 ? 1.0 / sqrt(in[i]) : 0.0;
+}
+__global__ void k_fill_double(double* p, double v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ Krylov driver
+template <typename T>
+void Krylov<T>::ensure(long n_, int m_, int nrhs, bool flex_, hipStream_t st) {
+  if (n == n_ && m >= m_ && cap >= nrhs && (flex || !flex_)) return;
+  n = n_;
+  m = std::max(m, m_);
+  cap = std::max(cap, nrhs);
+  flex = flex || flex_;
+  NB = reduce_blocks(n);
+  V.alloc((size_t)(m + 1) * cap * n);
+  if (flex) Z.alloc((size_t)m * cap * n);
+  w.alloc((size_t)cap * n);
+  H.alloc(2 * (size_t)cap * (m + 1) * m);
+  cs.alloc(2 * (size_t)cap * m);
+  sn.alloc(2 * (size_t)cap * m);
+  g.alloc(2 * (size_t)cap * (m + 1));
+  c1.alloc(2 * (size_t)cap * (m + 1));
+  c2.alloc(2 * (size_t)cap * (m + 1));
+  nrm.alloc(cap);
+  inv.alloc(cap);
+  beta0.alloc(cap);
+  tol.alloc(cap);
+  y.alloc(2 * (size_t)cap * m);
+  partial.alloc(2 * (size_t)cap * (m + 1) * NB);
+  active.alloc(cap);
+  kdone.alloc(cap);
+  status.alloc(cap);
+  launch_fill_zero(V.p, V.bytes(), st);
+  if (flex) launch_fill_zero(Z.p, Z.bytes(), st);
+  launch_fill_zero(w.p, w.bytes(), st);
+  launch_fill_zero(active.p, active.bytes(), st);
+  launch_fill_zero(kdone.p, kdone.bytes(), st);
+  launch_fill_zero(inv.p, inv.bytes(), st);
+}
+
+template <typename T>
+KrylovDev Krylov<T>::dev() const {
+  KrylovDev k;
+  k.m = m;
+  k.H = H.p; k.cs = cs.p; k.sn = sn.p; k.g = g.p; k.c1 = c1.p; k.c2 = c2.p;
+  k.nrm = nrm.p; k.inv = inv.p; k.beta0 = beta0.p; k.tol = tol.p; k.y = y.p;
+  k.active = active.p; k.kdone = kdone.p; k.status = status.p;
+  return k;
+}
+
+// One (F)GMRES cycle of at most maxit steps for A e = r0, accumulating into x:
+// x += Z y (flexible) or V y.  Per-RHS predication: a right-hand side stops
+// contributing once its implicit residual meets its target.  With
+// host_check the host reads the active flags after every step and ends the
+// cycle early; without it the launch schedule is fixed.
+template <typename T>
+int krylov_cycle(Krylov<T>& K, const OpFn<T>& A, const OpFn<T>* M, const cplx<T>* r0, cplx<T>* x, int nrhs,
+                 int maxit, double reltol, const double* abstol, bool host_check, int* host_flags, hipStream_t st) {
+  const long n = K.n;
+  const long vs = (long)nrhs * n;
+  KrylovDev kd = K.dev();
+  const int NB = K.NB;
+  maxit = std::min(maxit, K.m);
+  launch_norm2(r0, n, nrhs, K.partial.p, NB, nullptr, st);
+  launch_finalize_real(K.partial.p, nrhs, NB, kd.nrm, st);
+  launch_krylov_start(kd, reltol, abstol, nrhs, st);
+  launch_scale_dev(r0, K.V.p, kd.inv, n, nrhs, nullptr, st);
+  int done = 0;
+  if (host_check) {
+    HIPCHK(hipMemcpyAsync(host_flags, kd.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any |= host_flags[r] != 0;
+    if (!any) return 0;
+  }
+  for (int j = 0; j < maxit; ++j) {
+    cplx<T>* vj = K.V.p + (long)j * vs;
+    cplx<T>* zj = vj;
+    if (M) {
+      zj = K.Z.p + (long)j * vs;
+      (*M)(vj, zj);
+    }
+    A(zj, K.w.p);
+    launch_multidot(K.V.p, vs, j + 1, K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
+    launch_finalize(K.partial.p, nrhs * (j + 1), j + 1, NB, kd.c1, K.m + 1, st);
+    launch_multiaxpy(K.w.p, K.V.p, vs, j + 1, kd.c1, K.m + 1, n, nrhs, -1.0, kd.active, st);
+    launch_multidot(K.V.p, vs, j + 1, K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
+    launch_finalize(K.partial.p, nrhs * (j + 1), j + 1, NB, kd.c2, K.m + 1, st);
+    launch_multiaxpy(K.w.p, K.V.p, vs, j + 1, kd.c2, K.m + 1, n, nrhs, -1.0, kd.active, st);
+    launch_norm2(K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
+    launch_finalize_real(K.partial.p, nrhs, NB, kd.nrm, st);
+    launch_krylov_step(kd, j, nrhs, st);
+    if (j + 1 < maxit) launch_scale_dev(K.w.p, K.V.p + (long)(j + 1) * vs, kd.inv, n, nrhs, nullptr, st);
+    done = j + 1;
+    if (host_check) {
+      HIPCHK(hipMemcpyAsync(host_flags, kd.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool any = false;
+      for (int r = 0; r < nrhs; ++r) any |= host_flags[r] != 0;
+      if (!any) break;
+    }
+  }
+  launch_krylov_solve_y(kd, nrhs, st);
+  launch_krylov_update(x, M ? K.Z.p : K.V.p, vs, kd, n, nrhs, st);
+  return done;
+}
+
+// ------------------------------------------------------------------ hierarchy
+template <typename T, typename S>
+Hier<T, S>::Hier(Ctx* c_) : c(c_) {
+  const tmamg_params& p = c->par;
+  nlev = p.nlevels;
+  fop.g = c->fg;
+  if constexpr (std::is_same<T, double>::value) {
+    fop.links = c->links64.p;
+    fop.clover = c->clov64.p;
+  } else {
+    fop.links = c->links32.p;
+    fop.clover = c->clov32.p;
+  }
+  // fine SAP colour lists (blocks = aggregates of the fine ordering)
+  build_colours(c->fg.NB, blist0);
+  if (nlev >= 2) {
+    nv0 = p.nv[0];
+    d1 = 2 * nv0;
+    g1.V = 1;
+    for (int m = 0; m < 4; ++m) { g1.L[m] = c->fg.NB[m]; g1.V *= g1.L[m]; }
+  }
+  if (nlev >= 3) {
+    nv1 = p.nv[1];
+    d2 = 2 * nv1;
+    g2.V = 1;
+    for (int m = 0; m < 4; ++m) { g2.L[m] = g1.L[m] / p.agg[1][m]; g2.V *= g2.L[m]; }
+    int nb[4];
+    for (int m = 0; m < 4; ++m) nb[m] = g1.L[m] / p.sap_block1[m];
+    build_colours(nb, blist1);
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::build_colours(const int nb[4], DevArr<int> out[2]) {
+  std::vector<int> lists[2];
+  for (int b3 = 0; b3 < nb[3]; ++b3)
+    for (int b2 = 0; b2 < nb[2]; ++b2)
+      for (int b1 = 0; b1 < nb[1]; ++b1)
+        for (int b0 = 0; b0 < nb[0]; ++b0) {
+          int id = ((b3 * nb[2] + b2) * nb[1] + b1) * nb[0] + b0;
+          lists[(b0 + b1 + b2 + b3) & 1].push_back(id);
+        }
+  for (int cidx = 0; cidx < 2; ++cidx) {
+    out[cidx].alloc(std::max<size_t>(1, lists[cidx].size()));
+    if (!lists[cidx].empty())
+      HIPCHK(hipMemcpy(out[cidx].p, lists[cidx].data(), lists[cidx].size() * sizeof(int), hipMemcpyHostToDevice));
+    out[cidx].count = (int)lists[cidx].size();
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::ensure(int nrhs) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  int need = std::max(nrhs, std::max(nv0, nv1));
+  if (need <= cap) return;
+  cap = need;
+  red_partial.alloc(1024 * (size_t)cap);
+  red_out.alloc(cap);
+  red_inv.alloc(cap);
+  if (nlev >= 2) {
+    rc1.alloc((size_t)cap * g1.V * d1);
+    ec1.alloc((size_t)cap * g1.V * d1);
+    if (nlev == 2) K1.ensure(g1.V * d1, p.coarsest_iters, cap, false, st);
+    else K1.ensure(g1.V * d1, p.l2_iters, cap, true, st);
+  }
+  if (nlev >= 3) {
+    rc2.alloc((size_t)cap * g2.V * d2);
+    ec2.alloc((size_t)cap * g2.V * d2);
+    tmp1.alloc((size_t)cap * g1.V * d1);
+    K2.ensure(g2.V * d2, p.coarsest_iters, cap, false, st);
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::dc_apply(int level, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu) {
+  if (level == 1) launch_coarse_apply<T, S>(g1, d1, Dc1.p, in, out, nrhs, mu, c->st);
+  else launch_coarse_apply<T, S>(g2, d2, Dc2.p, in, out, nrhs, mu, c->st);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps) {
+  const tmamg_params& p = c->par;
+  for (int k = 0; k < sweeps; ++k)
+    for (int col = 0; col < 2; ++col) {
+      if (level == 0) {
+        if (blist0[col].count == 0) continue;
+        launch_sap_fine<T>(fop, eta, z, nrhs, mu, blist0[col].p, blist0[col].count, p.mr_steps, c->st);
+      } else {
+        if (blist1[col].count == 0) continue;
+        launch_sap_coarse<T, S>(g1, d1, p.sap_block1, Dc1.p, eta, z, nrhs, mu, blist1[col].p, blist1[col].count,
+                                p.mr_steps, c->st);
+      }
+    }
+}
+
+// Eq. (1): z = P D_c^-1 P^dag v (approximately), then k SAP sweeps on D z = v.
+template <typename T, typename S>
+void Hier<T, S>::precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, const double* mu) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  if (level == 0) {
+    if (nlev == 1) {
+      launch_fill_zero(z, (size_t)nrhs * 12 * c->fg.V * sizeof(cplx<T>), st);
+    } else {
+      launch_restrict_fine<T, S>(c->fg, P0.p, nv0, v, rc1.p, nrhs, st);
+      coarse_solve(1, rc1.p, ec1.p, nrhs, mu);
+      launch_prolong_fine<T, S>(c->fg, P0.p, nv0, ec1.p, z, nrhs, st);
+    }
+    sap(0, v, z, nrhs, mu, p.sap_sweeps[0]);
+  } else {
+    launch_restrict_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, v, rc2.p, nrhs, st);
+    coarse_solve(2, rc2.p, ec2.p, nrhs, mu);
+    launch_prolong_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, ec2.p, z, nrhs, st);
+    sap(1, v, z, nrhs, mu, p.sap_sweeps[1]);
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  long n = level == 1 ? g1.V * d1 : g2.V * d2;
+  launch_fill_zero(sol, (size_t)nrhs * n * sizeof(cplx<T>), st);
+  Krylov<T>& K = level == 1 ? K1 : K2;
+  OpFn<T> A = [this, level, nrhs, mu](const cplx<T>* in, cplx<T>* out) { dc_apply(level, in, out, nrhs, mu); };
+  if (level == nlev - 1) {
+    int it = krylov_cycle<T>(K, A, nullptr, rhs, sol, nrhs, p.coarsest_iters, p.coarsest_tol, nullptr, false,
+                             nullptr, st);
+    stats_coarsest += it;
+  } else {
+    OpFn<T> M = [this, nrhs, mu](const cplx<T>* in, cplx<T>* out) { precond(1, in, out, nrhs, mu); };
+    int it = krylov_cycle<T>(K, A, &M, rhs, sol, nrhs, p.l2_iters, p.l2_tol, nullptr, false, nullptr, st);
+    stats_l2 += it;
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::normalize(cplx<T>* v, long n, int nrhs) {
+  hipStream_t st = c->st;
+  int NB = reduce_blocks(n);
+  launch_norm2(v, n, nrhs, red_partial.p, NB, nullptr, st);
+  launch_finalize_real(red_partial.p, nrhs, NB, red_out.p, st);
+  hipLaunchKernelGGL(k_rsqrt, dim3((nrhs + 63) / 64), dim3(64), 0, st, red_out.p, red_inv.p, nrhs);
+  launch_scale_dev(v, v, red_inv.p, n, nrhs, nullptr, st);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::build(int l) {
+  hipStream_t st = c->st;
+  const tmamg_params& p = c->par;
+  if (l == 0) {
+    launch_gs_fine<T, S>(c->fg, tv0.p, nv0, P64.p, P0.p, st);
+    launch_galerkin_fine<T, S>(fop, P0.p, nv0, Dc1.p, st);
+  } else {
+    launch_gs_coarse<T, S>(g1, d1, p.agg[1], tv1.p, nv1, P64.p, P1.p, st);
+    launch_galerkin_coarse<T, S>(g1, d1, p.agg[1], Dc1.p, P1.p, nv1, Dc2.p, st);
+  }
+}
+
+template <typename T, typename S>
+void Hier<T, S>::galerkin_only(int l) {
+  const tmamg_params& p = c->par;
+  if (l == 1) launch_galerkin_coarse<T, S>(g1, d1, p.agg[1], Dc1.p, P1.p, nv1, Dc2.p, c->st);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::setup(double mu) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  if (nlev < 2) return;
+  const long n0 = 12 * c->fg.V;
+  tv0.alloc((size_t)nv0 * n0);
+  P0.alloc((size_t)nv0 * n0);
+  Dc1.alloc((size_t)g1.V * 9 * d1 * d1);
+  size_t p64 = (size_t)nv0 * n0;
+  if (nlev >= 3) {
+    tv1.alloc((size_t)nv1 * g1.V * d1);
+    P1.alloc((size_t)nv1 * g1.V * d1);
+    Dc2.alloc((size_t)g2.V * 9 * d2 * d2);
+    p64 = std::max(p64, (size_t)nv1 * g1.V * d1);
+  }
+  P64.alloc(p64);
+  ensure(std::max(nv0, nv1));
+  tvtmp.alloc((size_t)nv0 * n0);
+  mu_setup.alloc(std::max(nv0, nv1));
+  int nmax = std::max(nv0, nv1);
+  hipLaunchKernelGGL(k_fill_double, dim3(1), dim3(64), 0, st, mu_setup.p, mu, nmax);
+  // level-0 start vectors
+  if (c->inject0.p) launch_convert<double, T>(c->inject0.p, tv0.p, (long)nv0 * n0, st);
+  else launch_random<T>(tv0.p, (long)nv0 * n0, p.seed, st);
+  smooth_vectors(0);
+  build(0);
+  if (nlev >= 3) {
+    long n1 = g1.V * d1;
+    if (c->inject1.p) launch_convert<double, T>(c->inject1.p, tv1.p, (long)nv1 * n1, st);
+    else launch_random<T>(tv1.p, (long)nv1 * n1, p.seed + 7919, st);
+    smooth_vectors(1);
+    build(1);
+  }
+  for (int it = 0; it < p.setup_iters; ++it) setup_iteration();
+}
+
+// Initial phase: v <- SAP(v) from zero, normalised, init_smooth times.
+template <typename T, typename S>
+void Hier<T, S>::smooth_vectors(int l) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
+  int nv = l == 0 ? nv0 : nv1;
+  cplx<T>* v = l == 0 ? tv0.p : tv1.p;
+  cplx<T>* w = l == 0 ? tvtmp.p : tmp1.p;
+  for (int k = 0; k < p.init_smooth; ++k) {
+    launch_fill_zero(w, (size_t)nv * n * sizeof(cplx<T>), st);
+    sap(l, v, w, nv, mu_setup.p, p.sap_sweeps[l]);
+    HIPCHK(hipMemcpyAsync(v, w, (size_t)nv * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+    normalize(v, n, nv);
+  }
+}
+
+// v_i <- B_MG v_i on each level in turn (normalised), rebuilding P and D_c;
+// the Galerkin operator below a rebuilt one is recomputed at once from its
+// current P so the next level's update uses a consistent cycle.
+template <typename T, typename S>
+void Hier<T, S>::setup_iteration() {
+  hipStream_t st = c->st;
+  for (int l = 0; l < nlev - 1; ++l) {
+    long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
+    int nv = l == 0 ? nv0 : nv1;
+    cplx<T>* v = l == 0 ? tv0.p : tv1.p;
+    cplx<T>* w = l == 0 ? tvtmp.p : tmp1.p;
+    precond(l, v, w, nv, mu_setup.p);
+    HIPCHK(hipMemcpyAsync(v, w, (size_t)nv * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+    normalize(v, n, nv);
+    build(l);
+    if (l + 2 < nlev) galerkin_only(l + 1);
+  }
+}
+
+template struct Hier<double, double>;
+template struct Hier<float, float>;
+template struct Hier<float, __hip_bfloat16>;
+template struct Hier<float, __half>;
+template int krylov_cycle<double>(Krylov<double>&, const OpFn<double>&, const OpFn<double>*, const cplx<double>*,
+                                  cplx<double>*, int, int, double, const double*, bool, int*, hipStream_t);
+template int krylov_cycle<float>(Krylov<float>&, const OpFn<float>&, const OpFn<float>*, const cplx<float>*,
+                                 cplx<float>*, int, int, double, const double*, bool, int*, hipStream_t);
+template struct Krylov<double>;
+template struct Krylov<float>;
