@@ -1,0 +1,211 @@
+"""Benchmark: DD-alpha-AMG time to solution on one MI355X.
+
+Workload (default): the 24^3 x 48 precision-form case - synthetic links
+(spread 0.25), c_sw = 1.6, mu = 0.0015, 3-level DD-alpha-AMG (4^4 then 2^4
+aggregates, N_v = 24/32, SAP 4^4 / 3^4 with 4 MR steps, 3 setup
+iterations), FP32 stencil/SAP with bf16 P and D_c, FP64 outer FGMRES with
+reliable updates, one Gaussian right-hand side solved to relative residual
+1e-10.  A step is one full job: setup (link conversion, clover, adaptive
+setup) plus the solve.  The plain FP64 DD-alpha-AMG on the same GPU is
+timed alongside for the speed-up, and the fine stencil's HBM roofline is
+measured with HIP events on the library's stream.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solver_params(tm, w, precision):
+    p = dict(nlevels=w.nlevels, agg=w.agg, nv=w.nv, setup_iters=w.setup_iters, init_smooth=w.init_smooth,
+             sap_sweeps=w.sap_sweeps, mr_steps=w.mr_steps, restart=w.restart, precision=precision,
+             storage=tm.STORE_BF16, coarsest_iters=50 if w.nlevels == 3 else 100, l2_iters=10)
+    if w.nlevels == 3:
+        p["sap_block1"] = w.sap_block[1]
+    return tm.default_params(**p)
+
+
+def cpu_baseline(w, m0, budget_dims=(8, 8, 8, 8)):
+    """The oracle (FP64 DD-alpha-AMG, torch-CPU) on an 8^4 lattice drawn with
+    the workload's link spread, c_sw, mu and hierarchy; setup + solve time
+    scaled by the volume ratio to the workload's lattice."""
+    import torch
+    from lattice_inputs import gauge_links, gaussian_spinor
+    from oracle.dirac import WilsonClover, spinor_to_field, norm
+    from oracle import mg
+    U = gauge_links(budget_dims, w.eps, w.seeds["links"])
+    op = WilsonClover(U, m0, w.csw)
+    b = spinor_to_field(gaussian_spinor(budget_dims, w.seeds["source"])[0])
+    sap = [w.sap_block[0]] + [tuple(min(a, l) for a, l in zip(w.sap_block[1], (1, 1, 1, 1)))]
+    p = mg.MGParams(nlevels=w.nlevels, agg=w.agg, nv=w.nv, sap_block=tuple(sap[:w.nlevels - 1] or sap),
+                    setup_iters=w.setup_iters, mr_steps=w.mr_steps, init_smooth=w.init_smooth)
+    t0 = time.time()
+    H = mg.Hierarchy(op, p, w.mu)
+    H.setup(mg.setup_vectors(p, budget_dims, w.seeds["testvec"]))
+    t1 = time.time()
+    r = H.solve(b, w.tol, restart=w.restart)
+    t2 = time.time()
+    vol = 1
+    for d in budget_dims:
+        vol *= d
+    scale = w.volume / vol
+    res = norm(b - op.apply(r.x, w.mu)) / norm(b)
+    return {
+        "value": (t2 - t0) * scale,
+        "unit": "s",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle setup+solve at {'x'.join(map(str, budget_dims))} with the workload's spread, c_sw, mu "
+                   f"and hierarchy ({t1 - t0:.1f} s setup + {t2 - t1:.1f} s solve, {r.iters} iterations, "
+                   f"residual {res:.1e}), scaled by the volume ratio {scale:.0f}"),
+        "cpu_model": _cpu_model(),
+        "os_cpu_count": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is described in DESIGN.md, not implemented)"}))
+        return 2
+
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
+
+    w = workload(args.workload)
+    m0 = load_m0()[w.name]
+    kappa = 1.0 / (2 * m0 + 8)
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {w.name} dims {w.dims}: generating inputs")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    b = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"], n=1)).to(dev)
+    x = torch.empty_like(b)
+    stream = torch.cuda.Stream(device=dev)
+
+    def job(solver):
+        solver.setup(U, kappa, w.csw, w.mu)
+        return solver.solve(b, x, tol=w.tol)
+
+    mixed = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED), stream=stream)
+    for i in range(args.warmup):
+        log(f"[bench] warmup {i}")
+        info = job(mixed)
+        log(f"[bench]   {info.as_dict()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(job(mixed).as_dict())
+        log(f"[bench] step {i}: {infos[-1]}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    setup_s = sum(i["t_setup_s"] for i in infos) / len(infos)
+    solve_s = sum(i["t_solve_s"] for i in infos) / len(infos)
+
+    # fine stencil roofline (FP32, the solve's operator), HIP events on the library stream
+    V = w.volume
+    st_ms = mixed.time_kernel(tm.K_DSLASH32, 1, 50)
+    bytes_site = 768   # in 96 + out 96 + links 4*72 + clover 288 (FP32)
+    achieved = bytes_site * V / (st_ms * 1e-3) / 1e9
+    kern = {}
+    for nm, kid in (("sap_fine_colour", tm.K_SAP0), ("restrict_fine", tm.K_RESTRICT0),
+                    ("prolong_fine", tm.K_PROLONG0), ("coarse_op_l1", tm.K_DC1), ("coarse_op_l2", tm.K_DC2),
+                    ("sap_coarse_colour", tm.K_SAP1), ("dslash_fp64", tm.K_DSLASH64)):
+        try:
+            kern[nm] = round(mixed.time_kernel(kid, 1, 20), 4)
+        except tm.TmamgError:
+            pass
+    kern["dslash_fp32"] = round(st_ms, 4)
+
+    fp64 = None
+    if not args.no_fp64:
+        log("[bench] plain FP64 DD-alpha-AMG")
+        plain = tm.Solver(w.dims, solver_params(tm, w, tm.FP64), stream=stream)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        fi = job(plain).as_dict()
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        fp64 = {"total_s": f1 - f0, "setup_s": fi["t_setup_s"], "solve_s": fi["t_solve_s"],
+                "outer_iters": fi["outer_iters"], "true_rel_resid": fi["true_rel_resid"]}
+        log(f"[bench]   {fp64}")
+        plain.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(w, m0)
+        log(f"[bench]   {cpu}")
+
+    out = {
+        "metric": "solve time (s) @1e-10 rel. resid",
+        "value": ms / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "fp32+bf16 (fp64 outer)",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {'x'.join(map(str, w.dims))} twisted-mass clover, "
+                               f"{w.nlevels}-level DD-alpha-AMG, mixed precision, 1 RHS, setup+solve",
+                   "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "m0": m0, "nv": list(w.nv),
+                   "tol": w.tol, "parallelism": "1 GPU"},
+        "setup_s": setup_s,
+        "solve_s": solve_s,
+        "outer_iters": infos[-1]["outer_iters"],
+        "true_rel_resid": max(i["true_rel_resid"] for i in infos),
+        "fp64_amg": fp64,
+        "speedup_vs_fp64": (fp64["total_s"] / (ms / 1e3)) if fp64 else None,
+        "kernel_ms": kern,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_dslash<float> (fine stencil)", "bytes_per_site": bytes_site, "sites": V},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    mixed.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -163,6 +163,23 @@ tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void
 tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void* v);
 tmamg_status tmamg_debug_export(tmamg_ctx* ctx, int what, int level, void* out);
 
+/* Kernel timing for measurements: launches kernel `kernel` `reps` times on
+ * internal buffers of nrhs right-hand sides (random contents) between two
+ * HIP events on the context's stream and stores the mean milliseconds per
+ * launch in *avg_ms (host).  Kernels: TMAMG_K_*. Needs a completed setup
+ * for the multigrid kernels. */
+enum {
+  TMAMG_K_DSLASH32 = 0,   /* fine stencil, FP32 */
+  TMAMG_K_DSLASH64 = 1,   /* fine stencil, FP64 */
+  TMAMG_K_SAP0 = 2,       /* fine SAP, one colour (hierarchy precision) */
+  TMAMG_K_RESTRICT0 = 3,  /* fine -> level 1 */
+  TMAMG_K_PROLONG0 = 4,   /* level 1 -> fine */
+  TMAMG_K_DC1 = 5,        /* coarse operator, level 1 */
+  TMAMG_K_DC2 = 6,        /* coarse operator, level 2 */
+  TMAMG_K_SAP1 = 7        /* coarse SAP on level 1, one colour */
+};
+tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms);
+
 /* Sizes of level `level`: sites and dof per site (fine: 12). */
 tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int* dof);
 

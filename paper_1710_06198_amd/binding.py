@@ -21,8 +21,9 @@ EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",
     "tmamg_solve_shifted", "tmamg_force", "tmamg_force_from_fields", "tmamg_apply",
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
-    "tmamg_last_error",
+    "tmamg_time_kernel", "tmamg_last_error",
 ]
+K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1 = range(8)
 
 
 class Lattice(ctypes.Structure):
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.tmamg_debug_set_test_vectors.argtypes = [vp, i, vp]
     lib.tmamg_debug_export.argtypes = [vp, i, i, vp]
     lib.tmamg_level_info.argtypes = [vp, i, P(ctypes.c_long), P(i)]
+    lib.tmamg_time_kernel.argtypes = [vp, i, i, i, P(d)]
     lib.tmamg_destroy.argtypes = [vp]
     lib.tmamg_destroy.restype = None
     lib.tmamg_last_error.restype = ctypes.c_char_p
@@ -210,6 +212,11 @@ class Solver:
 
     def export(self, what, level, out):
         _check(self.lib.tmamg_debug_export(self.h, int(what), int(level), _ptr(out)))
+
+    def time_kernel(self, kernel, nrhs=1, reps=20):
+        ms = ctypes.c_double()
+        _check(self.lib.tmamg_time_kernel(self.h, int(kernel), int(nrhs), int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def level_info(self, level):
         s, d = ctypes.c_long(), ctypes.c_int()

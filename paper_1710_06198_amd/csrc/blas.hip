@@ -28,38 +28,38 @@ template <typename T> TM_D void block_sum2(double& a, double& b, double* red) {
   __syncthreads();
 }
 
-// partial[(r*nvec + i)*NB + b] = sum over block b's chunk of conj(V_i,r) w_r
+// partial[(r*nvec + i)*NB + b] = sum over block b's chunk of conj(V_i,r) w_r;
+// grid (NB, nvec, nrhs): every (chunk, vector) pair reduces in parallel.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_multidot(const cplx<T>* __restrict__ V, long vstride, int nvec,
                                                  const cplx<T>* __restrict__ w, long n, double* partial, int NB,
                                                  const int* __restrict__ active) {
   __shared__ double red[2 * (RB / 64)];
-  const int r = blockIdx.y, b = blockIdx.x;
+  const int b = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
   if (active && !active[r]) return;
   const long chunk = (n + NB - 1) / NB;
   const long lo = b * chunk, hi = min(n, lo + chunk);
   const cplx<T>* wr = w + (long)r * n;
-  for (int i = 0; i < nvec; ++i) {
-    const cplx<T>* v = V + (long)i * vstride + (long)r * n;
-    double are = 0, aim = 0;
-    for (long k = lo + threadIdx.x; k < hi; k += RB) {
-      cplx<T> a = v[k], c = wr[k];
-      are += (double)a.re * c.re + (double)a.im * c.im;
-      aim += (double)a.re * c.im - (double)a.im * c.re;
-    }
-    block_sum2<T>(are, aim, red);
-    if (threadIdx.x == 0) {
-      long o = ((long)r * nvec + i) * NB + b;
-      partial[2 * o] = are;
-      partial[2 * o + 1] = aim;
-    }
+  const cplx<T>* v = V + (long)i * vstride + (long)r * n;
+  double are = 0, aim = 0;
+  for (long k = lo + threadIdx.x; k < hi; k += RB) {
+    cplx<T> a = v[k], c = wr[k];
+    are += (double)a.re * c.re + (double)a.im * c.im;
+    aim += (double)a.re * c.im - (double)a.im * c.re;
+  }
+  block_sum2<T>(are, aim, red);
+  if (threadIdx.x == 0) {
+    long o = ((long)r * nvec + i) * NB + b;
+    partial[2 * o] = are;
+    partial[2 * o + 1] = aim;
   }
 }
 
 template <typename T>
 void launch_multidot(const cplx<T>* V, long vstride, int nvec, const cplx<T>* w, long n, int nrhs, double* partial,
                      int NB, const int* active, hipStream_t st) {
-  hipLaunchKernelGGL(k_multidot<T>, dim3(NB, nrhs), dim3(RB), 0, st, V, vstride, nvec, w, n, partial, NB, active);
+  hipLaunchKernelGGL(k_multidot<T>, dim3(NB, nvec, nrhs), dim3(RB), 0, st, V, vstride, nvec, w, n, partial, NB,
+                     active);
 }
 
 // out[(o / nvec)*ostride + o % nvec] = sum_b partial[o*NB + b] (complex), one wave per output
@@ -237,34 +237,35 @@ __global__ void k_krylov_step(KrylovDev k, int j, int nrhs) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs || !k.active[r]) return;
   const int m = k.m;
-  double* H = k.H + 2L * r * (m + 1) * m;     // H[i][j] at (i*m + j)
+  double* H = k.H + 2L * r * (m + 1) * m;     // H[i][j] at (i*m + j); column j built in place
   double* cs = k.cs + 2L * r * m;
   double* sn = k.sn + 2L * r * m;
   double* g = k.g + 2L * r * (m + 1);
   const double* c1 = k.c1 + 2L * r * (m + 1);
   const double* c2 = k.c2 + 2L * r * (m + 1);
-  double hre[128], him[128];   // column j, j < 128
-  for (int i = 0; i <= j; ++i) { hre[i] = c1[2 * i] + c2[2 * i]; him[i] = c1[2 * i + 1] + c2[2 * i + 1]; }
   double hn = sqrt(fmax(k.nrm[r], 0.0));
-  // apply previous rotations [[c, s], [-conj(s), conj(c)]]
+  // column j = c1 + c2 with the previous rotations [[c, s], [-conj(s), conj(c)]] applied
+  double ar = c1[0] + c2[0], ai = c1[1] + c2[1];
   for (int i = 0; i < j; ++i) {
+    double br = c1[2 * (i + 1)] + c2[2 * (i + 1)], bi = c1[2 * (i + 1) + 1] + c2[2 * (i + 1) + 1];
     double cr = cs[2 * i], ci = cs[2 * i + 1], sr = sn[2 * i], si = sn[2 * i + 1];
-    double ar = hre[i], ai = him[i], br = hre[i + 1], bi = him[i + 1];
     double tr = cr * ar - ci * ai + sr * br - si * bi;
     double ti = cr * ai + ci * ar + sr * bi + si * br;
     double ur = -(sr * ar + si * ai) + (cr * br + ci * bi);
     double ui = -(sr * ai - si * ar) + (cr * bi - ci * br);
-    hre[i] = tr; him[i] = ti; hre[i + 1] = ur; him[i + 1] = ui;
+    H[2 * (i * m + j)] = tr;
+    H[2 * (i * m + j) + 1] = ti;
+    ar = ur;
+    ai = ui;
   }
-  double ar = hre[j], ai = him[j];
   double den = sqrt(ar * ar + ai * ai + hn * hn);
   bool bad = !finite(den) || !finite(hn) || den == 0.0;
   if (bad) { k.active[r] = 0; k.status[r] = 2; k.inv[r] = 0; return; }
   // c = conj(a)/den, s = conj(b)/den with b = hn real
   cs[2 * j] = ar / den; cs[2 * j + 1] = -ai / den;
   sn[2 * j] = hn / den; sn[2 * j + 1] = 0;
-  hre[j] = den; him[j] = 0;
-  for (int i = 0; i <= j; ++i) { H[2 * (i * m + j)] = hre[i]; H[2 * (i * m + j) + 1] = him[i]; }
+  H[2 * (j * m + j)] = den;
+  H[2 * (j * m + j) + 1] = 0;
   double gr = g[2 * j], gi = g[2 * j + 1];
   double s_r = hn / den;
   g[2 * (j + 1)] = -s_r * gr;

@@ -6,8 +6,6 @@
 
 template <typename S> using SP = typename Store<S>::pair;
 
-TM_D int blk_index(int b, int mu, int step) { return b; }
-
 // ------------------------------------------------------------------ apply (K6)
 // One thread per (site, row); the 9 input vectors a site needs are staged in LDS.
 template <typename T, typename S>
@@ -24,13 +22,12 @@ __global__ void __launch_bounds__(256) k_coarse_apply(CoarseGeom g, int d, const
   const cplx<T>* inr = in + (long)r * g.V * d;
   cplx<T>* st = lds + ls * 9 * d;
   if (valid) {
-    int c[4];
-    coarse_coords(g, y, c);
+    const C4 c = cc_coords(g, y);
     st[i] = inr[y * d + i];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-      st[(1 + 2 * mu) * d + i] = inr[coarse_neighbour(g, c, mu, +1) * d + i];
-      st[(2 + 2 * mu) * d + i] = inr[coarse_neighbour(g, c, mu, -1) * d + i];
+      st[(1 + 2 * mu) * d + i] = inr[cc_nbr(g, c, mu, +1) * d + i];
+      st[(2 + 2 * mu) * d + i] = inr[cc_nbr(g, c, mu, -1) * d + i];
     }
   }
   __syncthreads();
@@ -48,12 +45,56 @@ __global__ void __launch_bounds__(256) k_coarse_apply(CoarseGeom g, int d, const
   out[(long)r * g.V * d + y * d + i] = acc;
 }
 
+template <typename T, typename S, int D>
+__global__ void __launch_bounds__(256) k_coarse_apply_d(CoarseGeom g, const SP<S>* __restrict__ Dc,
+                                                        const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                        const double* __restrict__ mu_dev) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int spw = 256 / D;
+  const int ls = threadIdx.x / D, i = threadIdx.x - ls * D;
+  const long y = (long)blockIdx.x * spw + ls;
+  const int r = blockIdx.y;
+  const bool valid = ls < spw && y < g.V;
+  const cplx<T>* inr = in + (long)r * g.V * D;
+  cplx<T>* st = lds + ls * 9 * D;
+  if (valid) {
+    const C4 c = cc_coords(g, y);
+    st[i] = inr[y * D + i];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      st[(1 + 2 * mu) * D + i] = inr[cc_nbr(g, c, mu, +1) * D + i];
+      st[(2 + 2 * mu) * D + i] = inr[cc_nbr(g, c, mu, -1) * D + i];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const SP<S>* Dm = Dc + y * 9L * D * D + i;
+  cplx<T> acc = mk<T>(0, 0);
+  for (int b = 0; b < 9; ++b) {
+    const SP<S>* Db = Dm + (long)b * D * D;
+    const cplx<T>* v = st + b * D;
+#pragma unroll 16
+    for (int j = 0; j < D; ++j) cfma(acc, Store<S>::template ld<T>(Db + j * D), v[j]);
+  }
+  const T mu = (T)mu_dev[r];
+  acc += (i < D / 2 ? mu : -mu) * times_i(st[i]);
+  out[(long)r * g.V * D + y * D + i] = acc;
+}
+
 template <typename T, typename S>
 void launch_coarse_apply(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out, int nrhs,
                          const double* mu_dev, hipStream_t st) {
   const int spw = 256 / d;
   dim3 grid((unsigned)((g.V + spw - 1) / spw), nrhs);
   size_t sh = (size_t)spw * 9 * d * sizeof(cplx<T>);
+  switch (d) {
+    case 24: hipLaunchKernelGGL((k_coarse_apply_d<T, S, 24>), grid, dim3(256), sh, st, g, Dc, in, out, mu_dev); return;
+    case 32: hipLaunchKernelGGL((k_coarse_apply_d<T, S, 32>), grid, dim3(256), sh, st, g, Dc, in, out, mu_dev); return;
+    case 48: hipLaunchKernelGGL((k_coarse_apply_d<T, S, 48>), grid, dim3(256), sh, st, g, Dc, in, out, mu_dev); return;
+    case 64: hipLaunchKernelGGL((k_coarse_apply_d<T, S, 64>), grid, dim3(256), sh, st, g, Dc, in, out, mu_dev); return;
+    default: break;
+  }
   hipLaunchKernelGGL((k_coarse_apply<T, S>), grid, dim3(256), sh, st, g, d, Dc, in, out, mu_dev);
 }
 
@@ -75,32 +116,37 @@ void launch_gamma5_coarse(long V, int d, const cplx<T>* in, cplx<T>* out, int nr
 struct CBlock {
   int B[4], NB[4], nbs;
 };
-TM_D void cblock_site(const CoarseGeom& g, const CBlock& cb, int blk, int sl, int c[4], int lc[4]) {
+// site of local index sl in block blk: global coordinates c, local coordinates lc
+TM_D void cblock_site(const CoarseGeom& g, const CBlock& cb, int blk, int sl, C4& c, C4& lc) {
   int b = blk;
-  int bc0 = b % cb.NB[0]; b /= cb.NB[0];
-  int bc1 = b % cb.NB[1]; b /= cb.NB[1];
-  int bc2 = b % cb.NB[2];
-  int bc3 = b / cb.NB[2];
+  const int bc0 = b % cb.NB[0]; b /= cb.NB[0];
+  const int bc1 = b % cb.NB[1]; b /= cb.NB[1];
+  const int bc2 = b % cb.NB[2];
+  const int bc3 = b / cb.NB[2];
   int l = sl;
-  lc[0] = l % cb.B[0]; l /= cb.B[0];
-  lc[1] = l % cb.B[1]; l /= cb.B[1];
-  lc[2] = l % cb.B[2];
-  lc[3] = l / cb.B[2];
-  c[0] = bc0 * cb.B[0] + lc[0];
-  c[1] = bc1 * cb.B[1] + lc[1];
-  c[2] = bc2 * cb.B[2] + lc[2];
-  c[3] = bc3 * cb.B[3] + lc[3];
+  lc.x = l % cb.B[0]; l /= cb.B[0];
+  lc.y = l % cb.B[1]; l /= cb.B[1];
+  lc.z = l % cb.B[2];
+  lc.t = l / cb.B[2];
+  c.x = bc0 * cb.B[0] + lc.x;
+  c.y = bc1 * cb.B[1] + lc.y;
+  c.z = bc2 * cb.B[2] + lc.z;
+  c.t = bc3 * cb.B[3] + lc.t;
 }
 // local index of the neighbour inside the block, or -1 when it lies outside
-TM_D int cblock_nbr_local(const CBlock& cb, const int lc[4], int mu, int step) {
-  int l2[4] = {lc[0], lc[1], lc[2], lc[3]};
-  int v = l2[mu] + step;
-  if (v < 0 || v >= cb.B[mu]) {
-    if (cb.NB[mu] != 1) return -1;
-    v = (v + cb.B[mu]) % cb.B[mu];
+TM_D int cblock_nbr_local(const CBlock& cb, C4 lc, int mu, int step) {
+  const int Bm = i4_get(cb.B, mu), NBm = i4_get(cb.NB, mu);
+  int v = c4_get(lc, mu) + step;
+  if (v < 0 || v >= Bm) {
+    if (NBm != 1) return -1;
+    v = v < 0 ? v + Bm : v - Bm;
   }
-  l2[mu] = v;
-  return ((l2[3] * cb.B[2] + l2[2]) * cb.B[1] + l2[1]) * cb.B[0] + l2[0];
+  C4 l2 = lc;
+  l2.x = mu == 0 ? v : lc.x;
+  l2.y = mu == 1 ? v : lc.y;
+  l2.z = mu == 2 ? v : lc.z;
+  l2.t = mu == 3 ? v : lc.t;
+  return ((l2.t * cb.B[2] + l2.z) * cb.B[1] + l2.y) * cb.B[0] + l2.x;
 }
 
 template <typename T>
@@ -139,13 +185,13 @@ __global__ void __launch_bounds__(256) k_sap_coarse(CoarseGeom g, int d, CBlock 
     e[k] = mk<T>(0, 0);
     if (el < nel) {
       int sl = el / d, i = el - sl * d;
-      int c[4], lc[4];
+      C4 c, lc;
       cblock_site(g, cb, blk, sl, c, lc);
-      long y = coarse_index(g, c);
+      long y = cc_index(g, c);
       const SP<S>* D = Dc + y * 9L * d * d + i;
       cplx<T> acc = mk<T>(0, 0);
       for (int b = 0; b < 9; ++b) {
-        long src = b == 0 ? y : coarse_neighbour(g, c, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
+        long src = b == 0 ? y : cc_nbr(g, c, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
         const cplx<T>* v = zr + src * d;
         const SP<S>* Db = D + (long)b * d * d;
         for (int j = 0; j < d; ++j) cfma(acc, Store<S>::template ld<T>(Db + (long)j * d), v[j]);
@@ -169,9 +215,9 @@ __global__ void __launch_bounds__(256) k_sap_coarse(CoarseGeom g, int d, CBlock 
       q[k] = mk<T>(0, 0);
       if (el < nel) {
         int sl = el / d, i = el - sl * d;
-        int c[4], lc[4];
+        C4 c, lc;
         cblock_site(g, cb, blk, sl, c, lc);
-        long y = coarse_index(g, c);
+        long y = cc_index(g, c);
         const SP<S>* D = Dc + y * 9L * d * d + i;
         cplx<T> acc = mk<T>(0, 0);
         for (int b = 0; b < 9; ++b) {
@@ -202,10 +248,105 @@ __global__ void __launch_bounds__(256) k_sap_coarse(CoarseGeom g, int d, CBlock 
     int el = threadIdx.x + k * 256;
     if (el < nel) {
       int sl = el / d, i = el - sl * d;
-      int c[4], lc[4];
+      C4 c, lc;
       cblock_site(g, cb, blk, sl, c, lc);
-      long y = coarse_index(g, c);
+      long y = cc_index(g, c);
       zr[y * d + i] += e[k];
+    }
+  }
+}
+
+// Same block solve with the dof count fixed at compile time: 512 threads,
+// up to 8 rows per thread, inner products partially unrolled.  The block
+// correction is added to z after every MR step (z of a block is read only
+// when its residual is formed, before the first step).
+template <typename T, typename S, int D>
+__global__ void __launch_bounds__(512) k_sap_coarse_d(CoarseGeom g, CBlock cb, const SP<S>* __restrict__ Dc,
+                                                      const cplx<T>* __restrict__ eta, cplx<T>* z,
+                                                      const double* __restrict__ mu_dev, const int* __restrict__ blist,
+                                                      int mr_steps) {
+  constexpr int EPT = 8;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int nel = cb.nbs * D;
+  T* red = reinterpret_cast<T*>(lds + nel);
+  const int r = blockIdx.y;
+  const int blk = blist[blockIdx.x];
+  const T mu = (T)mu_dev[r];
+  const cplx<T>* er = eta + (long)r * g.V * D;
+  cplx<T>* zr = z + (long)r * g.V * D;
+  cplx<T> rho[EPT], q[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int el = threadIdx.x + k * 512;
+    rho[k] = mk<T>(0, 0);
+    if (el < nel) {
+      const int sl = el / D, i = el - sl * D;
+      C4 c, lc;
+      cblock_site(g, cb, blk, sl, c, lc);
+      const long y = cc_index(g, c);
+      const SP<S>* Dm = Dc + y * 9L * D * D + i;
+      cplx<T> acc = mk<T>(0, 0);
+      for (int b = 0; b < 9; ++b) {
+        long src = b == 0 ? y : cc_nbr(g, c, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
+        const cplx<T>* v = zr + src * D;
+        const SP<S>* Db = Dm + (long)b * D * D;
+#pragma unroll 8
+        for (int j = 0; j < D; ++j) cfma(acc, Store<S>::template ld<T>(Db + j * D), v[j]);
+      }
+      acc += (i < D / 2 ? mu : -mu) * times_i(zr[y * D + i]);
+      rho[k] = er[y * D + i] - acc;
+    }
+  }
+  __syncthreads();   // every residual is formed before z changes
+  for (int it = 0; it < mr_steps; ++it) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int el = threadIdx.x + k * 512;
+      if (el < nel) lds[el] = rho[k];
+    }
+    __syncthreads();
+    T qq = 0, qre = 0, qim = 0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int el = threadIdx.x + k * 512;
+      q[k] = mk<T>(0, 0);
+      if (el < nel) {
+        const int sl = el / D, i = el - sl * D;
+        C4 c, lc;
+        cblock_site(g, cb, blk, sl, c, lc);
+        const long y = cc_index(g, c);
+        const SP<S>* Dm = Dc + y * 9L * D * D + i;
+        cplx<T> acc = mk<T>(0, 0);
+        for (int b = 0; b < 9; ++b) {
+          const int nl = b == 0 ? sl : cblock_nbr_local(cb, lc, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
+          if (nl < 0) continue;
+          const cplx<T>* v = lds + nl * D;
+          const SP<S>* Db = Dm + (long)b * D * D;
+#pragma unroll 8
+          for (int j = 0; j < D; ++j) cfma(acc, Store<S>::template ld<T>(Db + j * D), v[j]);
+        }
+        acc += (i < D / 2 ? mu : -mu) * times_i(rho[k]);
+        q[k] = acc;
+        qq += norm2(acc);
+        cplx<T> t = cmulc(acc, rho[k]);
+        qre += t.re;
+        qim += t.im;
+      }
+    }
+    block_reduce3c(qq, qre, qim, red);
+    const cplx<T> alpha = qq > (T)0 ? mk(qre / qq, qim / qq) : mk<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int el = threadIdx.x + k * 512;
+      if (el < nel) {
+        const int sl = el / D, i = el - sl * D;
+        C4 c, lc;
+        cblock_site(g, cb, blk, sl, c, lc);
+        const long y = cc_index(g, c);
+        cfma(zr[y * D + i], alpha, rho[k]);
+      }
+      rho[k] -= alpha * q[k];
     }
   }
 }
@@ -219,6 +360,18 @@ void launch_sap_coarse(const CoarseGeom& g, int d, const int blk[4], const SP<S>
   int nel = cb.nbs * d;
   size_t sh = (size_t)nel * sizeof(cplx<T>) + 3 * 4 * sizeof(T);
   dim3 grid(nblk, nrhs);
+  if (nel <= 8 * 512 && (d == 24 || d == 32 || d == 48 || d == 64)) {
+    size_t sh2 = (size_t)nel * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
+    if (d == 24)
+      hipLaunchKernelGGL((k_sap_coarse_d<T, S, 24>), grid, dim3(512), sh2, st, g, cb, Dc, eta, z, mu_dev, blist, mr_steps);
+    else if (d == 32)
+      hipLaunchKernelGGL((k_sap_coarse_d<T, S, 32>), grid, dim3(512), sh2, st, g, cb, Dc, eta, z, mu_dev, blist, mr_steps);
+    else if (d == 48)
+      hipLaunchKernelGGL((k_sap_coarse_d<T, S, 48>), grid, dim3(512), sh2, st, g, cb, Dc, eta, z, mu_dev, blist, mr_steps);
+    else
+      hipLaunchKernelGGL((k_sap_coarse_d<T, S, 64>), grid, dim3(512), sh2, st, g, cb, Dc, eta, z, mu_dev, blist, mr_steps);
+    return;
+  }
   if (nel <= 4 * 256)
     hipLaunchKernelGGL((k_sap_coarse<T, S, 4>), grid, dim3(256), sh, st, g, d, cb, Dc, eta, z, mu_dev, blist,
                        mr_steps);

@@ -49,16 +49,29 @@ template <typename T> TM_HD void cfmac(cplx<T>& a, cplx<T> b, cplx<T> c) {
 template <typename T> TM_HD cplx<T> times_i(cplx<T> a) { return mk(-a.im, a.re); }
 template <typename T> TM_HD T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
 
+// Load/store at element i of a wave-uniform base pointer with a 32-bit
+// per-lane offset: the backend then addresses through a scalar base and one
+// 32-bit VGPR instead of a 64-bit VGPR address per access.  Requires
+// i * sizeof(X) < 2^32.
+template <typename X> TM_D X ldu(const X* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + (size_t)(i * (unsigned)sizeof(X)));
+}
+template <typename X> TM_D void stu(X* base, unsigned i, X v) {
+  *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + (size_t)(i * (unsigned)sizeof(X))) = v;
+}
+
 // ------------------------------------------------------------------ storage
 // A complex number stored in precision S and computed with in precision T.
 template <typename S> struct Store;
 template <> struct Store<double> {
   using pair = cplx<double>;
+  template <typename T> TM_D static cplx<T> cvt(pair v) { return mk<T>((T)v.re, (T)v.im); }
   template <typename T> TM_D static cplx<T> ld(const pair* p) { pair v = *p; return mk<T>((T)v.re, (T)v.im); }
   template <typename T> TM_D static void st(pair* p, cplx<T> v) { *p = mk<double>((double)v.re, (double)v.im); }
 };
 template <> struct Store<float> {
   using pair = cplx<float>;
+  template <typename T> TM_D static cplx<T> cvt(pair v) { return mk<T>((T)v.re, (T)v.im); }
   template <typename T> TM_D static cplx<T> ld(const pair* p) { pair v = *p; return mk<T>((T)v.re, (T)v.im); }
   template <typename T> TM_D static void st(pair* p, cplx<T> v) { *p = mk<float>((float)v.re, (float)v.im); }
 };
@@ -66,6 +79,9 @@ struct __align__(4) bf16pair { __hip_bfloat16 re, im; };
 struct __align__(4) halfpair { __half re, im; };
 template <> struct Store<__hip_bfloat16> {
   using pair = bf16pair;
+  template <typename T> TM_D static cplx<T> cvt(pair v) {
+    return mk<T>((T)__bfloat162float(v.re), (T)__bfloat162float(v.im));
+  }
   template <typename T> TM_D static cplx<T> ld(const pair* p) {
     pair v = *p;
     return mk<T>((T)__bfloat162float(v.re), (T)__bfloat162float(v.im));
@@ -79,6 +95,7 @@ template <> struct Store<__hip_bfloat16> {
 };
 template <> struct Store<__half> {
   using pair = halfpair;
+  template <typename T> TM_D static cplx<T> cvt(pair v) { return mk<T>((T)__half2float(v.re), (T)__half2float(v.im)); }
   template <typename T> TM_D static cplx<T> ld(const pair* p) {
     pair v = *p;
     return mk<T>((T)__half2float(v.re), (T)__half2float(v.im));
@@ -89,6 +106,12 @@ template <> struct Store<__half> {
     o.im = __float2half((float)v.im);
     *p = o;
   }
+};
+
+// Four consecutive stored complex numbers, loaded with one vector access.
+template <typename S>
+struct __align__(4 * sizeof(typename Store<S>::pair)) Quad {
+  typename Store<S>::pair e[4];
 };
 
 // ------------------------------------------------------------------ fine geometry
@@ -150,6 +173,15 @@ TM_HD long fine_neighbour(const FineGeom& g, long s, const int c[4], int mu, int
   }
 }
 
+// Fine-lattice arrays are tiled: FT consecutive sites (in the block-major
+// order above) form a tile, and a tile stores its NC components one after
+// the other, FT sites each.  Element (s, k) of an NC-component array sits
+// at tsite(s, NC) + k * FT.  A wave then reads one component of 64
+// consecutive sites as contiguous memory, and all components of one site
+// hang off a single address with small immediate offsets.
+constexpr unsigned FT = 32;
+TM_HD size_t tsite(unsigned s, unsigned nc) { return (size_t)(s / FT) * nc * FT + (s % FT); }
+
 // ------------------------------------------------------------------ coarse geometry
 // Coarse lattices are lexicographic (x fastest) and periodic.
 struct CoarseGeom {
@@ -172,6 +204,36 @@ TM_HD long coarse_neighbour(const CoarseGeom& g, const int c[4], int mu, int ste
   cc[mu] = (cc[mu] + step + g.L[mu]) % g.L[mu];
   return coarse_index(g, cc);
 }
+
+// Scalar-coordinate variants (no runtime-indexed private arrays, which the
+// compiler would place in scratch memory).
+struct C4 {
+  int x, y, z, t;
+};
+TM_HD int wrapc(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+TM_HD C4 cc_coords(const CoarseGeom& g, long s) {
+  C4 c;
+  long r = s;
+  c.x = (int)(r % g.L[0]); r /= g.L[0];
+  c.y = (int)(r % g.L[1]); r /= g.L[1];
+  c.z = (int)(r % g.L[2]);
+  c.t = (int)(r / g.L[2]);
+  return c;
+}
+TM_HD long cc_index(const CoarseGeom& g, C4 c) {
+  return ((long)(c.t * g.L[2] + c.z) * g.L[1] + c.y) * g.L[0] + c.x;
+}
+TM_HD C4 cc_shift(const CoarseGeom& g, C4 c, int mu, int step) {
+  C4 o = c;
+  o.x = mu == 0 ? wrapc(c.x + step, g.L[0]) : c.x;
+  o.y = mu == 1 ? wrapc(c.y + step, g.L[1]) : c.y;
+  o.z = mu == 2 ? wrapc(c.z + step, g.L[2]) : c.z;
+  o.t = mu == 3 ? wrapc(c.t + step, g.L[3]) : c.t;
+  return o;
+}
+TM_HD long cc_nbr(const CoarseGeom& g, C4 c, int mu, int step) { return cc_index(g, cc_shift(g, c, mu, step)); }
+TM_HD int c4_get(C4 c, int mu) { return mu == 0 ? c.x : (mu == 1 ? c.y : (mu == 2 ? c.z : c.t)); }
+TM_HD int i4_get(const int* a, int mu) { return mu == 0 ? a[0] : (mu == 1 ? a[1] : (mu == 2 ? a[2] : a[3])); }
 
 // ------------------------------------------------------------------ reductions
 template <typename T> TM_D T wave_sum(T v) {

@@ -7,8 +7,11 @@
 #include <complex>
 #include <cstring>
 #include <vector>
+#include <cstdlib>
 
 using clk = std::chrono::steady_clock;
+
+__global__ void k_fill_double(double* p, double v, int n);
 
 // ------------------------------------------------------------------ Hier: typed hooks
 template <typename T, typename S>
@@ -56,7 +59,8 @@ void Hier<T, S>::test_op(int op, int level, const void* in_, void* out_, int nrh
       need(level == 0 || (level == 1 && nlev >= 3));
       long n = level == 0 ? 12 * c->fg.V : g1.V * d1;
       launch_fill_zero(out, (size_t)nrhs * n * sizeof(cplx<T>), st);
-      sap(level, in, out, nrhs, mu, p.sap_sweeps[level]);
+      if (level == 0) sap(0, in, out, nrhs, mu, p.sap_sweeps[0]);
+      else sap_level1(in, out, nrhs, mu, p.sap_sweeps[1]);
       break;
     }
     case TMAMG_OP_PREC:
@@ -89,6 +93,65 @@ void Hier<T, S>::export_Dc(int level, cplx<double>* out) {
   if (level == 1 && nlev >= 2) launch_store_to64<S>(Dc1.p, out, (long)g1.V * 9 * d1 * d1, c->st);
   else if (level == 2 && nlev >= 3) launch_store_to64<S>(Dc2.p, out, (long)g2.V * 9 * d2 * d2, c->st);
   else throw TmError{TMAMG_EINVAL, "no such coarse level"};
+}
+
+template <typename T, typename S>
+double Hier<T, S>::time_kernel(int kernel, int nrhs, int reps) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  ensure(nrhs);
+  const long n0 = 12 * c->fg.V;
+  auto need = [&](bool ok) { if (!ok) throw TmError{TMAMG_EINVAL, "kernel not available in this hierarchy"}; };
+  DevArr<cplx<T>> a, b;
+  DevArr<double> mu;
+  mu.alloc(nrhs);
+  hipLaunchKernelGGL(k_fill_double, dim3(1), dim3(64), 0, st, mu.p, c->mu, nrhs);
+  switch (kernel) {
+    case TMAMG_K_SAP0: {
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * n0);
+      launch_random<T>(a.p, (long)nrhs * n0, 11, st);
+      launch_fill_zero(b.p, b.bytes(), st);
+      return time_launches(st, reps, [&]() {
+        launch_sap_fine<T>(fop, a.p, b.p, nrhs, mu.p, blist0[0].p, blist0[0].count, p.mr_steps, st);
+      });
+    }
+    case TMAMG_K_RESTRICT0:
+    case TMAMG_K_PROLONG0: {
+      need(nlev >= 2);
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * g1.V * d1);
+      launch_random<T>(a.p, (long)nrhs * n0, 12, st);
+      launch_random<T>(b.p, (long)nrhs * g1.V * d1, 13, st);
+      if (kernel == TMAMG_K_RESTRICT0)
+        return time_launches(st, reps, [&]() { launch_restrict_fine<T, S>(c->fg, P0.p, nv0, a.p, b.p, nrhs, st); });
+      return time_launches(st, reps, [&]() { launch_prolong_fine<T, S>(c->fg, P0.p, nv0, b.p, a.p, nrhs, st); });
+    }
+    case TMAMG_K_DC1:
+    case TMAMG_K_DC2: {
+      int lv = kernel == TMAMG_K_DC1 ? 1 : 2;
+      need(nlev > lv);
+      long n = lv == 1 ? g1.V * d1 : g2.V * d2;
+      a.alloc((size_t)nrhs * n);
+      b.alloc((size_t)nrhs * n);
+      launch_random<T>(a.p, (long)nrhs * n, 14, st);
+      return time_launches(st, reps, [&]() { dc_apply(lv, a.p, b.p, nrhs, mu.p); });
+    }
+    case TMAMG_K_SAP1: {
+      need(nlev >= 3);
+      long n = g1.V * d1;
+      a.alloc((size_t)nrhs * n);
+      b.alloc((size_t)nrhs * n);
+      launch_random<T>(a.p, (long)nrhs * n, 15, st);
+      launch_fill_zero(b.p, b.bytes(), st);
+      return time_launches(st, reps, [&]() {
+        launch_sap_coarse<T, S>(g1, d1, p.sap_block1, Dc1.p, a.p, b.p, nrhs, mu.p, blist1[0].p, blist1[0].count,
+                                p.mr_steps, st);
+      });
+    }
+    default:
+      throw TmError{TMAMG_EINVAL, "unknown kernel id"};
+  }
 }
 
 template struct Hier<double, double>;
@@ -156,6 +219,8 @@ Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s) : lat(l),
     check(nbs * 2 * p.nv[0] <= 4000, "coarse SAP block too large (sites * dof <= 4000)");
   }
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&host_flags), 1024 * sizeof(int), hipHostMallocDefault));
+  const char* tv = getenv("TMAMG_TIMING");
+  timer.on = tv && tv[0] == '1';
 }
 
 Ctx::~Ctx() {
@@ -169,7 +234,8 @@ __global__ void k_unitarity(const cplx<double>* U, long V, double* out) {
   double dev = 0;
   if (s < V) {
     cplx<double> u[3][3];
-    for (int k = 0; k < 9; ++k) u[k / 3][k % 3] = U[((long)mu * 9 + k) * V + s];
+    const cplx<double>* p = U + (size_t)mu * 9 * V + tsite((unsigned)s, 9);
+    for (int k = 0; k < 9; ++k) u[k / 3][k % 3] = p[k * FT];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         cplx<double> a = mk(0.0, 0.0);
@@ -272,6 +338,7 @@ void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
   hier->setup(mu);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
+  timer.report("setup", st);
   have_setup = true;
   t_setup = std::chrono::duration<double>(clk::now() - t0).count();
 }
@@ -350,8 +417,16 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
   FineOp<double> o64 = op64();
   FineOp<float> o32 = mixed ? op32() : FineOp<float>{};
   const double* mu_d = mu_dev.p;
-  OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) { launch_dslash<double>(o64, in, out, nrhs, mu_d, st); };
-  OpFn<float> A32 = [&](const cplx<float>* in, cplx<float>* out) { launch_dslash<float>(o32, in, out, nrhs, mu_d, st); };
+  OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) {
+    hipEvent_t e0 = timer.begin(st);
+    launch_dslash<double>(o64, in, out, nrhs, mu_d, st);
+    timer.end(PhaseTimer::OUTER_OP, e0, st);
+  };
+  OpFn<float> A32 = [&](const cplx<float>* in, cplx<float>* out) {
+    hipEvent_t e0 = timer.begin(st);
+    launch_dslash<float>(o32, in, out, nrhs, mu_d, st);
+    timer.end(PhaseTimer::OUTER_OP, e0, st);
+  };
   OpFn<double> M64 = [&](const cplx<double>* in, cplx<double>* out) { hier->precond_d(in, out, nrhs, mu_d); };
   OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, nrhs, mu_d); };
   const bool use_m = par.nlevels >= 1;
@@ -416,6 +491,7 @@ tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const 
   tmamg_status s = solve_core(nrhs, mu_host, tol, &loc);
   launch_spinor_to_canonical<double>(fg, x64.p, x, nrhs, st);
   HIPCHK(hipStreamSynchronize(st));
+  timer.report("solve", st);
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   loc.status = s;
@@ -560,6 +636,30 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
   if (lout == 0) launch_spinor_to_canonical<double>(fg, o64.p, out, nrhs, st);
   else HIPCHK(hipMemcpyAsync(out, o64.p, nout * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+}
+
+double Ctx::time_kernel(int kernel, int nrhs, int reps) {
+  check(nrhs >= 1 && reps >= 1, "nrhs and reps must be positive");
+  if (!have_links) throw TmError{TMAMG_ESTATE, "timing before setup"};
+  ensure(nrhs);
+  upload_mu(nrhs, nullptr);
+  const long n0 = 12 * fg.V;
+  if (kernel == TMAMG_K_DSLASH64) {
+    launch_random<double>(b64.p, (long)nrhs * n0, 21, st);
+    FineOp<double> o = op64();
+    return time_launches(st, reps, [&]() { launch_dslash<double>(o, b64.p, t64.p, nrhs, mu_dev.p, st); });
+  }
+  if (kernel == TMAMG_K_DSLASH32) {
+    if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
+    DevArr<cplx<float>> a, b;
+    a.alloc((size_t)nrhs * n0);
+    b.alloc((size_t)nrhs * n0);
+    launch_random<float>(a.p, (long)nrhs * n0, 22, st);
+    FineOp<float> o = op32();
+    return time_launches(st, reps, [&]() { launch_dslash<float>(o, a.p, b.p, nrhs, mu_dev.p, st); });
+  }
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "timing before setup"};
+  return hier->time_kernel(kernel, nrhs, reps);
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -722,6 +822,14 @@ tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int*
       *sites = s;
       *dof = 2 * c->par.nv[1];
     } else throw TmError{TMAMG_EINVAL, "no such level"};
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms) {
+  return guarded([&]() {
+    check(ctx != nullptr && avg_ms != nullptr, "null argument");
+    *avg_ms = C(ctx)->time_kernel(kernel, nrhs, reps);
     return TMAMG_OK;
   });
 }

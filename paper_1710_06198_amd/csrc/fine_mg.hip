@@ -21,16 +21,17 @@ __global__ void __launch_bounds__(256) k_restrict_fine(FineGeom g, const SP<S>* 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int no = 2 * nv;
   cplx<T> f[12];
-  const cplx<T>* inr = in + (long)r * 12 * V + s;
+  const size_t ts = tsite((unsigned)s, 12);
+  const cplx<T>* inr = in + (long)r * 12 * V + ts;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) f[k] = inr[(long)k * V];
+  for (int k = 0; k < 12; ++k) f[k] = inr[k * FT];
   for (int i = 0; i < nv; ++i) {
-    const SP<S>* Pi = P + (long)i * 12 * V + s;
+    const SP<S>* Pi = P + (long)i * 12 * V + ts;
     cplx<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cfmac(a0, Store<S>::template ld<T>(Pi + (long)k * V), f[k]);
+    for (int k = 0; k < 6; ++k) cfmac(a0, Store<S>::template ld<T>(Pi + k * FT), f[k]);
 #pragma unroll
-    for (int k = 6; k < 12; ++k) cfmac(a1, Store<S>::template ld<T>(Pi + (long)k * V), f[k]);
+    for (int k = 6; k < 12; ++k) cfmac(a1, Store<S>::template ld<T>(Pi + k * FT), f[k]);
     a0.re = wave_sum(a0.re); a0.im = wave_sum(a0.im);
     a1.re = wave_sum(a1.re); a1.im = wave_sum(a1.im);
     if (lane == 0) { red[w * no + i] = a0; red[w * no + nv + i] = a1; }
@@ -61,20 +62,21 @@ __global__ void __launch_bounds__(256) k_prolong_fine(FineGeom g, const SP<S>* _
   for (int k = threadIdx.x; k < no; k += blockDim.x) e[k] = in[((long)r * g.nblocks + y) * no + k];
   __syncthreads();
   const long s = (long)y * g.bvol + threadIdx.x;
+  const size_t ts = tsite((unsigned)s, 12);
   cplx<T> acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
   for (int i = 0; i < nv; ++i) {
-    const SP<S>* Pi = P + (long)i * 12 * V + s;
+    const SP<S>* Pi = P + (long)i * 12 * V + ts;
     cplx<T> e0 = e[i], e1 = e[nv + i];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cfma(acc[k], Store<S>::template ld<T>(Pi + (long)k * V), e0);
+    for (int k = 0; k < 6; ++k) cfma(acc[k], Store<S>::template ld<T>(Pi + k * FT), e0);
 #pragma unroll
-    for (int k = 6; k < 12; ++k) cfma(acc[k], Store<S>::template ld<T>(Pi + (long)k * V), e1);
+    for (int k = 6; k < 12; ++k) cfma(acc[k], Store<S>::template ld<T>(Pi + k * FT), e1);
   }
-  cplx<T>* o = out + (long)r * 12 * V + s;
+  cplx<T>* o = out + (long)r * 12 * V + ts;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) o[(long)k * V] = acc[k];
+  for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
 }
 template <typename T, typename S>
 void launch_prolong_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<T>* in, cplx<T>* out, int nrhs,
@@ -93,12 +95,12 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
   const long s = (long)y * g.bvol + threadIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const long vs = 12 * V;
-  const long base = s + (long)sc * 6 * V;
+  const size_t base = tsite((unsigned)s, 12) + (size_t)sc * 6 * FT;
   for (int i = 0; i < nv; ++i) {
     cplx<double> x[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      cplx<T> v = tv[(long)i * vs + base + (long)k * V];
+      cplx<T> v = tv[(long)i * vs + base + k * FT];
       x[k] = mk((double)v.re, (double)v.im);
     }
     for (int pass = 0; pass < 2 && i > 0; ++pass) {
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
           cplx<double> p = mk(0.0, 0.0);
           const cplx<double>* q = P64 + (long)(j0 + jj) * vs + base;
 #pragma unroll
-          for (int k = 0; k < 6; ++k) cfmac(p, q[(long)k * V], x[k]);
+          for (int k = 0; k < 6; ++k) cfmac(p, q[k * FT], x[k]);
           p.re = wave_sum(p.re);
           p.im = wave_sum(p.im);
           if (lane == 0) { red[w][2 * jj] = p.re; red[w][2 * jj + 1] = p.im; }
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
           for (int ww = 0; ww < nw; ++ww) cj += mk(red[ww][2 * jj], red[ww][2 * jj + 1]);
           const cplx<double>* q = P64 + (long)(j0 + jj) * vs + base;
 #pragma unroll
-          for (int k = 0; k < 6; ++k) x[k] -= cj * q[(long)k * V];
+          for (int k = 0; k < 6; ++k) x[k] -= cj * q[k * FT];
         }
         __syncthreads();
       }
@@ -137,8 +139,8 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       cplx<double> q = inv * x[k];
-      P64[(long)i * vs + base + (long)k * V] = q;
-      Store<S>::st(P + (long)i * vs + base + (long)k * V, q);
+      P64[(long)i * vs + base + k * FT] = q;
+      Store<S>::st(P + (long)i * vs + base + k * FT, q);
     }
   }
 }
@@ -179,19 +181,19 @@ TM_D void intra_hops(const FineOp<T>& op, const cplx<T>* wl, int sp, long s, int
 }
 
 template <int MU, typename T>
-TM_D bool face_hop(const FineOp<T>& op, int step, long s, const int c[4], const cplx<T>* wx, cplx<T>* v, long& tsite) {
+TM_D bool face_hop(const FineOp<T>& op, int step, long s, const int c[4], const cplx<T>* wx, cplx<T>* v, long& tgt_site) {
   const FineGeom& g = op.g;
   const int lc = c[MU] % g.B[MU];
 #pragma unroll
   for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
   if (step > 0) {
     if (lc != 0) return false;
-    tsite = fine_neighbour(g, s, c, MU, -1);      // x' = x - mu, forward hop at x' pulls w(x)
-    M3<T> u = load_link(op.links, MU, tsite, g.V);
+    tgt_site = fine_neighbour(g, s, c, MU, -1);      // x' = x - mu, forward hop at x' pulls w(x)
+    M3<T> u = load_link(op.links, MU, tgt_site, g.V);
     hop_fwd<MU>(u, wx, v);
   } else {
     if (lc != g.B[MU] - 1) return false;
-    tsite = fine_neighbour(g, s, c, MU, +1);      // x'' = x + mu, backward hop at x'' pulls w(x)
+    tgt_site = fine_neighbour(g, s, c, MU, +1);      // x'' = x + mu, backward hop at x'' pulls w(x)
     M3<T> u = load_link(op.links, MU, s, g.V);
     hop_bwd<MU>(u, wx, v);
   }
@@ -223,7 +225,7 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(FineOp<T> op, const SP<S>
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     bool in_s = (k < 6) == (sp == 0);
-    wx[k] = in_s ? Store<S>::template ld<T>(P + (long)jv * 12 * V + (long)k * V + s) : mk<T>(0, 0);
+    wx[k] = in_s ? Store<S>::template ld<T>(P + (long)jv * 12 * V + tsite((unsigned)s, 12) + k * FT) : mk<T>(0, 0);
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) wl[k * bv + loc] = wx[sp * 6 + k];
@@ -242,8 +244,8 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(FineOp<T> op, const SP<S>
     if (part == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
-      clover_block_mv(op.clover + s, V, wx, v);
-      clover_block_mv(op.clover + 36 * V + s, V, wx + 6, v + 6);
+      clover_block_mv(op.clover, (unsigned)s, V, wx, v);
+      clover_block_mv(op.clover + 36 * V, (unsigned)s, V, wx + 6, v + 6);
       intra_hops<0>(op, wl, sp, s, loc, c, v);
       intra_hops<1>(op, wl, sp, s, loc, c, v);
       intra_hops<2>(op, wl, sp, s, loc, c, v);
@@ -279,12 +281,13 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(FineOp<T> op, const SP<S>
       const int t = threadIdx.x, iv = t % nv, grp = t / nv;
       cplx<T> acc = mk<T>(0, 0);
       if (grp < G) {
-        const SP<S>* Pi = P + (long)iv * 12 * V + (long)sc * 6 * V;
+        const SP<S>* Pi = P + (long)iv * 12 * V + (long)sc * 6 * FT;
         for (int l = grp; l < bv; l += G) {
           long tsl = tgt[l];
           if (tsl < 0) continue;
 #pragma unroll
-          for (int k = 0; k < 6; ++k) cfmac(acc, Store<S>::template ld<T>(Pi + (long)k * V + tsl), u[k * bv + l]);
+          for (int k = 0; k < 6; ++k)
+            cfmac(acc, Store<S>::template ld<T>(Pi + tsite((unsigned)tsl, 12) + k * FT), u[k * bv + l]);
         }
       }
       red[t] = acc;

@@ -22,9 +22,10 @@ __global__ void k_convert_links(FineGeom g, const cplx<double>* __restrict__ can
   long s = fine_index(g, c);
   double sign = (antiperiodic && mu == 3 && c[3] == g.L[3] - 1) ? -1.0 : 1.0;
   const cplx<double>* src = canon + ((long)mu * g.V + cs) * 9;
+  const size_t ob = (size_t)mu * 9 * g.V + tsite((unsigned)s, 9);
   for (int k = 0; k < 9; ++k) {
     cplx<double> v = sign * src[k];
-    long o = ((long)mu * 9 + k) * g.V + s;
+    size_t o = ob + k * FT;
     if (out64) out64[o] = v;
     if (out32) out32[o] = mk<float>((float)v.re, (float)v.im);
   }
@@ -49,8 +50,8 @@ __global__ void k_spinor_to_internal(FineGeom g, const cplx<double>* __restrict_
   c[3] = (int)(r / g.L[2]);
   long s = fine_index(g, c);
   const cplx<double>* src = canon + (rhs * g.V + cs) * 12;
-  cplx<T>* dst = out + rhs * 12 * g.V + s;
-  for (int k = 0; k < 12; ++k) dst[(long)k * g.V] = mk<T>((T)src[k].re, (T)src[k].im);
+  cplx<T>* dst = out + rhs * 12 * g.V + tsite((unsigned)s, 12);
+  for (int k = 0; k < 12; ++k) dst[k * FT] = mk<T>((T)src[k].re, (T)src[k].im);
 }
 
 template <typename T>
@@ -65,10 +66,10 @@ __global__ void k_spinor_to_canonical(FineGeom g, const cplx<T>* __restrict__ in
   c[2] = (int)(r % g.L[2]);
   c[3] = (int)(r / g.L[2]);
   long s = fine_index(g, c);
-  const cplx<T>* src = in + rhs * 12 * g.V + s;
+  const cplx<T>* src = in + rhs * 12 * g.V + tsite((unsigned)s, 12);
   cplx<double>* dst = canon + (rhs * g.V + cs) * 12;
   for (int k = 0; k < 12; ++k) {
-    cplx<T> v = src[(long)k * g.V];
+    cplx<T> v = src[k * FT];
     dst[k] = mk<double>((double)v.re, (double)v.im);
   }
 }
@@ -150,18 +151,18 @@ __global__ void k_clover_build(FineGeom g, const cplx<double>* __restrict__ U, C
           }
     }
   for (int ch = 0; ch < 2; ++ch) {
-    long base = (long)ch * 36;
+    const size_t base = (size_t)ch * 36 * g.V + tsite((unsigned)s, 36);
     for (int i = 0; i < 6; ++i) {
       double v = A[ch][i][i].re;
-      if (clov64) clov64[(base + i) * g.V + s] = v;
-      if (clov32) clov32[(base + i) * g.V + s] = (float)v;
+      if (clov64) clov64[base + i * FT] = v;
+      if (clov32) clov32[base + i * FT] = (float)v;
     }
     for (int i = 0; i < 6; ++i)
       for (int j = i + 1; j < 6; ++j) {
-        long k = base + 6 + 2 * herm_idx(i, j);
+        const size_t k = 6 + 2 * herm_idx(i, j);
         cplx<double> v = A[ch][i][j];
-        if (clov64) { clov64[k * g.V + s] = v.re; clov64[(k + 1) * g.V + s] = v.im; }
-        if (clov32) { clov32[k * g.V + s] = (float)v.re; clov32[(k + 1) * g.V + s] = (float)v.im; }
+        if (clov64) { clov64[base + k * FT] = v.re; clov64[base + (k + 1) * FT] = v.im; }
+        if (clov32) { clov32[base + k * FT] = (float)v.re; clov32[base + (k + 1) * FT] = (float)v.im; }
       }
   }
 }
@@ -173,20 +174,33 @@ void launch_clover_build(const FineGeom& g, const cplx<double>* links64, const C
 }
 
 // ------------------------------------------------------------------ stencil (K1)
+// Compiler-only fence (emits no instruction): memory accesses may not move
+// across it and the accumulator must be fully computed at this point, so
+// each hopping direction's loads and arithmetic stay together.
 template <typename T>
-TM_D void load_spinor(const cplx<T>* __restrict__ f, long s, long V, cplx<T>* p) {
+TM_D void compiler_fence(cplx<T>* acc) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = f[(long)k * V + s];
+  for (int k = 0; k < 12; ++k) __asm__ __volatile__("" : "+v"(acc[k].re), "+v"(acc[k].im));
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// Every access goes through a wave-uniform base (field + component * V) and
+// the lane's 32-bit site index.
+template <typename T>
+TM_D void load_spinor(const cplx<T>* __restrict__ f, unsigned s, long V, cplx<T>* p) {
+  const cplx<T>* q = f + tsite(s, 12);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = q[k * FT];
 }
 
 // acc = (A + i mu g5) psi
 template <typename T>
-TM_D void site_diag(const FineOp<T>& op, long s, T mu, const cplx<T>* psi, cplx<T>* acc) {
+TM_D void site_diag(const FineOp<T>& op, unsigned s, T mu, const cplx<T>* psi, cplx<T>* acc) {
   const long V = op.g.V;
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
-  clover_block_mv(op.clover + s, V, psi, acc);
-  clover_block_mv(op.clover + 36 * V + s, V, psi + 6, acc + 6);
+  clover_block_mv(op.clover, s, V, psi, acc);
+  clover_block_mv(op.clover + 36 * V, s, V, psi + 6, acc + 6);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     acc[k] += mu * times_i(psi[k]);
@@ -195,30 +209,38 @@ TM_D void site_diag(const FineOp<T>& op, long s, T mu, const cplx<T>* psi, cplx<
 }
 
 template <int MU, typename T>
-TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, long s, const int c[4], cplx<T>* acc) {
+TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
+                        cplx<T>* acc) {
   const long V = op.g.V;
   cplx<T> pn[12];
-  long sf = fine_neighbour(op.g, s, c, MU, +1);
+  const unsigned sf = (unsigned)fine_neighbour(op.g, s, c, MU, +1);
   load_spinor(in, sf, V, pn);
-  M3<T> u = load_link(op.links, MU, s, V);
+  M3<T> u = load_link_u<MU>(op.links, s, V);
   hop_fwd<MU>(u, pn, acc);
-  long sb = fine_neighbour(op.g, s, c, MU, -1);
+  compiler_fence(acc);
+  const unsigned sb = (unsigned)fine_neighbour(op.g, s, c, MU, -1);
   load_spinor(in, sb, V, pn);
-  M3<T> ub = load_link(op.links, MU, sb, V);
+  M3<T> ub = load_link_u<MU>(op.links, sb, V);
   hop_bwd<MU>(ub, pn, acc);
 }
 
 // (D(mu) in)(s) for one right-hand side
 template <typename T>
-TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, long s, T mu, cplx<T>* acc) {
+TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc) {
   int c[4];
   fine_coords(op.g, s, c);
   cplx<T> psi[12];
   load_spinor(in, s, op.g.V, psi);
   site_diag(op, s, mu, psi, acc);
+  // one direction at a time: without these compiler fences every
+  // neighbour's loads are hoisted to the top (> 256 live VGPRs, occupancy 1)
+  compiler_fence(acc);
   site_hops_dir<0>(op, in, s, c, acc);
+  compiler_fence(acc);
   site_hops_dir<1>(op, in, s, c, acc);
+  compiler_fence(acc);
   site_hops_dir<2>(op, in, s, c, acc);
+  compiler_fence(acc);
   site_hops_dir<3>(op, in, s, c, acc);
 }
 
@@ -226,15 +248,15 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out, const double* __restrict__ mu_dev) {
   const long V = op.g.V;
-  long s = blockIdx.x * 256L + threadIdx.x;
+  const unsigned s = blockIdx.x * 256u + threadIdx.x;
   if (s >= V) return;
   const int r = blockIdx.y;
   const T mu = (T)mu_dev[r];
   cplx<T> acc[12];
   site_dslash(op, in + (long)r * 12 * V, s, mu, acc);
-  cplx<T>* o = out + (long)r * 12 * V + s;
+  cplx<T>* o = out + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) o[(long)k * V] = acc[k];
+  for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
 }
 
 template <typename T>
@@ -250,13 +272,13 @@ template void launch_dslash<float>(const FineOp<float>&, const cplx<float>*, cpl
 
 template <typename T>
 __global__ void k_gamma5_fine(long V, const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out) {
-  long s = blockIdx.x * 256L + threadIdx.x;
+  unsigned s = blockIdx.x * 256u + threadIdx.x;
   if (s >= V) return;
-  long base = (long)blockIdx.y * 12 * V + s;
+  size_t base = (size_t)blockIdx.y * 12 * V + tsite(s, 12);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    cplx<T> v = in[base + (long)k * V];
-    out[base + (long)k * V] = k < 6 ? v : -v;
+    cplx<T> v = in[base + k * FT];
+    out[base + k * FT] = k < 6 ? v : -v;
   }
 }
 template <typename T>
@@ -274,7 +296,7 @@ template void launch_gamma5_fine<float>(const FineGeom&, const cplx<float>*, cpl
 // then z_B += e.  Blocks of one colour only neighbour blocks of the other
 // colour, so blocks of one launch never read what another writes.
 template <int MU, typename T>
-TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, long s, int loc, const int c[4], cplx<T>* acc) {
+TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, int loc, const int c[4], cplx<T>* acc) {
   const FineGeom& g = op.g;
   const int bv = g.bvol;
   const int lc = c[MU] % g.B[MU];
@@ -287,17 +309,18 @@ TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, long s, int lo
   if (nl >= 0) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
-    M3<T> u = load_link(op.links, MU, s, g.V);
+    M3<T> u = load_link_u<MU>(op.links, (unsigned)s, g.V);
     hop_fwd<MU>(u, pn, acc);
   }
+  compiler_fence(acc);
   nl = -1;
   if (lc > 0) nl = loc - g.lstride[MU];
   else if (whole) nl = loc + (g.B[MU] - 1) * g.lstride[MU];
   if (nl >= 0) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
-    long sb = s - loc + nl;
-    M3<T> ub = load_link(op.links, MU, sb, g.V);
+    const unsigned sb = (unsigned)(s - loc + nl);
+    M3<T> ub = load_link_u<MU>(op.links, sb, g.V);
     hop_bwd<MU>(ub, pn, acc);
   }
 }
@@ -328,7 +351,7 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* _
   const int r = blockIdx.y;
   const T mu = (T)mu_dev[r];
   const int loc = threadIdx.x;
-  const long s = (long)blist[blockIdx.x] * bv + loc;
+  const unsigned s = (unsigned)blist[blockIdx.x] * bv + loc;
   const cplx<T>* zr = z + (long)r * 12 * V;
   int c[4];
   fine_coords(g, s, c);
@@ -336,18 +359,22 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* _
   {
     cplx<T> dz[12];
     site_dslash(op, zr, s, mu, dz);
-    const cplx<T>* er = eta + (long)r * 12 * V + s;
+    const cplx<T>* er = eta + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) { rho[k] = er[(long)k * V] - dz[k]; e[k] = mk<T>(0, 0); }
+    for (int k = 0; k < 12; ++k) { rho[k] = er[k * FT] - dz[k]; e[k] = mk<T>(0, 0); }
   }
   for (int it = 0; it < mr_steps; ++it) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) lds[k * bv + loc] = rho[k];
     __syncthreads();
     site_diag(op, s, mu, rho, q);
+    compiler_fence(q);
     block_hops_dir<0>(op, lds, s, loc, c, q);
+    compiler_fence(q);
     block_hops_dir<1>(op, lds, s, loc, c, q);
+    compiler_fence(q);
     block_hops_dir<2>(op, lds, s, loc, c, q);
+    compiler_fence(q);
     block_hops_dir<3>(op, lds, s, loc, c, q);
     T qq = 0, qr_re = 0, qr_im = 0;
 #pragma unroll
@@ -365,9 +392,9 @@ __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* _
       rho[k] -= alpha * q[k];
     }
   }
-  cplx<T>* zo = z + (long)r * 12 * V + s;
+  cplx<T>* zo = z + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) zo[(long)k * V] += e[k];
+  for (int k = 0; k < 12; ++k) zo[k * FT] += e[k];
 }
 
 template <typename T>

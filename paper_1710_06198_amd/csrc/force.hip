@@ -42,7 +42,8 @@ __global__ void k_force_xi(FineGeom g, SigmaTab sg, double csw, const cplx<doubl
   long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   cplx<double> x[12], y[12];
-  for (int k = 0; k < 12; ++k) { x[k] = X[(long)k * g.V + s]; y[k] = Y[(long)k * g.V + s]; }
+  const size_t ts = tsite((unsigned)s, 12);
+  for (int k = 0; k < 12; ++k) { x[k] = X[ts + k * FT]; y[k] = Y[ts + k * FT]; }
   for (int p = 0; p < 6; ++p) {
     cplx<double> S[3][3];
     for (int i = 0; i < 3; ++i)
@@ -108,11 +109,12 @@ __device__ void hop_lambda(const FineOp<double>& op, const cplx<double>* X, cons
                            cplx<double> L1[3][3], cplx<double> L2[3][3]) {
   const long V = op.g.V;
   cplx<double> yn[12], xz[12], yz[12], xn[12];
+  const size_t tz = tsite((unsigned)z, 12), tp = tsite((unsigned)zp, 12);
   for (int k = 0; k < 12; ++k) {
-    yn[k] = Y[(long)k * V + zp];
-    xz[k] = X[(long)k * V + z];
-    yz[k] = Y[(long)k * V + z];
-    xn[k] = X[(long)k * V + zp];
+    yn[k] = Y[tp + k * FT];
+    xz[k] = X[tz + k * FT];
+    yz[k] = Y[tz + k * FT];
+    xn[k] = X[tp + k * FT];
   }
   // (1 - g) Y(z+l) and (1 + g) Y(z) as full spinors via the chiral projection
   cplx<double> h[6], pm[12], pp[12];

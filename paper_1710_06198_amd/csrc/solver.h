@@ -8,6 +8,7 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 struct TmError {
   tmamg_status st;
@@ -73,6 +74,42 @@ int krylov_cycle(Krylov<T>& K, const OpFn<T>& A, const OpFn<T>* M, const cplx<T>
 
 struct Ctx;
 
+// Phase timing with HIP events on the library stream, enabled by the
+// environment variable TMAMG_TIMING=1; a summary line goes to stderr after
+// each setup and solve.
+struct PhaseTimer {
+  enum { FINE_SAP, FINE_TRANSFER, L1_SOLVE, L1_SAP, COARSEST, OUTER_OP, SETUP_BUILD, NPH };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int ph; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  hipEvent_t begin(hipStream_t st) {
+    if (!on) return nullptr;
+    hipEvent_t a = ev();
+    HIPCHK(hipEventRecord(a, st));
+    return a;
+  }
+  void end(int ph, hipEvent_t a, hipStream_t st) {
+    if (!on) return;
+    hipEvent_t b = ev();
+    HIPCHK(hipEventRecord(b, st));
+    recs.push_back({ph, a, b});
+  }
+  void report(const char* tag, hipStream_t st);
+  ~PhaseTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct HierBase {
   virtual ~HierBase() {}
   virtual void setup(double mu) = 0;
@@ -87,7 +124,9 @@ struct HierBase {
   virtual void test_op(int op, int level, const void* in, void* out, int nrhs, const double* mu) = 0;
   virtual void export_P(int level, cplx<double>* out) = 0;
   virtual void export_Dc(int level, cplx<double>* out) = 0;
+  virtual double time_kernel(int kernel, int nrhs, int reps) = 0;
   long stats_l2 = 0, stats_coarsest = 0;
+  PhaseTimer* timer = nullptr;
 };
 
 template <typename T, typename S>
@@ -105,17 +144,25 @@ struct Hier : HierBase {
   DevArr<cplx<T>> rc1, ec1, rc2, ec2;
   Krylov<T> K1, K2;
   DevArr<double> red_partial, red_out, red_inv, mu_setup;
+  // persistent coarse kernels: SAP residual/product vectors and partial sums,
+  // coarsest-GMRES scalars
+  DevArr<cplx<T>> sap_rho, sap_q;
+  DevArr<double> sap_part, cg_dws;
+  DevArr<int> cg_iws;
   int cap = 0;
+  bool use_coop = true;
 
   explicit Hier(Ctx* c_);
   void build_colours(const int nb[4], DevArr<int> out[2]);
   void ensure(int nrhs) override;
   void dc_apply(int level, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu);
   void sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
+  void sap_level1(const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
   void precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, const double* mu);
   void coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu);
   void normalize(cplx<T>* v, long n, int nrhs);
   void build(int l);
+  void build_inner(int l);
   void galerkin_only(int l);
   void setup(double mu) override;
   void smooth_vectors(int l);
@@ -127,6 +174,7 @@ struct Hier : HierBase {
   void test_op(int op, int level, const void* in, void* out, int nrhs, const double* mu) override;
   void export_P(int level, cplx<double>* out) override;
   void export_Dc(int level, cplx<double>* out) override;
+  double time_kernel(int kernel, int nrhs, int reps) override;
 };
 
 struct Ctx {
@@ -149,6 +197,7 @@ struct Ctx {
   DevArr<cplx<float>> r32, e32;
   DevArr<double> mu_dev, abstol_dev, red_partial, red_out;
   int* host_flags = nullptr;
+  PhaseTimer timer;
   double t_setup = 0;
   int cap = 0;
 
@@ -170,7 +219,26 @@ struct Ctx {
   void force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F);
   void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
   void upload_mu(int nrhs, const double* mu_host);
+  double time_kernel(int kernel, int nrhs, int reps);
 };
+
+// mean milliseconds per call of f over reps calls, HIP events on st
+template <typename F>
+double time_launches(hipStream_t st, int reps, F&& f) {
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  f();   // warm
+  HIPCHK(hipEventRecord(a, st));
+  for (int i = 0; i < reps; ++i) f();
+  HIPCHK(hipEventRecord(b, st));
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
 
 // force kernels (K13-K15)
 void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, const cplx<double>* Y,

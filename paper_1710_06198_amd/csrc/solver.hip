@@ -22,6 +22,24 @@ __global__ void k_fill_double(double* p, double v, int n) {
   if (i < n) p[i] = v;
 }
 
+void PhaseTimer::report(const char* tag, hipStream_t st) {
+  if (!on) return;
+  HIPCHK(hipStreamSynchronize(st));
+  double t[NPH] = {0};
+  for (const Rec& r : recs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    t[r.ph] += ms;
+  }
+  static const char* names[NPH] = {"fine_sap", "fine_transfer", "level1_solve", "level1_sap", "coarsest",
+                                   "outer_operator", "setup_build"};
+  fprintf(stderr, "[tmamg timing] %s", tag);
+  for (int i = 0; i < NPH; ++i) fprintf(stderr, " %s=%.2fms", names[i], t[i]);
+  fprintf(stderr, "\n");
+  recs.clear();
+  used = 0;
+}
+
 // ------------------------------------------------------------------ Krylov driver
 template <typename T>
 void Krylov<T>::ensure(long n_, int m_, int nrhs, bool flex_, hipStream_t st) {
@@ -195,6 +213,18 @@ void Hier<T, S>::ensure(int nrhs) {
     ec2.alloc((size_t)cap * g2.V * d2);
     tmp1.alloc((size_t)cap * g1.V * d1);
     K2.ensure(g2.V * d2, p.coarsest_iters, cap, false, st);
+    sap_rho.alloc((size_t)cap * g1.V * d1);
+    sap_q.alloc((size_t)cap * g1.V * d1);
+    sap_part.alloc(3 * (size_t)g1.V * cap);
+  }
+  // coarsest level: persistent GMRES workspace
+  {
+    const CoarseGeom& gc = nlev >= 3 ? g2 : g1;
+    const int dc = nlev >= 3 ? d2 : d1;
+    if (nlev >= 2) {
+      cg_dws.alloc(coarsest_ws_doubles(gc.V * dc, cap, p.coarsest_iters, (int)gc.V));
+      cg_iws.alloc(2 * (size_t)cap);
+    }
   }
 }
 
@@ -220,25 +250,51 @@ void Hier<T, S>::sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const 
     }
 }
 
+// Coarse-level SAP: one persistent cooperative launch for all sweeps when
+// the shape is covered, else one launch per colour and sweep.
+template <typename T, typename S>
+void Hier<T, S>::sap_level1(const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps) {
+  const tmamg_params& p = c->par;
+  if (use_coop && sweeps > 0 &&
+      launch_sap_coarse_coop<T, S>(g1, d1, p.sap_block1, Dc1.p, eta, z, nrhs, mu, blist1[0].p, blist1[0].count,
+                                   blist1[1].p, blist1[1].count, sweeps, p.mr_steps, sap_rho.p, sap_q.p, sap_part.p,
+                                   (long)sap_part.n, c->st))
+    return;
+  sap(1, eta, z, nrhs, mu, sweeps);
+}
+
 // Eq. (1): z = P D_c^-1 P^dag v (approximately), then k SAP sweeps on D z = v.
 template <typename T, typename S>
 void Hier<T, S>::precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, const double* mu) {
   const tmamg_params& p = c->par;
   hipStream_t st = c->st;
+  PhaseTimer& tmr = c->timer;
   if (level == 0) {
     if (nlev == 1) {
       launch_fill_zero(z, (size_t)nrhs * 12 * c->fg.V * sizeof(cplx<T>), st);
     } else {
+      hipEvent_t e0 = tmr.begin(st);
       launch_restrict_fine<T, S>(c->fg, P0.p, nv0, v, rc1.p, nrhs, st);
+      tmr.end(PhaseTimer::FINE_TRANSFER, e0, st);
+      e0 = tmr.begin(st);
       coarse_solve(1, rc1.p, ec1.p, nrhs, mu);
+      tmr.end(PhaseTimer::L1_SOLVE, e0, st);
+      e0 = tmr.begin(st);
       launch_prolong_fine<T, S>(c->fg, P0.p, nv0, ec1.p, z, nrhs, st);
+      tmr.end(PhaseTimer::FINE_TRANSFER, e0, st);
     }
+    hipEvent_t e1 = tmr.begin(st);
     sap(0, v, z, nrhs, mu, p.sap_sweeps[0]);
+    tmr.end(PhaseTimer::FINE_SAP, e1, st);
   } else {
     launch_restrict_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, v, rc2.p, nrhs, st);
+    hipEvent_t e0 = tmr.begin(st);
     coarse_solve(2, rc2.p, ec2.p, nrhs, mu);
+    tmr.end(PhaseTimer::COARSEST, e0, st);
     launch_prolong_coarse<T, S>(g1, d1, p.agg[1], P1.p, nv1, ec2.p, z, nrhs, st);
-    sap(1, v, z, nrhs, mu, p.sap_sweeps[1]);
+    e0 = tmr.begin(st);
+    sap_level1(v, z, nrhs, mu, p.sap_sweeps[1]);
+    tmr.end(PhaseTimer::L1_SAP, e0, st);
   }
 }
 
@@ -251,6 +307,12 @@ void Hier<T, S>::coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int n
   Krylov<T>& K = level == 1 ? K1 : K2;
   OpFn<T> A = [this, level, nrhs, mu](const cplx<T>* in, cplx<T>* out) { dc_apply(level, in, out, nrhs, mu); };
   if (level == nlev - 1) {
+    const CoarseGeom& gc = level == 1 ? g1 : g2;
+    const int dc = level == 1 ? d1 : d2;
+    const SPair* Dc = level == 1 ? Dc1.p : Dc2.p;
+    if (use_coop && launch_coarsest_gmres<T, S>(gc, dc, Dc, rhs, sol, nrhs, mu, p.coarsest_iters, p.coarsest_tol,
+                                                K.V.p, K.w.p, cg_dws.p, cg_dws.n, cg_iws.p, st))
+      return;
     int it = krylov_cycle<T>(K, A, nullptr, rhs, sol, nrhs, p.coarsest_iters, p.coarsest_tol, nullptr, false,
                              nullptr, st);
     stats_coarsest += it;
@@ -273,6 +335,15 @@ void Hier<T, S>::normalize(cplx<T>* v, long n, int nrhs) {
 
 template <typename T, typename S>
 void Hier<T, S>::build(int l) {
+  hipStream_t st = c->st;
+  const tmamg_params& p = c->par;
+  hipEvent_t e0 = c->timer.begin(st);
+  build_inner(l);
+  c->timer.end(PhaseTimer::SETUP_BUILD, e0, st);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::build_inner(int l) {
   hipStream_t st = c->st;
   const tmamg_params& p = c->par;
   if (l == 0) {
@@ -338,7 +409,8 @@ void Hier<T, S>::smooth_vectors(int l) {
   cplx<T>* w = l == 0 ? tvtmp.p : tmp1.p;
   for (int k = 0; k < p.init_smooth; ++k) {
     launch_fill_zero(w, (size_t)nv * n * sizeof(cplx<T>), st);
-    sap(l, v, w, nv, mu_setup.p, p.sap_sweeps[l]);
+    if (l == 0) sap(0, v, w, nv, mu_setup.p, p.sap_sweeps[0]);
+    else sap_level1(v, w, nv, mu_setup.p, p.sap_sweeps[1]);
     HIPCHK(hipMemcpyAsync(v, w, (size_t)nv * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
     normalize(v, n, nv);
   }

@@ -67,13 +67,18 @@ template <typename T> TM_HD M3<T> m3_add(const M3<T>& a, const M3<T>& b) {
   return r;
 }
 
+// U_mu(s): links are four tiled 9-component arrays, one per direction.
 template <typename T>
 TM_D M3<T> load_link(const cplx<T>* __restrict__ links, int mu, long s, long V) {
   M3<T> u;
-  const cplx<T>* p = links + (long)mu * 9 * V + s;
+  const cplx<T>* p = links + (size_t)mu * 9 * V + tsite((unsigned)s, 9);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) u.e[k / 3][k % 3] = p[(long)k * V];
+  for (int k = 0; k < 9; ++k) u.e[k / 3][k % 3] = p[k * FT];
   return u;
+}
+template <int MU, typename T>
+TM_D M3<T> load_link_u(const cplx<T>* __restrict__ links, unsigned s, long V) {
+  return load_link(links, MU, s, V);
 }
 
 // w = U h (colour), h a colour vector
@@ -162,26 +167,27 @@ template <int MU, typename T> TM_D void hop_bwd(const M3<T>& u, const cplx<T>* p
 // Packed Hermitian 6x6: 6 real diagonal, then upper (i<j) row-major, 15 complex.
 TM_HD int herm_idx(int i, int j) { return i * 6 - i * (i + 1) / 2 + (j - i - 1); }
 
-// acc[0..5] += A v[0..5] with A packed at cl[k*V], k = 0..35
+// acc[0..5] += A v[0..5]; cl is one chirality's tiled 36-component array
 template <typename T>
-TM_D void clover_block_mv(const T* __restrict__ cl, long V, const cplx<T>* v, cplx<T>* acc) {
+TM_D void clover_block_mv(const T* __restrict__ cl, unsigned s, long V, const cplx<T>* v, cplx<T>* acc) {
   T a[36];
+  const T* p = cl + tsite(s, 36);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) a[k] = cl[(long)k * V];
+  for (int k = 0; k < 36; ++k) a[k] = p[k * FT];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    cplx<T> s = a[i] * v[i];
+    cplx<T> row = a[i] * v[i];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       if (j == i) continue;
       if (j > i) {
         int k = 6 + 2 * herm_idx(i, j);
-        cfma(s, mk(a[k], a[k + 1]), v[j]);
+        cfma(row, mk(a[k], a[k + 1]), v[j]);
       } else {
         int k = 6 + 2 * herm_idx(j, i);
-        cfma(s, mk(a[k], -a[k + 1]), v[j]);
+        cfma(row, mk(a[k], -a[k + 1]), v[j]);
       }
     }
-    acc[i] += s;
+    acc[i] += row;
   }
 }

@@ -235,3 +235,65 @@ def test_solve_shifted(c1):
         xr = field(x.cpu()[r])
         lhs = op.apply(op.apply_dag(xr, w.mu), w.mu) + sig[r] * xr
         assert norm(lhs - field(b[r])) / norm(field(b[r])) < 1e-8
+
+
+@pytest.fixture(scope="module")
+def injected_three_level():
+    """3-level hierarchy from injected test vectors on both coarsenings."""
+    dims = (8, 8, 8, 16)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1235)
+    op = WilsonClover(U, m0, 1.6)
+    nv = (12, 16)
+    agg = ((4, 4, 4, 4), (2, 2, 2, 2))
+    sap1 = (1, 1, 1, 2)
+    p = tm.default_params(nlevels=3, agg=agg, nv=nv, sap_block1=sap1, coarsest_iters=50, setup_iters=0,
+                          init_smooth=0)
+    s = tm.Solver(dims, p)
+    tv0, tv0d = spinors(dims, 7001, nv[0])
+    s.set_test_vectors(0, tv0d)
+    P0 = mg.build_prolongation(field(tv0), agg[0], dims, 12)
+    Dc1 = mg.galerkin(op, P0)
+    tv1 = mg.random_test_vectors(P0.coarse_dims, 2 * nv[0], nv[1], 7002)
+    Vc1, d1 = 2 * 2 * 2 * 4, 2 * nv[0]
+    s.set_test_vectors(1, to_dev(tv1.reshape(nv[1], Vc1, d1).numpy()))
+    s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+    P1 = mg.build_prolongation(tv1, agg[1], P0.coarse_dims, d1)
+    Dc2 = mg.galerkin(Dc1, P1)
+    return s, op, P0, Dc1, P1, Dc2, sap1
+
+
+def test_second_coarsening_parity(injected_three_level):
+    s, op, P0, Dc1, P1, Dc2, sap1 = injected_three_level
+    say("3-level P / D_c parity")
+    Vc2, d2 = s.level_info(2)
+    D = torch.empty((Vc2, 9, d2, d2), dtype=torch.complex128, device=DEV)
+    s.export(1, 2, D)
+    D = D.cpu().transpose(-1, -2)
+    assert rel(D[:, 0], Dc2.S.reshape(-1, d2, d2)) < 1e-12
+    for m in range(4):
+        assert rel(D[:, 1 + 2 * m], Dc2.F[m].reshape(-1, d2, d2)) < 1e-12
+        assert rel(D[:, 2 + 2 * m], Dc2.B[m].reshape(-1, d2, d2)) < 1e-12
+
+
+def test_coarse_sap_and_cycle(injected_three_level):
+    s, op, P0, Dc1, P1, Dc2, sap1 = injected_three_level
+    say("coarse SAP / level-1 cycle parity")
+    Vc1, d1 = s.level_info(1)
+    cd = P0.coarse_dims
+    v = mg.random_test_vectors(cd, d1, 2, 7003)
+    vd = to_dev(v.reshape(2, Vc1, d1).numpy())
+    out = torch.empty_like(vd)
+    mus = [0.003, -0.05]
+    s.apply(tm.OP_SAP, 1, vd, out, mus)
+    for r in range(2):
+        ref = mg.sap(Dc1, v[r], torch.zeros_like(v[r]), mus[r], sap1, 2, 4)
+        assert rel(out.cpu()[r], ref.reshape(Vc1, d1)) < 1e-11
+    s.apply(tm.OP_PREC, 1, vd, out, mus)
+    p = mg.MGParams(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16),
+                    sap_block=((4, 4, 4, 4), sap1), coarsest_maxiter=50)
+    H = mg.Hierarchy(op, p, 0.003)
+    lvl1 = mg.Level(Dc1, 1, P=P1, nxt=mg.Level(Dc2, 2))
+    for r in range(2):
+        ref = H.precondition(lvl1, v[r], mus[r])
+        assert rel(out.cpu()[r], ref.reshape(Vc1, d1)) < 1e-9
