@@ -149,7 +149,9 @@ enum {
   TMAMG_OP_RESTRICT = 3,  /* level -> level+1: out = P^dag in */
   TMAMG_OP_DC = 4,        /* coarse D_c(mu) on level 1 or 2 */
   TMAMG_OP_SAP = 5,       /* k SAP sweeps from zero on level 0 or 1: out ~ D^-1 in */
-  TMAMG_OP_PREC = 6       /* one multigrid cycle B_MG on level 0 or 1 */
+  TMAMG_OP_PREC = 6,      /* one multigrid cycle B_MG on level 0 or 1 */
+  TMAMG_OP_COARSEST = 7   /* coarsest-level GMRES from zero (coarsest_iters, coarsest_tol) on
+                             level nlevels-1: out ~ D_c^-1 in */
 };
 tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
                          const double* mu_rhs);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtmamg.so")
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16 = 0, 1, 2, 3
-OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC = range(7)
+OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST = range(8)
 
 EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",

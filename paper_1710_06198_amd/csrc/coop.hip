@@ -1,22 +1,25 @@
-// Persistent cooperative kernels for the coarse levels.
+// Coarse-level SAP and the coarsest-level GMRES, organised around one
+// coarse site per workgroup.
 //
 // Coarse lattices are small (a few hundred to a few thousand sites), so a
-// launch per Krylov or MR step leaves the GPU idle and a thread per matrix
-// row is latency-bound.  These kernels run a whole coarse-level SAP smoother
-// or a whole coarsest-level GMRES in one cooperative launch.  The unit of
-// work is one coarse site (for one right-hand side): a 256-thread workgroup
-// stages the nine input vectors the site needs in LDS and forms the D rows
-// of D_c with every thread owning four consecutive rows and a slice of the
+// thread per matrix row is latency-bound.  Here a 256-thread workgroup
+// stages the nine input vectors a site needs in LDS and forms the D rows of
+// D_c with every thread owning four consecutive rows and a slice of the
 // 9*D-term sum (one 4-wide vector load per term), followed by an LDS
-// reduction over the slices.  Global information (MR alphas, Gram-Schmidt
-// coefficients, norms) is combined with wave-parallel reductions between
-// grid barriers.  Every loop containing a barrier has a trip count that all
-// workgroups evaluate identically.
-#include <hip/hip_cooperative_groups.h>
+// reduction over the slices.
+//
+// Global synchronisation is priced by what it costs on a chip of 8 XCDs: a
+// grid-wide barrier over a thousand workgroups costs tens of microseconds,
+// a kernel boundary about two and a half.  The SAP smoother therefore uses
+// plain launches, one per minimal-residual step, with the update of step k
+// folded into the staging of step k+1.  The coarsest GMRES runs as one
+// persistent launch on at most a few dozen workgroups that synchronise
+// through a counter barrier; each workgroup reduces the per-workgroup
+// partial sums itself, in a fixed order, so all of them hold identical
+// Gram-Schmidt coefficients without a separate reduction phase.
+#include <type_traits>
 
 #include "kernels.h"
-
-namespace cg = cooperative_groups;
 
 template <typename S> using SP = typename Store<S>::pair;
 
@@ -40,6 +43,7 @@ TM_D void cblk_site(const CBlk& cb, int blk, int sl, C4& c, C4& lc) {
   c.z = bc2 * cb.B[2] + lc.z;
   c.t = bc3 * cb.B[3] + lc.t;
 }
+// in-block neighbour (local index) or -1 when the hop leaves the block
 TM_D int cblk_nbr(const CBlk& cb, C4 lc, int mu, int step) {
   const int Bm = i4_get(cb.B, mu), NBm = i4_get(cb.NB, mu);
   int v = c4_get(lc, mu) + step;
@@ -54,13 +58,15 @@ TM_D int cblk_nbr(const CBlk& cb, C4 lc, int mu, int step) {
   l2.t = mu == 3 ? v : lc.t;
   return ((l2.t * cb.B[2] + l2.z) * cb.B[1] + l2.y) * cb.B[0] + l2.x;
 }
+TM_D int hop_mu(int b) { return (b - 1) >> 1; }
+TM_D int hop_step(int b) { return ((b - 1) & 1) ? -1 : 1; }
 
-// Partial products of one site's D rows: red[ks][i] (ks < KS) summed over
-// ks gives sum_{b in mask} sum_j Dm[b][j][i] vst[b*D + j].  Ends with a
-// workgroup barrier.
+// Partial products of one site's D rows: red[ks][i] summed over ks gives
+// sum_{b in mask} sum_j Dm[b][j][i] vst[b*D + j].  Ends with a workgroup
+// barrier.
 template <int D> struct SiteMV {
-  static constexpr int RG = D / 4;        // row groups of 4 rows
-  static constexpr int KS = 256 / RG;     // slices of the 9*D-term sum
+  static constexpr int RG = D / 4;      // row groups of 4 rows
+  static constexpr int KS = 256 / RG;   // slices of the 9*D-term sum
 };
 template <typename T, typename S, int D>
 TM_D void site_mv(const SP<S>* __restrict__ Dm, const cplx<T>* vst, unsigned mask, cplx<T>* red) {
@@ -94,199 +100,260 @@ TM_D cplx<T> site_mv_row(const cplx<T>* red, int i) {
   return s;
 }
 
-// ------------------------------------------------------------------ SAP (whole smoother)
-struct CoopSap {
+// ------------------------------------------------------------------ SAP with fused MR steps
+struct SapArgs {
   CoarseGeom g;
   CBlk cb;
-  const int* bl[2];
-  int nb[2];
-  int sweeps, mr_steps, nrhs;
+  const int* bl;   // blocks of the colour being solved
+  int nrhs;
 };
 
-// k sweeps of SAP on D_c z = eta.  Unit = (block of the colour, site of the
-// block, right-hand side).  Per colour: r = eta - D_c z on every block
-// site; then per MR step q = D_B rho, per-unit partial dot products, a
-// barrier, the block's alpha summed over its sites in a fixed order, and
-// z += alpha rho, rho -= alpha q.
+// unit u -> (block of the colour, site of the block, right-hand side)
+TM_D void sap_unit(const SapArgs& a, int u, int& bi, int& sl, int& r) {
+  r = u % a.nrhs;
+  const int tt = u / a.nrhs;
+  sl = tt % a.cb.nbs;
+  bi = tt / a.cb.nbs;
+}
+
+// MR step size of a block: alpha = (q, rho) / (q, q), summed over the
+// block's sites in a fixed order from per-site partials (q.q, q^H rho).
+template <typename T>
+TM_D void block_alpha(const double* __restrict__ part, int bi, int nbs, int nrhs, int r, cplx<T>* alpha_s) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    double sq = 0, sre = 0, sim = 0;
+    for (int q = t; q < nbs; q += 64) {
+      const long o = 3L * (((long)bi * nbs + q) * nrhs + r);
+      sq += part[o];
+      sre += part[o + 1];
+      sim += part[o + 2];
+    }
+    sq = wave_sum(sq);
+    sre = wave_sum(sre);
+    sim = wave_sum(sim);
+    if (t == 0) *alpha_s = sq > 0 ? mk<T>((T)(sre / sq), (T)(sim / sq)) : mk<T>(0, 0);
+  }
+  __syncthreads();
+}
+
+// rho = eta - D_c(mu) z on the sites of the colour's blocks
 template <typename T, typename S, int D>
-__global__ void __launch_bounds__(256) k_sap_coarse_coop(CoopSap a, const SP<S>* __restrict__ Dc,
-                                                         const cplx<T>* __restrict__ eta, cplx<T>* z, cplx<T>* rho_g,
-                                                         cplx<T>* q_g, double* part, const double* __restrict__ mu_dev) {
-  cg::grid_group grid = cg::this_grid();
+__global__ void __launch_bounds__(256) k_sap1_resid(SapArgs a, const SP<S>* __restrict__ Dc,
+                                                    const cplx<T>* __restrict__ eta, const cplx<T>* __restrict__ z,
+                                                    cplx<T>* __restrict__ rho, const double* __restrict__ mu_dev) {
+  __shared__ cplx<T> vst[9 * D];
+  __shared__ cplx<T> red[SiteMV<D>::KS * D];
+  const CoarseGeom& g = a.g;
+  const long VD = g.V * D;
+  const int t = threadIdx.x;
+  int bi, sl, r;
+  sap_unit(a, blockIdx.x, bi, sl, r);
+  C4 c, lc;
+  cblk_site(a.cb, a.bl[bi], sl, c, lc);
+  const long y = cc_index(g, c);
+  const cplx<T>* zr = z + r * VD;
+  for (int k = t; k < 9 * D; k += 256) {
+    const int b = k / D, j = k - b * D;
+    const long src = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
+    vst[k] = zr[src * D + j];
+  }
+  __syncthreads();
+  site_mv<T, S, D>(Dc + y * 9L * D * D, vst, 0x1FFu, red);
+  if (t < D) {
+    const T mu = (T)mu_dev[r];
+    cplx<T> acc = site_mv_row<T, D>(red, t);
+    acc += (t < D / 2 ? mu : -mu) * times_i(vst[t]);
+    rho[r * VD + y * D + t] = eta[r * VD + y * D + t] - acc;
+  }
+}
+
+// One MR step on every block of the colour.  With first == 0 the previous
+// step is completed on the fly: alpha_prev from part_in, rho = rho_in -
+// alpha_prev q_in for the staged in-block neighbours, z += alpha_prev
+// rho_in on the own site.  Then q = D_B rho, written with rho and the
+// per-site partials of the next alpha.
+template <typename T, typename S, int D>
+__global__ void __launch_bounds__(256) k_sap1_mr(SapArgs a, const SP<S>* __restrict__ Dc, cplx<T>* __restrict__ z,
+                                                 const cplx<T>* __restrict__ rho_in, const cplx<T>* __restrict__ q_in,
+                                                 const double* __restrict__ part_in, cplx<T>* __restrict__ rho_out,
+                                                 cplx<T>* __restrict__ q_out, double* __restrict__ part_out,
+                                                 const double* __restrict__ mu_dev, int first) {
   __shared__ cplx<T> vst[9 * D];
   __shared__ cplx<T> red[SiteMV<D>::KS * D];
   __shared__ cplx<T> alpha_s;
   const CoarseGeom& g = a.g;
   const CBlk& cb = a.cb;
   const long VD = g.V * D;
-  const int nbs = cb.nbs, nrhs = a.nrhs;
   const int t = threadIdx.x;
-  for (int sw = 0; sw < a.sweeps; ++sw) {
-    for (int col = 0; col < 2; ++col) {
-      const int* bl = a.bl[col];
-      const int units = a.nb[col] * nbs * nrhs;
-      // residual
-      for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const int r = u % nrhs, tt = u / nrhs, sl = tt % nbs, bi = tt / nbs;
-        C4 c, lc;
-        cblk_site(cb, bl[bi], sl, c, lc);
-        const long y = cc_index(g, c);
-        const cplx<T>* zr = z + r * VD;
-        for (int k = t; k < 9 * D; k += 256) {
-          const int b = k / D, j = k - b * D;
-          const long src = b == 0 ? y : cc_nbr(g, c, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
-          vst[k] = zr[src * D + j];
-        }
-        __syncthreads();
-        site_mv<T, S, D>(Dc + y * 9L * D * D, vst, 0x1FFu, red);
-        if (t < D) {
-          const T mu = (T)mu_dev[r];
-          cplx<T> acc = site_mv_row<T, D>(red, t);
-          acc += (t < D / 2 ? mu : -mu) * times_i(vst[t]);
-          rho_g[r * VD + y * D + t] = eta[r * VD + y * D + t] - acc;
-        }
-        __syncthreads();
+  int bi, sl, r;
+  sap_unit(a, blockIdx.x, bi, sl, r);
+  const int blk = a.bl[bi];
+  C4 c, lc;
+  cblk_site(cb, blk, sl, c, lc);
+  const long y = cc_index(g, c);
+  if (!first) block_alpha<T>(part_in, bi, cb.nbs, a.nrhs, r, &alpha_s);
+  const cplx<T> alpha = first ? mk<T>(0, 0) : alpha_s;
+  unsigned mask = 1u;
+  for (int b = 1; b < 9; ++b)
+    if (cblk_nbr(cb, lc, hop_mu(b), hop_step(b)) >= 0) mask |= 1u << b;
+  const cplx<T>* rr = rho_in + r * VD;
+  const cplx<T>* qr = q_in + r * VD;
+  for (int k = t; k < 9 * D; k += 256) {
+    const int b = k / D, j = k - b * D;
+    const int nl = b == 0 ? sl : cblk_nbr(cb, lc, hop_mu(b), hop_step(b));
+    cplx<T> v = mk<T>(0, 0);
+    if (nl >= 0) {
+      long src = y;
+      if (b != 0) {
+        C4 cn, lcn;
+        cblk_site(cb, blk, nl, cn, lcn);
+        src = cc_index(g, cn);
       }
-      __threadfence();
-      grid.sync();
-      for (int it = 0; it < a.mr_steps; ++it) {
-        for (int u = blockIdx.x; u < units; u += gridDim.x) {
-          const int r = u % nrhs, tt = u / nrhs, sl = tt % nbs, bi = tt / nbs;
-          const int blk = bl[bi];
-          C4 c, lc;
-          cblk_site(cb, blk, sl, c, lc);
-          const long y = cc_index(g, c);
-          const cplx<T>* rr = rho_g + r * VD;
-          unsigned mask = 1u;
-          for (int b = 1; b < 9; ++b)
-            if (cblk_nbr(cb, lc, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1) >= 0) mask |= 1u << b;
-          for (int k = t; k < 9 * D; k += 256) {
-            const int b = k / D, j = k - b * D;
-            const int nl = b == 0 ? sl : cblk_nbr(cb, lc, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
-            cplx<T> v = mk<T>(0, 0);
-            if (nl >= 0) {
-              C4 cn, lcn;
-              cblk_site(cb, blk, nl, cn, lcn);
-              v = rr[cc_index(g, cn) * D + j];
-            }
-            vst[k] = v;
-          }
-          __syncthreads();
-          site_mv<T, S, D>(Dc + y * 9L * D * D, vst, mask, red);
-          if (t < 64) {
-            T qq = 0, qre = 0, qim = 0;
-            if (t < D) {
-              const T mu = (T)mu_dev[r];
-              const cplx<T> rho = vst[t];
-              cplx<T> acc = site_mv_row<T, D>(red, t);
-              acc += (t < D / 2 ? mu : -mu) * times_i(rho);
-              q_g[r * VD + y * D + t] = acc;
-              qq = norm2(acc);
-              const cplx<T> tq = cmulc(acc, rho);
-              qre = tq.re;
-              qim = tq.im;
-            }
-            qq = wave_sum(qq);
-            qre = wave_sum(qre);
-            qim = wave_sum(qim);
-            if (t == 0) {
-              part[3L * u] = qq;
-              part[3L * u + 1] = qre;
-              part[3L * u + 2] = qim;
-            }
-          }
-          __syncthreads();
-        }
-        __threadfence();
-        grid.sync();
-        for (int u = blockIdx.x; u < units; u += gridDim.x) {
-          const int r = u % nrhs, tt = u / nrhs, sl = tt % nbs, bi = tt / nbs;
-          if (t < 64) {
-            double sq = 0, sre = 0, sim = 0;
-            for (int q = t; q < nbs; q += 64) {
-              const long o = 3L * (((long)bi * nbs + q) * nrhs + r);
-              sq += part[o];
-              sre += part[o + 1];
-              sim += part[o + 2];
-            }
-            sq = wave_sum(sq);
-            sre = wave_sum(sre);
-            sim = wave_sum(sim);
-            if (t == 0) alpha_s = sq > 0 ? mk<T>((T)(sre / sq), (T)(sim / sq)) : mk<T>(0, 0);
-          }
-          __syncthreads();
-          if (t < D) {
-            C4 c, lc;
-            cblk_site(cb, bl[bi], sl, c, lc);
-            const long o = r * VD + cc_index(g, c) * D + t;
-            const cplx<T> alpha = alpha_s;
-            const cplx<T> rho = rho_g[o];
-            cfma(z[o], alpha, rho);
-            rho_g[o] = rho - alpha * q_g[o];
-          }
-          __syncthreads();
-        }
-        __threadfence();
-        grid.sync();
+      v = rr[src * D + j];
+      if (!first) {
+        const cplx<T> qv = qr[src * D + j];
+        v.re -= alpha.re * qv.re - alpha.im * qv.im;
+        v.im -= alpha.re * qv.im + alpha.im * qv.re;
       }
+    }
+    vst[k] = v;
+  }
+  __syncthreads();
+  site_mv<T, S, D>(Dc + y * 9L * D * D, vst, mask, red);
+  if (t < 64) {
+    T qq = 0, qre = 0, qim = 0;
+    if (t < D) {
+      const T mu = (T)mu_dev[r];
+      const cplx<T> rho = vst[t];
+      cplx<T> acc = site_mv_row<T, D>(red, t);
+      acc += (t < D / 2 ? mu : -mu) * times_i(rho);
+      const long o = r * VD + y * D + t;
+      q_out[o] = acc;
+      rho_out[o] = rho;
+      if (!first) cfma(z[o], alpha, rr[y * D + t]);
+      qq = norm2(acc);
+      const cplx<T> tq = cmulc(acc, rho);
+      qre = tq.re;
+      qim = tq.im;
+    }
+    qq = wave_sum(qq);
+    qre = wave_sum(qre);
+    qim = wave_sum(qim);
+    if (t == 0) {
+      const long u = blockIdx.x;
+      part_out[3 * u] = qq;
+      part_out[3 * u + 1] = qre;
+      part_out[3 * u + 2] = qim;
     }
   }
 }
 
-static int max_coresident(const void* kern, int threads, size_t shmem) {
-  int dev = 0, per_cu = 0, ncu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, shmem);
-  return std::max(1, per_cu * ncu);
+// completes the last MR step: z += alpha rho
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_sap1_fin(SapArgs a, cplx<T>* __restrict__ z,
+                                                  const cplx<T>* __restrict__ rho_in,
+                                                  const double* __restrict__ part_in) {
+  __shared__ cplx<T> alpha_s;
+  const CoarseGeom& g = a.g;
+  int bi, sl, r;
+  sap_unit(a, blockIdx.x, bi, sl, r);
+  block_alpha<T>(part_in, bi, a.cb.nbs, a.nrhs, r, &alpha_s);
+  C4 c, lc;
+  cblk_site(a.cb, a.bl[bi], sl, c, lc);
+  const long o = r * g.V * D + cc_index(g, c) * D + threadIdx.x;
+  if (threadIdx.x < D) cfma(z[o], alpha_s, rho_in[o]);
 }
 
 template <typename T, typename S, int D>
-static hipError_t sap_coop_launch(CoopSap a, const SP<S>* Dc, const cplx<T>* eta, cplx<T>* z, cplx<T>* rho_g,
-                                  cplx<T>* q_g, double* part, const double* mu_dev, hipStream_t st) {
-  const void* kern = reinterpret_cast<const void*>(&k_sap_coarse_coop<T, S, D>);
-  static int cap = 0;
-  if (cap == 0) cap = std::min(2048, max_coresident(kern, 256, 0));
-  const int units = std::max(a.nb[0], a.nb[1]) * a.cb.nbs * a.nrhs;
-  dim3 grid(std::max(1, std::min(cap, units)));
-  void* args[] = {&a, (void*)&Dc, (void*)&eta, (void*)&z, (void*)&rho_g, (void*)&q_g, (void*)&part, (void*)&mu_dev};
-  return hipLaunchCooperativeKernel(kern, grid, dim3(256), args, 0, st);
+static void sap_fused(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const cplx<T>* eta, cplx<T>* z, int nrhs,
+                      const double* mu, const int* const bl[2], const int nb[2], int sweeps, int mr,
+                      cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
+  SapArgs a;
+  a.g = g;
+  a.cb = cb;
+  a.nrhs = nrhs;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int col = 0; col < 2; ++col) {
+      const int units = nb[col] * cb.nbs * nrhs;
+      if (units == 0) continue;
+      a.bl = bl[col];
+      // the residual goes to slot 1, the slot step 0 reads
+      hipLaunchKernelGGL((k_sap1_resid<T, S, D>), dim3(units), dim3(256), 0, st, a, Dc, eta, z, rho[1], mu);
+      for (int k = 0; k < mr; ++k) {
+        const int in = (k + 1) & 1, out = k & 1;
+        hipLaunchKernelGGL((k_sap1_mr<T, S, D>), dim3(units), dim3(256), 0, st, a, Dc, z, rho[in], q[in], part[in],
+                           rho[out], q[out], part[out], mu, k == 0 ? 1 : 0);
+      }
+      if (mr > 0) {
+        const int in = (mr - 1) & 1;
+        hipLaunchKernelGGL((k_sap1_fin<T, D>), dim3(units), dim3(256), 0, st, a, z, rho[in], part[in]);
+      }
+    }
 }
 
-// returns false when this shape has no cooperative kernel (caller falls back)
 template <typename T, typename S>
-bool launch_sap_coarse_coop(const CoarseGeom& g, int d, const int blk[4], const SP<S>* Dc, const cplx<T>* eta,
-                            cplx<T>* z, int nrhs, const double* mu_dev, const int* bl0, int n0, const int* bl1, int n1,
-                            int sweeps, int mr_steps, cplx<T>* rho_g, cplx<T>* q_g, double* part, long part_cap,
-                            hipStream_t st) {
+bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const SP<S>* Dc, const cplx<T>* eta,
+                             cplx<T>* z, int nrhs, const double* mu_dev, const int* bl0, int n0, const int* bl1,
+                             int n1, int sweeps, int mr_steps, cplx<T>* const rho[2], cplx<T>* const q[2],
+                             double* const part[2], long part_cap, hipStream_t st) {
   if (!(d == 24 || d == 32 || d == 48 || d == 64)) return false;
-  CoopSap a;
-  a.g = g;
-  a.cb.nbs = 1;
-  for (int m = 0; m < 4; ++m) { a.cb.B[m] = blk[m]; a.cb.NB[m] = g.L[m] / blk[m]; a.cb.nbs *= blk[m]; }
-  a.bl[0] = bl0;
-  a.bl[1] = bl1;
-  a.nb[0] = n0;
-  a.nb[1] = n1;
-  a.sweeps = sweeps;
-  a.mr_steps = mr_steps;
-  a.nrhs = nrhs;
-  if ((long)std::max(n0, n1) * a.cb.nbs * nrhs * 3 > part_cap) return false;
-  hipError_t e;
-  switch (d) {
-    case 24: e = sap_coop_launch<T, S, 24>(a, Dc, eta, z, rho_g, q_g, part, mu_dev, st); break;
-    case 32: e = sap_coop_launch<T, S, 32>(a, Dc, eta, z, rho_g, q_g, part, mu_dev, st); break;
-    case 48: e = sap_coop_launch<T, S, 48>(a, Dc, eta, z, rho_g, q_g, part, mu_dev, st); break;
-    default: e = sap_coop_launch<T, S, 64>(a, Dc, eta, z, rho_g, q_g, part, mu_dev, st); break;
+  CBlk cb;
+  cb.nbs = 1;
+  for (int m = 0; m < 4; ++m) {
+    cb.B[m] = blk[m];
+    cb.NB[m] = g.L[m] / blk[m];
+    cb.nbs *= blk[m];
   }
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
+  const long units = (long)std::max(n0, n1) * cb.nbs * nrhs;
+  if (units * 3 > part_cap || units > (1L << 30)) return false;
+  const int* bl[2] = {bl0, bl1};
+  const int nb[2] = {n0, n1};
+  switch (d) {
+    case 24: sap_fused<T, S, 24>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
+    case 32: sap_fused<T, S, 32>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
+    case 48: sap_fused<T, S, 48>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
+    default: sap_fused<T, S, 64>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
   }
   return true;
 }
 
 // ------------------------------------------------------------------ coarsest GMRES
+// Barrier over the workgroups of a co-resident launch.  The counter only
+// grows within a launch (epoch e waits for e * gridDim.x arrivals); the
+// last workgroup to leave the kernel sets it back to zero for the next
+// launch on the stream.  The wait is bounded: a timeout raises err and
+// lets every wave run to the end.
+TM_D void gbar(unsigned* ctr, unsigned& epoch, int* err) {
+  __syncthreads();
+  ++epoch;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(ctr, 1u);
+    const unsigned target = epoch * gridDim.x;
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins == (1u << 26)) {
+        atomicOr(err, 1);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+TM_D void gbar_exit(unsigned* ctr) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(ctr + 1, 1u) == gridDim.x - 1) {
+      atomicExch(ctr, 0u);
+      atomicExch(ctr + 1, 0u);
+    }
+  }
+}
+
 struct CoopGmres {
   CoarseGeom g;
   int nrhs, m;
@@ -296,62 +363,113 @@ struct CoopGmres {
 struct CoopGmresWs {
   void* V;          // [(m+1)][nrhs][n] cplx<T>
   void* w;          // [nrhs][n]
-  double* part;     // [V][nrhs][m+1] complex: per-site partial sums
-  double* coef;     // [nrhs][m+1] complex: reduced Gram-Schmidt coefficients
-  double* nrm;      // [nrhs]
-  double* H;        // [nrhs][m+1][m] complex
-  double* cs;       // [nrhs][m] complex
+  double* part1;    // [G][nrhs][m+2] complex: per-workgroup partial sums
+  double* part2;    // [G][nrhs][m+2] complex
+  double* R;        // [nrhs][m][m] complex: rotated Hessenberg, column j at [j][.]
+  double* cs;       // [nrhs][m] complex (workgroup 0 only)
   double* sn;       // [nrhs][m]
   double* gv;       // [nrhs][m+1] complex
-  double* y;        // [nrhs][m] complex
   double* tolabs;   // [nrhs]
   int* flags;       // [nrhs]
   int* kdone;       // [nrhs]
+  unsigned* bar;    // [2] barrier counters (zero between launches)
+  int* err;         // [1] barrier timeouts
+  int* stat;        // [2] iterations summed over right-hand sides, launches
 };
 
-// Sum the per-site partials of pair (r, i) over all sites with one wave per
-// pair, pairs spread over every wave of the grid; fixed order, so every run
-// gives the same bits.
-TM_D void reduce_pairs(const double* part, int nsites, int nrhs, int m, int npairs, int ni, double* coef,
-                       double* H, int j, int pass, bool cplx_out, double* nrm) {
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int nw = gridDim.x * (blockDim.x >> 6);
-  for (int q = gw; q < npairs; q += nw) {
-    const int r = q / ni, i = q - r * ni;
+// Partial sums over the workgroup's own sites of conj(V_i) . w for the
+// pairs (r, i), i < ni, plus (with with_norm) |w|^2 in slot ni; waves over
+// pairs, lanes over the D rows, sites in a fixed order.
+template <typename T, int D>
+TM_D void own_dots(const cplx<T>* V, long vs, const cplx<T>* w, long n, int nrhs, int m, int ni, bool with_norm,
+                   const int* flags, int nsites, double* part) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int per = ni + (with_norm ? 1 : 0);
+  for (int q = wv; q < nrhs * per; q += 4) {
+    const int r = q / per, i = q - r * per;
     double sre = 0, sim = 0;
-    for (int u = lane; u < nsites; u += 64) {
-      const long o = 2L * (((long)u * nrhs + r) * (m + 1) + i);
-      sre += part[o];
-      sim += part[o + 1];
-    }
+    if (flags[r] && lane < D)
+      for (int u = blockIdx.x; u < nsites; u += gridDim.x) {
+        const long o = r * n + (long)u * D + lane;
+        const cplx<T> cw = w[o];
+        const cplx<T> av = i < ni ? V[(long)i * vs + o] : cw;
+        sre += (double)av.re * cw.re + (double)av.im * cw.im;
+        sim += (double)av.re * cw.im - (double)av.im * cw.re;
+      }
     sre = wave_sum(sre);
     sim = wave_sum(sim);
     if (lane == 0) {
-      if (cplx_out) {
-        coef[2L * (r * (m + 1) + i)] = sre;
-        coef[2L * (r * (m + 1) + i) + 1] = sim;
-        double* h = H + 2L * ((long)r * (m + 1) * m + (long)i * m + j);
-        if (pass == 0) { h[0] = sre; h[1] = sim; }
-        else { h[0] += sre; h[1] += sim; }
-      } else {
-        nrm[r] = sqrt(sre);
-      }
+      double* p = part + 2L * (((long)blockIdx.x * nrhs + r) * (m + 2) + i);
+      p[0] = sre;
+      p[1] = sim;
     }
   }
+}
+// coef[r][i] = sum over workgroups of part[wg][r][i].  Four lanes share a
+// pair, each summing every fourth workgroup, then combine by two
+// shuffles: a fixed order, so every workgroup gets the same bits.
+TM_D void all_reduce(const double* part, int nrhs, int m, int per, double* coef) {
+  const int np = nrhs * per, sub = threadIdx.x & 3;
+  for (int q0 = 0; q0 < np; q0 += 64) {
+    const int q = q0 + (threadIdx.x >> 2);
+    double sre = 0, sim = 0;
+    if (q < np) {
+      const int r = q / per, i = q - r * per;
+      for (int wg = sub; wg < (int)gridDim.x; wg += 4) {
+        const double* p = part + 2L * (((long)wg * nrhs + r) * (m + 2) + i);
+        sre += p[0];
+        sim += p[1];
+      }
+    }
+    sre += __shfl_xor(sre, 1, 64);
+    sim += __shfl_xor(sim, 1, 64);
+    sre += __shfl_xor(sre, 2, 64);
+    sim += __shfl_xor(sim, 2, 64);
+    if (q < np && sub == 0) {
+      const int r = q / per, i = q - r * per;
+      coef[2 * (r * (m + 2) + i)] = sre;
+      coef[2 * (r * (m + 2) + i) + 1] = sim;
+    }
+  }
+  __syncthreads();
+}
+// w -= V c on the own sites (c from LDS, first ni columns)
+template <typename T, int D>
+TM_D void own_update(const cplx<T>* V, long vs, cplx<T>* w, long n, int nrhs, int m, int ni, const double* coef,
+                     const int* flags, int nsites) {
+  for (int u = blockIdx.x; u < nsites; u += gridDim.x)
+    for (int k = threadIdx.x; k < nrhs * D; k += blockDim.x) {
+      const int r = k / D, i = k - r * D;
+      if (!flags[r]) continue;
+      const long o = r * n + (long)u * D + i;
+      cplx<T> acc = w[o];
+      for (int l = 0; l < ni; ++l)
+        cfma(acc, mk<T>((T)(-coef[2 * (r * (m + 2) + l)]), (T)(-coef[2 * (r * (m + 2) + l) + 1])),
+             V[(long)l * vs + o]);
+      w[o] = acc;
+    }
+}
+// |h_{j+1,j}| from the second pass: |w|^2 - |c2|^2
+TM_D double new_norm(const double* c2r, int j) {
+  double h2 = c2r[2 * (j + 1)];
+  for (int l = 0; l <= j; ++l) h2 -= c2r[2 * l] * c2r[2 * l] + c2r[2 * l + 1] * c2r[2 * l + 1];
+  return h2 > 0 ? sqrt(h2) : 0.0;
 }
 
 // GMRES(m) from x = 0 for D_c(mu_r) x_r = b_r, stopping a right-hand side
 // when its implicit residual <= reltol * ||b_r||.  Classical Gram-Schmidt
-// with one re-orthogonalisation; Givens updates by workgroup 0.
+// with one re-orthogonalisation pass; the norm of the new direction comes
+// from |w|^2 - |c2|^2 after the second pass.  Workgroup 0 applies the
+// Givens rotations; every workgroup solves the small triangular system at
+// the end for its own sites.
 template <typename T, typename S, int D>
 __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>* __restrict__ Dc,
                                                         const cplx<T>* __restrict__ b, cplx<T>* x,
                                                         const double* __restrict__ mu_dev, CoopGmresWs ws) {
-  cg::grid_group grid = cg::this_grid();
   __shared__ cplx<T> vst[9 * D];
   __shared__ cplx<T> red[SiteMV<D>::KS * D];
   __shared__ int any_active;
+  extern __shared__ double coef[];   // c1 [nrhs][m+2], c2 [nrhs][m+2] complex; y reuses c1
   const CoarseGeom& g = a.g;
   const int nrhs = a.nrhs, m = a.m;
   const long n = g.V * D;
@@ -359,39 +477,45 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
   cplx<T>* V = static_cast<cplx<T>*>(ws.V);
   cplx<T>* w = static_cast<cplx<T>*>(ws.w);
   const long vs = (long)nrhs * n;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double* c1 = coef;
+  double* c2 = coef + 2 * nrhs * (m + 2);
+  const int t = threadIdx.x;
+  unsigned epoch = 0;
 
-  // ||b_r||
-  for (int u = blockIdx.x; u < nsites; u += gridDim.x)
-    if (t < 64)
-      for (int r = 0; r < nrhs; ++r) {
-        double s2 = t < D ? (double)norm2(b[r * n + (long)u * D + t]) : 0.0;
-        s2 = wave_sum(s2);
-        if (t == 0) { ws.part[2L * (((long)u * nrhs + r) * (m + 1))] = s2; ws.part[2L * (((long)u * nrhs + r) * (m + 1)) + 1] = 0; }
+  // ||b_r||^2 partials in part1 slot 0
+  {
+    const int lane = t & 63, wv = t >> 6;
+    for (int r = wv; r < nrhs; r += 4) {
+      double s2 = 0;
+      if (lane < D)
+        for (int u = blockIdx.x; u < nsites; u += gridDim.x) s2 += (double)norm2(b[r * n + (long)u * D + lane]);
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        double* p = ws.part1 + 2L * (((long)blockIdx.x * nrhs + r) * (m + 2));
+        p[0] = s2;
+        p[1] = 0;
       }
-  __threadfence();
-  grid.sync();
-  reduce_pairs(ws.part, nsites, nrhs, m, nrhs, 1, nullptr, nullptr, 0, 0, false, ws.nrm);
-  __threadfence();
-  grid.sync();
+    }
+  }
+  gbar(ws.bar, epoch, ws.err);
+  all_reduce(ws.part1, nrhs, m, 1, c1);
   for (int u = blockIdx.x; u < nsites; u += gridDim.x)
     for (int k = t; k < nrhs * D; k += 256) {
       const int r = k / D, i = k - r * D;
-      const double bt = ws.nrm[r];
+      const double bt = sqrt(c1[2 * r * (m + 2)]);
       const long o = r * n + (long)u * D + i;
       V[o] = bt > 0 ? (T)(1.0 / bt) * b[o] : mk<T>(0, 0);
     }
   if (blockIdx.x == 0)
     for (int r = t; r < nrhs; r += 256) {
-      const double bt = ws.nrm[r];
-      for (int i = 0; i <= m; ++i) { ws.gv[2 * (r * (m + 1) + i)] = 0; ws.gv[2 * (r * (m + 1) + i) + 1] = 0; }
+      const double bt = sqrt(c1[2 * r * (m + 2)]);
       ws.gv[2 * r * (m + 1)] = bt;
+      ws.gv[2 * r * (m + 1) + 1] = 0;
       ws.tolabs[r] = a.reltol * bt;
       ws.kdone[r] = 0;
       ws.flags[r] = (bt > 0 && bt < 1e300) ? 1 : 0;
     }
-  __threadfence();
-  grid.sync();
+  gbar(ws.bar, epoch, ws.err);
 
   for (int j = 0; j < m; ++j) {
     if (t == 0) {
@@ -400,9 +524,9 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
       any_active = any;
     }
     __syncthreads();
-    if (!any_active) break;   // identical in every workgroup: flags only change before a barrier
+    if (!any_active) break;   // same in every workgroup: flags change only before a barrier
     const cplx<T>* vj = V + (long)j * vs;
-    // w = D_c(mu) v_j, one site unit at a time
+    // w = D_c(mu) v_j on the own sites
     for (int u = blockIdx.x; u < nsites; u += gridDim.x) {
       const C4 c = cc_coords(g, u);
       for (int r = 0; r < nrhs; ++r) {
@@ -410,7 +534,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
         const cplx<T>* vr = vj + r * n;
         for (int k = t; k < 9 * D; k += 256) {
           const int bb = k / D, jj = k - bb * D;
-          const long src = bb == 0 ? u : cc_nbr(g, c, (bb - 1) >> 1, ((bb - 1) & 1) ? -1 : 1);
+          const long src = bb == 0 ? u : cc_nbr(g, c, hop_mu(bb), hop_step(bb));
           vst[k] = vr[src * D + jj];
         }
         __syncthreads();
@@ -424,94 +548,60 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
         __syncthreads();
       }
     }
-    // two Gram-Schmidt passes: per-site partials, grid reduction, update
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int u = blockIdx.x; u < nsites; u += gridDim.x)
-        for (int q = wv; q < nrhs * (j + 1); q += 4) {
-          const int r = q / (j + 1), i = q - r * (j + 1);
-          double sre = 0, sim = 0;
-          if (ws.flags[r] && lane < D) {
-            const cplx<T> av = V[(long)i * vs + r * n + (long)u * D + lane];
-            const cplx<T> cw = w[r * n + (long)u * D + lane];
-            sre = (double)av.re * cw.re + (double)av.im * cw.im;
-            sim = (double)av.re * cw.im - (double)av.im * cw.re;
-          }
-          sre = wave_sum(sre);
-          sim = wave_sum(sim);
-          if (lane == 0) {
-            const long o = 2L * (((long)u * nrhs + r) * (m + 1) + i);
-            ws.part[o] = sre;
-            ws.part[o + 1] = sim;
-          }
-        }
-      __threadfence();
-      grid.sync();
-      reduce_pairs(ws.part, nsites, nrhs, m, nrhs * (j + 1), j + 1, ws.coef, ws.H, j, pass, true, nullptr);
-      __threadfence();
-      grid.sync();
-      for (int u = blockIdx.x; u < nsites; u += gridDim.x)
-        for (int k = t; k < nrhs * D; k += 256) {
-          const int r = k / D, i = k - r * D;
-          if (!ws.flags[r]) continue;
-          const long o = r * n + (long)u * D + i;
-          cplx<T> acc = w[o];
-          for (int l = 0; l <= j; ++l)
-            cfma(acc, mk<T>((T)(-ws.coef[2L * (r * (m + 1) + l)]), (T)(-ws.coef[2L * (r * (m + 1) + l) + 1])),
-                 V[(long)l * vs + o]);
-          w[o] = acc;
-        }
-      __syncthreads();   // the next phase reads w of this workgroup's sites from other threads
-    }
-    // norm of w
-    for (int u = blockIdx.x; u < nsites; u += gridDim.x)
-      if (t < 64)
-        for (int r = 0; r < nrhs; ++r) {
-          double s2 = (ws.flags[r] && t < D) ? (double)norm2(w[r * n + (long)u * D + t]) : 0.0;
-          s2 = wave_sum(s2);
-          if (t == 0) { ws.part[2L * (((long)u * nrhs + r) * (m + 1))] = s2; ws.part[2L * (((long)u * nrhs + r) * (m + 1)) + 1] = 0; }
-        }
-    __threadfence();
-    grid.sync();
-    reduce_pairs(ws.part, nsites, nrhs, m, nrhs, 1, nullptr, nullptr, 0, 0, false, ws.nrm);
-    __threadfence();
-    grid.sync();
+    // first Gram-Schmidt pass
+    own_dots<T, D>(V, vs, w, n, nrhs, m, j + 1, false, ws.flags, nsites, ws.part1);
+    gbar(ws.bar, epoch, ws.err);
+    all_reduce(ws.part1, nrhs, m, j + 1, c1);
+    own_update<T, D>(V, vs, w, n, nrhs, m, j + 1, c1, ws.flags, nsites);
+    __syncthreads();
+    // second pass, with |w|^2 in slot j + 1
+    own_dots<T, D>(V, vs, w, n, nrhs, m, j + 1, true, ws.flags, nsites, ws.part2);
+    gbar(ws.bar, epoch, ws.err);
+    all_reduce(ws.part2, nrhs, m, j + 2, c2);
+    own_update<T, D>(V, vs, w, n, nrhs, m, j + 1, c2, ws.flags, nsites);
+    __syncthreads();
     cplx<T>* vn = V + (long)(j + 1) * vs;
     for (int u = blockIdx.x; u < nsites; u += gridDim.x)
       for (int k = t; k < nrhs * D; k += 256) {
         const int r = k / D, i = k - r * D;
-        const double hn = ws.nrm[r];
+        if (!ws.flags[r]) continue;
+        const double hn = new_norm(c2 + 2 * r * (m + 2), j);
         const long o = r * n + (long)u * D + i;
         vn[o] = hn > 0 ? (T)(1.0 / hn) * w[o] : mk<T>(0, 0);
       }
-    __syncthreads();
     if (blockIdx.x == 0)
       for (int r = t; r < nrhs; r += 256) {
         if (!ws.flags[r]) continue;
-        double* H = ws.H + 2L * r * (m + 1) * m;
+        double* Rc = ws.R + 2L * ((long)r * m * m + (long)j * m);   // column j
         double* cs = ws.cs + 2L * r * m;
         double* sn = ws.sn + (long)r * m;
         double* gg = ws.gv + 2L * r * (m + 1);
-        const double hn = ws.nrm[r];
+        const double* h1 = c1 + 2 * r * (m + 2);
+        const double* h2 = c2 + 2 * r * (m + 2);
+        const double hn = new_norm(h2, j);
         // previous rotations [[c, s], [-s, conj(c)]] (s real) on column j
-        double ar = H[2 * j], ai = H[2 * j + 1];
+        double ar = h1[0] + h2[0], ai = h1[1] + h2[1];
         for (int i = 0; i < j; ++i) {
-          const double br = H[2 * ((i + 1) * m + j)], bi = H[2 * ((i + 1) * m + j) + 1];
+          const double br = h1[2 * (i + 1)] + h2[2 * (i + 1)], bi = h1[2 * (i + 1) + 1] + h2[2 * (i + 1) + 1];
           const double cr = cs[2 * i], ci = cs[2 * i + 1], s = sn[i];
-          H[2 * (i * m + j)] = cr * ar - ci * ai + s * br;
-          H[2 * (i * m + j) + 1] = cr * ai + ci * ar + s * bi;
+          Rc[2 * i] = cr * ar - ci * ai + s * br;
+          Rc[2 * i + 1] = cr * ai + ci * ar + s * bi;
           const double ur = -s * ar + (cr * br + ci * bi);
           const double ui = -s * ai + (cr * bi - ci * br);
           ar = ur;
           ai = ui;
         }
         const double den = sqrt(ar * ar + ai * ai + hn * hn);
-        if (!(den > 0) || den != den) { ws.flags[r] = 0; continue; }
+        if (!(den > 0) || den != den) {
+          ws.flags[r] = 0;
+          continue;
+        }
         const double cr = ar / den, ci = -ai / den, s = hn / den;
         cs[2 * j] = cr;
         cs[2 * j + 1] = ci;
         sn[j] = s;
-        H[2 * (j * m + j)] = den;
-        H[2 * (j * m + j) + 1] = 0;
+        Rc[2 * j] = den;
+        Rc[2 * j + 1] = 0;
         const double gr = gg[2 * j], gi = gg[2 * j + 1];
         gg[2 * (j + 1)] = -s * gr;
         gg[2 * (j + 1) + 1] = -s * gi;
@@ -521,66 +611,479 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
         const double res = s * sqrt(gr * gr + gi * gi);
         if (res <= ws.tolabs[r] || hn <= 1e-15 * den || j + 1 >= m) ws.flags[r] = 0;
       }
-    __threadfence();
-    grid.sync();
+    gbar(ws.bar, epoch, ws.err);
   }
-  // y = R^-1 g, then x = V y
-  if (blockIdx.x == 0)
-    for (int r = t; r < nrhs; r += 256) {
-      const int k = ws.kdone[r];
-      const double* H = ws.H + 2L * r * (m + 1) * m;
-      const double* gg = ws.gv + 2L * r * (m + 1);
-      double* yv = ws.y + 2L * r * m;
-      for (int i = k - 1; i >= 0; --i) {
-        double sr = gg[2 * i], si = gg[2 * i + 1];
-        for (int l = i + 1; l < k; ++l) {
-          const double hr = H[2 * (i * m + l)], hi = H[2 * (i * m + l) + 1];
-          sr -= hr * yv[2 * l] - hi * yv[2 * l + 1];
-          si -= hr * yv[2 * l + 1] + hi * yv[2 * l];
-        }
-        const double dr = H[2 * (i * m + i)], di = H[2 * (i * m + i) + 1];
-        const double dd = dr * dr + di * di;
-        yv[2 * i] = (sr * dr + si * di) / dd;
-        yv[2 * i + 1] = (si * dr - sr * di) / dd;
+  // y = R^-1 g (every workgroup, into c1), then x = V y on the own sites
+  for (int r = t; r < nrhs; r += 256) {
+    const int k = ws.kdone[r];
+    const double* Rr = ws.R + 2L * r * m * m;
+    const double* gg = ws.gv + 2L * r * (m + 1);
+    double* yv = c1 + 2 * r * (m + 2);
+    for (int i = k - 1; i >= 0; --i) {
+      double sr = gg[2 * i], si = gg[2 * i + 1];
+      for (int l = i + 1; l < k; ++l) {
+        const double hr = Rr[2 * (l * m + i)], hi = Rr[2 * (l * m + i) + 1];
+        sr -= hr * yv[2 * l] - hi * yv[2 * l + 1];
+        si -= hr * yv[2 * l + 1] + hi * yv[2 * l];
       }
+      const double dr = Rr[2 * (i * m + i)], di = Rr[2 * (i * m + i) + 1];
+      const double dd = dr * dr + di * di;
+      yv[2 * i] = (sr * dr + si * di) / dd;
+      yv[2 * i + 1] = (si * dr - sr * di) / dd;
     }
-  __threadfence();
-  grid.sync();
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    int its = 0;
+    for (int r = 0; r < nrhs; ++r) its += ws.kdone[r];
+    atomicAdd(ws.stat, its);
+    atomicAdd(ws.stat + 1, 1);
+  }
+  __syncthreads();
   for (int u = blockIdx.x; u < nsites; u += gridDim.x)
     for (int k = t; k < nrhs * D; k += 256) {
       const int r = k / D, i = k - r * D;
       const int kd = ws.kdone[r];
-      const double* yv = ws.y + 2L * r * m;
+      const double* yv = c1 + 2 * r * (m + 2);
       const long o = r * n + (long)u * D + i;
       cplx<T> acc = mk<T>(0, 0);
       for (int l = 0; l < kd; ++l) cfma(acc, mk<T>((T)yv[2 * l], (T)yv[2 * l + 1]), V[(long)l * vs + o]);
       x[o] = acc;
     }
+  gbar_exit(ws.bar);
 }
+
+// ------------------------------------------------------------------ coarsest GMRES, one site per workgroup
+// Single right-hand side, FP32 arithmetic on a 16-bit D_c, at most 256
+// coarse sites.  Workgroup u owns site u and keeps:
+//  * the nine D_c blocks of the site in LDS for the whole solve;
+//  * the site's rows of the Krylov basis v_i and of p_i = (v_i - sum_{l<i}
+//    R_li p_l) / R_ii in registers, wave w holding i = w (mod 4);
+//  * its rows of x = sum_i g_i p_i, updated as soon as column i of the
+//    rotated Hessenberg R and the rotated g_i are final, so no triangular
+//    solve is left at the end.
+// Only the newest basis vector goes through global memory (for the
+// neighbours' matrix-vector products), together with per-workgroup partial
+// sums in pair-major order, [pair][workgroup].
+struct SiteGmres {
+  CoarseGeom g;
+  int m;
+  double reltol;
+};
+struct SiteGmresWs {
+  cplx<float>* vg0;   // [n] newest basis vector, even j
+  cplx<float>* vg1;   // [n] odd j
+  double* part1;      // [m+2][G] complex
+  double* part2;      // [m+2][G] complex
+  double* R;          // [m][m] complex, column j at [j][.]
+  double* gv;         // [m] complex, final rotated right-hand side
+  int* flag;          // [1] still iterating
+  int* kdone;         // [1] valid columns
+  unsigned* bar;      // [2]
+  int* err;           // [1]
+  int* stat;          // [2]
+};
+
+constexpr int SITE_SLOTS = 32;   // basis vectors per wave: m + 1 <= 128
+
+// sums[q] (q < P) = sum over workgroups of part[q][wg] (complex).  L lanes
+// share a pair (the largest power of two with L * P <= 256), each with
+// eight loads in flight, combined by shuffles; identical bits in every
+// workgroup.
+TM_D void gather_sums(const double* __restrict__ part, int P, int G, double* out) {
+  int L = 64;
+  while (L > 1 && L * P > 256) L >>= 1;
+  const int t = threadIdx.x, sub = t & (L - 1), slot = t / L, nslot = 256 / L;
+  for (int q0 = 0; q0 < P; q0 += nslot) {
+    const int q = q0 + slot;
+    double re[8], im[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) re[k] = im[k] = 0;
+    if (q < P) {
+      const double2* p = reinterpret_cast<const double2*>(part) + (long)q * G;
+      int wg = sub;
+      for (; wg + 7 * L < G; wg += 8 * L) {
+        double2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[wg + k * L];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          re[k] += v[k].x;
+          im[k] += v[k].y;
+        }
+      }
+      for (; wg < G; wg += L) {
+        const double2 v = p[wg];
+        re[0] += v.x;
+        im[0] += v.y;
+      }
+    }
+    double sr = ((re[0] + re[1]) + (re[2] + re[3])) + ((re[4] + re[5]) + (re[6] + re[7]));
+    double si = ((im[0] + im[1]) + (im[2] + im[3])) + ((im[4] + im[5]) + (im[6] + im[7]));
+    for (int o = 1; o < L; o <<= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      si += __shfl_xor(si, o, 64);
+    }
+    if (q < P && sub == 0) {
+      out[2 * q] = sr;
+      out[2 * q + 1] = si;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename S, int D>
+__global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const SP<S>* __restrict__ Dc,
+                                                             const cplx<float>* __restrict__ b,
+                                                             cplx<float>* __restrict__ x,
+                                                             const double* __restrict__ mu_dev, SiteGmresWs ws) {
+  using cf = cplx<float>;
+  constexpr int KQ = 9 * D / 4;   // terms per wave in the matrix-vector product
+  __shared__ cf vst[9 * D];
+  __shared__ cf comb[4][64];
+  __shared__ cf wl[64];
+  __shared__ cf pl[64];
+  __shared__ double c1[2 * (4 * SITE_SLOTS + 1)];
+  __shared__ double c2[2 * (4 * SITE_SLOTS + 1)];
+  __shared__ double rcol[2 * 4 * SITE_SLOTS];
+  __shared__ int s_flag, s_kd;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  SP<S>* dcl = reinterpret_cast<SP<S>*>(dyn);
+  const CoarseGeom& g = a.g;
+  const int m = a.m, G = gridDim.x, u = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const float mu = (float)mu_dev[0];
+  unsigned epoch = 0;
+  cf Vr[SITE_SLOTS], Pr[SITE_SLOTS];
+#pragma unroll
+  for (int s = 0; s < SITE_SLOTS; ++s) Vr[s] = Pr[s] = mk<float>(0, 0);
+  // wave 0: x rows, the newest basis vector, and v_i of the column i whose
+  // p_i is formed at the top of the next iteration
+  cf xacc = mk<float>(0, 0), vcur = mk<float>(0, 0), vfin = mk<float>(0, 0);
+  // Givens state, wave 0 of workgroup 0: rotation i in lane i % 64, slot i / 64
+  double csr0 = 0, csi0 = 0, sn0 = 0, csr1 = 0, csi1 = 0, sn1 = 0, gre = 0, gim = 0, tolabs = 0;
+
+  {
+    const Quad<S>* src = reinterpret_cast<const Quad<S>*>(Dc + (long)u * 9L * D * D);
+    Quad<S>* dst = reinterpret_cast<Quad<S>*>(dcl);
+    for (int k = t; k < 9 * D * D / 4; k += 256) dst[k] = src[k];
+  }
+  if (t < 64) {
+    const cf bv = lane < D ? b[(long)u * D + lane] : mk<float>(0, 0);
+    vcur = bv;
+    float s2 = norm2(bv);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      ws.part1[2L * u] = s2;
+      ws.part1[2L * u + 1] = 0;
+    }
+  }
+  gbar(ws.bar, epoch, ws.err);
+  gather_sums(ws.part1, 1, G, c1);
+  {
+    const double beta = sqrt(c1[0]);
+    const bool ok = beta > 0 && beta < 1e300;
+    if (t < 64) {
+      vcur = ok ? (float)(1.0 / beta) * vcur : mk<float>(0, 0);
+      Vr[0] = vcur;
+      if (lane < D) ws.vg0[(long)u * D + lane] = vcur;
+    }
+    if (u == 0 && t < 64) {
+      gre = beta;
+      tolabs = a.reltol * beta;
+      if (t == 0) {
+        *ws.flag = ok ? 1 : 0;
+        *ws.kdone = 0;
+      }
+    }
+  }
+  gbar(ws.bar, epoch, ws.err);
+
+  for (int j = 0;; ++j) {
+    // state written by workgroup 0 before the barrier just passed
+    if (t == 0) {
+      s_flag = __hip_atomic_load(ws.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_kd = __hip_atomic_load(ws.kdone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (j > 0 && t < j) {
+      rcol[2 * t] = ws.R[2L * ((long)(j - 1) * m + t)];
+      rcol[2 * t + 1] = ws.R[2L * ((long)(j - 1) * m + t) + 1];
+    }
+    __syncthreads();
+    const int kd = s_kd;
+    // column j-1 final: p_{j-1} = (v_{j-1} - sum_{l<j-1} R_{l,j-1} p_l) / R_{j-1,j-1}, x += g_{j-1} p_{j-1}
+    if (j > 0 && kd >= j) {
+      const int i = j - 1;
+      cf acc = mk<float>(0, 0);
+#pragma unroll
+      for (int s = 0; s < SITE_SLOTS; ++s) {
+        const int l = 4 * s + wv;
+        if (4 * s >= i) break;
+        if (l < i) cfma(acc, mk<float>((float)rcol[2 * l], (float)rcol[2 * l + 1]), Pr[s]);
+      }
+      comb[wv][lane] = acc;
+      __syncthreads();
+      if (t < 64) {
+        const cf sum = (comb[0][lane] + comb[1][lane]) + (comb[2][lane] + comb[3][lane]);
+        const double dr = rcol[2 * i], di = rcol[2 * i + 1], dd = dr * dr + di * di;
+        const cf num = vfin - sum;
+        // num / R_ii
+        const cf p = mk<float>((float)((num.re * dr + num.im * di) / dd), (float)((num.im * dr - num.re * di) / dd));
+        pl[lane] = p;
+        const double gr = ws.gv[2 * i], gi = ws.gv[2 * i + 1];
+        cfma(xacc, mk<float>((float)gr, (float)gi), p);
+      }
+      __syncthreads();
+      if (wv == (i & 3)) {
+#pragma unroll
+        for (int s = 0; s < SITE_SLOTS; ++s)
+          if (s == (i >> 2)) Pr[s] = pl[lane];
+      }
+    }
+    if (j == m || !s_flag) break;   // same in every workgroup
+
+    // w = D_c(mu) v_j on the own site: stage the nine input vectors, then
+    // rows over lanes and a quarter of the 9*D terms per wave
+    const cf* vj = (j & 1) ? ws.vg1 : ws.vg0;
+    {
+      const C4 c = cc_coords(g, u);
+      for (int k = t; k < 9 * D; k += 256) {
+        const int bb = k / D, jj = k - bb * D;
+        const long src = bb == 0 ? u : cc_nbr(g, c, hop_mu(bb), hop_step(bb));
+        vst[k] = vj[src * D + jj];
+      }
+    }
+    __syncthreads();
+    if (lane < D) {
+      cf acc = mk<float>(0, 0);
+      const int k0 = wv * KQ;
+#pragma unroll 8
+      for (int k = k0; k < k0 + KQ; ++k) cfma(acc, Store<S>::template cvt<float>(dcl[k * D + lane]), vst[k]);
+      comb[wv][lane] = acc;
+    }
+    __syncthreads();
+    if (t < D) {
+      cf w = (comb[0][t] + comb[1][t]) + (comb[2][t] + comb[3][t]);
+      w += (t < D / 2 ? mu : -mu) * times_i(vst[t]);
+      wl[t] = w;
+    }
+    __syncthreads();
+
+    // two classical Gram-Schmidt passes; the second also gives |w|^2
+    for (int pass = 0; pass < 2; ++pass) {
+      double* part = pass ? ws.part2 : ws.part1;
+      double* cc = pass ? c2 : c1;
+      const cf wv_l = lane < D ? wl[lane] : mk<float>(0, 0);
+#pragma unroll
+      for (int s = 0; s < SITE_SLOTS; ++s) {
+        const int i = 4 * s + wv;
+        if (4 * s > j) break;
+        if (i <= j) {
+          const cf d = cmulc(Vr[s], wv_l);
+          const float dre = wave_sum(d.re), dim = wave_sum(d.im);
+          if (lane == 0) {
+            part[2L * ((long)i * G + u)] = dre;
+            part[2L * ((long)i * G + u) + 1] = dim;
+          }
+        }
+      }
+      if (pass == 1 && wv == 0) {
+        const float n2 = wave_sum(norm2(wv_l));
+        if (lane == 0) {
+          part[2L * ((long)(j + 1) * G + u)] = n2;
+          part[2L * ((long)(j + 1) * G + u) + 1] = 0;
+        }
+      }
+      gbar(ws.bar, epoch, ws.err);
+      gather_sums(part, j + 1 + pass, G, cc);
+      cf acc = mk<float>(0, 0);
+#pragma unroll
+      for (int s = 0; s < SITE_SLOTS; ++s) {
+        const int i = 4 * s + wv;
+        if (4 * s > j) break;
+        if (i <= j) cfma(acc, mk<float>((float)cc[2 * i], (float)cc[2 * i + 1]), Vr[s]);
+      }
+      comb[wv][lane] = acc;
+      __syncthreads();
+      if (t < D) wl[t] = wl[t] - ((comb[0][t] + comb[1][t]) + (comb[2][t] + comb[3][t]));
+      __syncthreads();
+    }
+    // h_{j+1,j} = sqrt(|w|^2 - |c2|^2) after the second pass
+    double h2 = c2[2 * (j + 1)];
+    for (int l = 0; l <= j; ++l) h2 -= c2[2 * l] * c2[2 * l] + c2[2 * l + 1] * c2[2 * l + 1];
+    const double hn = h2 > 0 ? sqrt(h2) : 0.0;
+    {
+      const cf vn = (lane < D && hn > 0) ? (float)(1.0 / hn) * wl[lane] : mk<float>(0, 0);
+      if (wv == ((j + 1) & 3)) {
+#pragma unroll
+        for (int s = 0; s < SITE_SLOTS; ++s)
+          if (s == ((j + 1) >> 2)) Vr[s] = vn;
+      }
+      if (t < 64) {
+        vfin = vcur;
+        vcur = vn;
+        if (lane < D) ((j & 1) ? ws.vg0 : ws.vg1)[(long)u * D + lane] = vn;
+      }
+    }
+    // Givens rotations, wave 0 of workgroup 0
+    if (u == 0 && t < 64) {
+      double ar = c1[0] + c2[0], ai = c1[1] + c2[1];
+      for (int i = 0; i < j; ++i) {
+        const bool hi = i >= 64;
+        const double cr = __shfl(hi ? csr1 : csr0, i & 63, 64);
+        const double ci = __shfl(hi ? csi1 : csi0, i & 63, 64);
+        const double sn = __shfl(hi ? sn1 : sn0, i & 63, 64);
+        const double br = c1[2 * (i + 1)] + c2[2 * (i + 1)], bi = c1[2 * (i + 1) + 1] + c2[2 * (i + 1) + 1];
+        if (t == 0) {
+          ws.R[2L * ((long)j * m + i)] = cr * ar - ci * ai + sn * br;
+          ws.R[2L * ((long)j * m + i) + 1] = cr * ai + ci * ar + sn * bi;
+        }
+        const double ur = -sn * ar + (cr * br + ci * bi);
+        const double ui = -sn * ai + (cr * bi - ci * br);
+        ar = ur;
+        ai = ui;
+      }
+      const double den = sqrt(ar * ar + ai * ai + hn * hn);
+      if (!(den > 0) || den != den) {
+        if (t == 0) *ws.flag = 0;
+      } else {
+        const double cr = ar / den, ci = -ai / den, sn = hn / den;
+        if (lane == (j & 63)) {
+          if (j >= 64) { csr1 = cr; csi1 = ci; sn1 = sn; }
+          else { csr0 = cr; csi0 = ci; sn0 = sn; }
+        }
+        const double res = sn * sqrt(gre * gre + gim * gim);
+        if (t == 0) {
+          ws.R[2L * ((long)j * m + j)] = den;
+          ws.R[2L * ((long)j * m + j) + 1] = 0;
+          ws.gv[2 * j] = cr * gre - ci * gim;
+          ws.gv[2 * j + 1] = cr * gim + ci * gre;
+          *ws.kdone = j + 1;
+          if (res <= tolabs || hn <= 1e-15 * den || j + 1 >= m) *ws.flag = 0;
+        }
+        const double ngr = -sn * gre, ngi = -sn * gim;
+        gre = ngr;
+        gim = ngi;
+      }
+    }
+    gbar(ws.bar, epoch, ws.err);
+  }
+  if (t < D) x[(long)u * D + t] = xacc;
+  if (u == 0 && t == 0) {
+    atomicAdd(ws.stat, s_kd);
+    atomicAdd(ws.stat + 1, 1);
+  }
+  gbar_exit(ws.bar);
+}
+
+// Workgroups of the shared-site coarsest GMRES (several sites per
+// workgroup); TMAMG_COARSEST_WG overrides the default.
+static int coarsest_shared_groups() {
+  static int cap = -1;
+  if (cap < 0) {
+    const char* e = getenv("TMAMG_COARSEST_WG");
+    cap = e ? std::max(1, std::min(256, atoi(e))) : 64;
+  }
+  return cap;
+}
+
+// upper bound of the workgroup count, which sizes the partial-sum arrays
+int coarsest_groups(long nsites) { return (int)std::max<long>(1, std::min<long>(256, nsites)); }
+
+size_t coarsest_ws_doubles(int nrhs, int m, int G) {
+  return 2 * 2 * (size_t)G * nrhs * (m + 2) + (size_t)nrhs * (2 * (size_t)m * m + 2 * m + m + 2 * (m + 1) + 1);
+}
+// ints: barrier counters [0, 1], timeout flag [2], statistics [3, 4],
+// flags and iteration counts of the right-hand sides from [8]
+size_t coarsest_ws_ints(int nrhs) { return 2 * (size_t)nrhs + 8; }
 
 template <typename T, typename S, int D>
-static hipError_t gmres_coop_launch(CoopGmres a, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x, const double* mu_dev,
-                                    CoopGmresWs ws, hipStream_t st) {
+static hipError_t gmres_launch(CoopGmres a, size_t coef_bytes, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x,
+                               const double* mu_dev, CoopGmresWs ws, hipStream_t st) {
+  const int G = (int)std::min<long>(a.g.V, coarsest_shared_groups());
   const void* kern = reinterpret_cast<const void*>(&k_coarsest_gmres<T, S, D>);
-  static int cap = 0;
-  if (cap == 0) cap = std::min(2048, max_coresident(kern, 256, 0));
-  const int G = (int)std::max<long>(1, std::min<long>(cap, a.g.V));
+  if (coef_bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)coef_bytes);
+    if (e != hipSuccess) return e;
+  }
   void* args[] = {&a, (void*)&Dc, (void*)&b, (void*)&x, (void*)&mu_dev, &ws};
-  return hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, 0, st);
+  return hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, (unsigned)coef_bytes, st);
 }
 
-size_t coarsest_ws_doubles(long n, int nrhs, int m, int nsites) {
-  (void)n;
-  return 2 * (size_t)nsites * nrhs * (m + 1) + (size_t)nrhs * (2 * (m + 1) + 1 + 2 * (m + 1) * m + 2 * m + m +
-                                                              2 * (m + 1) + 2 * m + 1);
+template <typename S, int D>
+static hipError_t site_gmres_launch(const SiteGmres& a, const SP<S>* Dc, const cplx<float>* b, cplx<float>* x,
+                                    const double* mu_dev, const SiteGmresWs& ws, hipStream_t st) {
+  const void* kern = reinterpret_cast<const void*>(&k_coarsest_gmres_site<S, D>);
+  const size_t dyn = 9 * (size_t)D * D * sizeof(SP<S>);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  SiteGmres aa = a;
+  SiteGmresWs ww = ws;
+  void* args[] = {&aa, (void*)&Dc, (void*)&b, (void*)&x, (void*)&mu_dev, &ww};
+  return hipLaunchCooperativeKernel(kern, dim3((unsigned)a.g.V), dim3(256), args, (unsigned)dyn, st);
+}
+
+// one right-hand side, FP32 over a 16-bit D_c, at most 256 sites
+template <typename T, typename S>
+static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x, int nrhs,
+                           const double* mu_dev, int m, double reltol, cplx<T>* Vbasis, double* dws, size_t dws_cap,
+                           int* iws, size_t iws_cap, hipStream_t st) {
+  if constexpr (!std::is_same<T, float>::value || sizeof(SP<S>) != 4) {
+    return false;
+  } else {
+    if (nrhs != 1 || g.V > 256 || m + 1 > 4 * SITE_SLOTS) return false;
+    const int G = (int)g.V;
+    if (4 * (size_t)G * (m + 2) + 2 * (size_t)m * m + 2 * (size_t)m > dws_cap || iws_cap < 8) return false;
+    SiteGmres a;
+    a.g = g;
+    a.m = m;
+    a.reltol = reltol;
+    SiteGmresWs ws;
+    ws.vg0 = Vbasis;
+    ws.vg1 = Vbasis + g.V * d;
+    double* p = dws;
+    ws.part1 = p; p += 2 * (size_t)G * (m + 2);
+    ws.part2 = p; p += 2 * (size_t)G * (m + 2);
+    ws.R = p; p += 2 * (size_t)m * m;
+    ws.gv = p; p += 2 * (size_t)m;
+    ws.bar = reinterpret_cast<unsigned*>(iws);
+    ws.err = iws + 2;
+    ws.stat = iws + 3;
+    ws.flag = iws + 5;
+    ws.kdone = iws + 6;
+    hipError_t e;
+    switch (d) {
+      case 24: e = site_gmres_launch<S, 24>(a, Dc, b, x, mu_dev, ws, st); break;
+      case 32: e = site_gmres_launch<S, 32>(a, Dc, b, x, mu_dev, ws, st); break;
+      case 48: e = site_gmres_launch<S, 48>(a, Dc, b, x, mu_dev, ws, st); break;
+      case 64: e = site_gmres_launch<S, 64>(a, Dc, b, x, mu_dev, ws, st); break;
+      default: return false;
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  }
 }
 
 template <typename T, typename S>
 bool launch_coarsest_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x, int nrhs,
                            const double* mu_dev, int m, double reltol, cplx<T>* Vbasis, cplx<T>* w, double* dws,
-                           size_t dws_cap, int* iws, hipStream_t st) {
-  if (!(d == 24 || d == 32 || d == 48 || d == 64)) return false;
-  if (coarsest_ws_doubles(g.V * d, nrhs, m, (int)g.V) > dws_cap) return false;
+                           size_t dws_cap, int* iws, size_t iws_cap, hipStream_t st) {
+  if (!(d == 24 || d == 32 || d == 48 || d == 64) || m < 1) return false;
+  if (try_site_gmres<T, S>(g, d, Dc, b, x, nrhs, mu_dev, m, reltol, Vbasis, dws, dws_cap, iws, iws_cap, st))
+    return true;
+  // the shared-site kernel serialises right-hand sides inside a workgroup:
+  // wide batches go to the generic Krylov path
+  if (nrhs > 2) return false;
+  const int Gmax = coarsest_groups(g.V);
+  const size_t coef_bytes = 2 * 2 * sizeof(double) * (size_t)nrhs * (m + 2);
+  if (coef_bytes > 65536) return false;
+  if (coarsest_ws_doubles(nrhs, m, Gmax) > dws_cap || coarsest_ws_ints(nrhs) > iws_cap) return false;
   CoopGmres a;
   a.g = g;
   a.nrhs = nrhs;
@@ -590,23 +1093,24 @@ bool launch_coarsest_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
   ws.V = Vbasis;
   ws.w = w;
   double* p = dws;
-  ws.part = p; p += 2 * (size_t)g.V * nrhs * (m + 1);
-  ws.coef = p; p += 2 * (size_t)nrhs * (m + 1);
-  ws.nrm = p; p += nrhs;
-  ws.H = p; p += 2 * (size_t)nrhs * (m + 1) * m;
+  ws.part1 = p; p += 2 * (size_t)Gmax * nrhs * (m + 2);
+  ws.part2 = p; p += 2 * (size_t)Gmax * nrhs * (m + 2);
+  ws.R = p; p += 2 * (size_t)nrhs * m * m;
   ws.cs = p; p += 2 * (size_t)nrhs * m;
   ws.sn = p; p += (size_t)nrhs * m;
   ws.gv = p; p += 2 * (size_t)nrhs * (m + 1);
-  ws.y = p; p += 2 * (size_t)nrhs * m;
   ws.tolabs = p; p += nrhs;
-  ws.flags = iws;
-  ws.kdone = iws + nrhs;
+  ws.bar = reinterpret_cast<unsigned*>(iws);
+  ws.err = iws + 2;
+  ws.stat = iws + 3;
+  ws.flags = iws + 8;
+  ws.kdone = iws + 8 + nrhs;
   hipError_t e;
   switch (d) {
-    case 24: e = gmres_coop_launch<T, S, 24>(a, Dc, b, x, mu_dev, ws, st); break;
-    case 32: e = gmres_coop_launch<T, S, 32>(a, Dc, b, x, mu_dev, ws, st); break;
-    case 48: e = gmres_coop_launch<T, S, 48>(a, Dc, b, x, mu_dev, ws, st); break;
-    default: e = gmres_coop_launch<T, S, 64>(a, Dc, b, x, mu_dev, ws, st); break;
+    case 24: e = gmres_launch<T, S, 24>(a, coef_bytes, Dc, b, x, mu_dev, ws, st); break;
+    case 32: e = gmres_launch<T, S, 32>(a, coef_bytes, Dc, b, x, mu_dev, ws, st); break;
+    case 48: e = gmres_launch<T, S, 48>(a, coef_bytes, Dc, b, x, mu_dev, ws, st); break;
+    default: e = gmres_launch<T, S, 64>(a, coef_bytes, Dc, b, x, mu_dev, ws, st); break;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -616,12 +1120,13 @@ bool launch_coarsest_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
 }
 
 #define INST_COOP(T, S)                                                                                             \
-  template bool launch_sap_coarse_coop<T, S>(const CoarseGeom&, int, const int*, const SP<S>*, const cplx<T>*,     \
-                                             cplx<T>*, int, const double*, const int*, int, const int*, int, int,   \
-                                             int, cplx<T>*, cplx<T>*, double*, long, hipStream_t);                 \
+  template bool launch_sap_coarse_fused<T, S>(const CoarseGeom&, int, const int*, const SP<S>*, const cplx<T>*,    \
+                                              cplx<T>*, int, const double*, const int*, int, const int*, int, int,  \
+                                              int, cplx<T>* const*, cplx<T>* const*, double* const*, long,          \
+                                              hipStream_t);                                                         \
   template bool launch_coarsest_gmres<T, S>(const CoarseGeom&, int, const SP<S>*, const cplx<T>*, cplx<T>*, int,   \
                                             const double*, int, double, cplx<T>*, cplx<T>*, double*, size_t, int*, \
-                                            hipStream_t);
+                                            size_t, hipStream_t);
 INST_COOP(double, double)
 INST_COOP(float, float)
 INST_COOP(float, __hip_bfloat16)

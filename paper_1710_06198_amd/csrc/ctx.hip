@@ -67,6 +67,10 @@ void Hier<T, S>::test_op(int op, int level, const void* in_, void* out_, int nrh
       need(level == 0 || (level == 1 && nlev >= 3));
       precond(level, in, out, nrhs, mu);
       break;
+    case TMAMG_OP_COARSEST:
+      need(level >= 1 && level == nlev - 1);
+      coarse_solve(level, in, out, nrhs, mu);
+      break;
     default:
       throw TmError{TMAMG_EINVAL, "unknown operator"};
   }
@@ -338,7 +342,7 @@ void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
   hier->setup(mu);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  timer.report("setup", st);
+  timer.report("setup", st, timer.on ? hier->stats_line() : std::string());
   have_setup = true;
   t_setup = std::chrono::duration<double>(clk::now() - t0).count();
 }
@@ -491,7 +495,7 @@ tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const 
   tmamg_status s = solve_core(nrhs, mu_host, tol, &loc);
   launch_spinor_to_canonical<double>(fg, x64.p, x, nrhs, st);
   HIPCHK(hipStreamSynchronize(st));
-  timer.report("solve", st);
+  timer.report("solve", st, timer.on ? hier->stats_line() : std::string());
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   loc.status = s;

@@ -153,17 +153,20 @@ void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const 
 // complex Gaussian noise, E|z|^2 = 1, counter-based (seed, index)
 template <typename T>
 void launch_random(cplx<T>* out, long count, unsigned long long seed, hipStream_t st);
-// persistent cooperative versions for the coarse levels (false: shape not covered)
+// Coarse-level SAP with fused MR launches, and the persistent coarsest
+// GMRES (false: shape not covered, the caller uses the generic kernels)
 template <typename T, typename S>
-bool launch_sap_coarse_coop(const CoarseGeom& g, int d, const int blk[4], const typename Store<S>::pair* Dc,
-                            const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev, const int* bl0, int n0,
-                            const int* bl1, int n1, int sweeps, int mr_steps, cplx<T>* rho_g, cplx<T>* q_g,
-                            double* part, long part_cap, hipStream_t st);
-size_t coarsest_ws_doubles(long n, int nrhs, int m, int G);
+bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const typename Store<S>::pair* Dc,
+                             const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev, const int* bl0, int n0,
+                             const int* bl1, int n1, int sweeps, int mr_steps, cplx<T>* const rho[2],
+                             cplx<T>* const q[2], double* const part[2], long part_cap, hipStream_t st);
+int coarsest_groups(long nsites);
+size_t coarsest_ws_doubles(int nrhs, int m, int G);
+size_t coarsest_ws_ints(int nrhs);
 template <typename T, typename S>
 bool launch_coarsest_gmres(const CoarseGeom& g, int d, const typename Store<S>::pair* Dc, const cplx<T>* b, cplx<T>* x,
                            int nrhs, const double* mu_dev, int m, double reltol, cplx<T>* Vbasis, cplx<T>* w,
-                           double* dws, size_t dws_cap, int* iws, hipStream_t st);
+                           double* dws, size_t dws_cap, int* iws, size_t iws_cap, hipStream_t st);
 // storage conversions for the debug/export hooks
 template <typename S>
 void launch_store_to64(const typename Store<S>::pair* in, cplx<double>* out, long count, hipStream_t st);

@@ -104,7 +104,7 @@ struct PhaseTimer {
     HIPCHK(hipEventRecord(b, st));
     recs.push_back({ph, a, b});
   }
-  void report(const char* tag, hipStream_t st);
+  void report(const char* tag, hipStream_t st, const std::string& extra = "");
   ~PhaseTimer() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
@@ -125,6 +125,8 @@ struct HierBase {
   virtual void export_P(int level, cplx<double>* out) = 0;
   virtual void export_Dc(int level, cplx<double>* out) = 0;
   virtual double time_kernel(int kernel, int nrhs, int reps) = 0;
+  // counters of the coarse solves since the last call, for the timing line
+  virtual std::string stats_line() { return ""; }
   long stats_l2 = 0, stats_coarsest = 0;
   PhaseTimer* timer = nullptr;
 };
@@ -144,10 +146,10 @@ struct Hier : HierBase {
   DevArr<cplx<T>> rc1, ec1, rc2, ec2;
   Krylov<T> K1, K2;
   DevArr<double> red_partial, red_out, red_inv, mu_setup;
-  // persistent coarse kernels: SAP residual/product vectors and partial sums,
-  // coarsest-GMRES scalars
-  DevArr<cplx<T>> sap_rho, sap_q;
-  DevArr<double> sap_part, cg_dws;
+  // fused coarse SAP: residual/product vectors and per-site partial sums,
+  // two slots each; coarsest-GMRES scalars, flags and barrier counters
+  DevArr<cplx<T>> sap_rho[2], sap_q[2];
+  DevArr<double> sap_part[2], cg_dws;
   DevArr<int> cg_iws;
   int cap = 0;
   bool use_coop = true;
@@ -155,6 +157,7 @@ struct Hier : HierBase {
   explicit Hier(Ctx* c_);
   void build_colours(const int nb[4], DevArr<int> out[2]);
   void ensure(int nrhs) override;
+  std::string stats_line() override;
   void dc_apply(int level, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu);
   void sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
   void sap_level1(const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);

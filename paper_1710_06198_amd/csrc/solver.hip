@@ -22,7 +22,7 @@ __global__ void k_fill_double(double* p, double v, int n) {
   if (i < n) p[i] = v;
 }
 
-void PhaseTimer::report(const char* tag, hipStream_t st) {
+void PhaseTimer::report(const char* tag, hipStream_t st, const std::string& extra) {
   if (!on) return;
   HIPCHK(hipStreamSynchronize(st));
   double t[NPH] = {0};
@@ -35,7 +35,7 @@ void PhaseTimer::report(const char* tag, hipStream_t st) {
                                    "outer_operator", "setup_build"};
   fprintf(stderr, "[tmamg timing] %s", tag);
   for (int i = 0; i < NPH; ++i) fprintf(stderr, " %s=%.2fms", names[i], t[i]);
-  fprintf(stderr, "\n");
+  fprintf(stderr, "%s\n", extra.c_str());
   recs.clear();
   used = 0;
 }
@@ -213,19 +213,39 @@ void Hier<T, S>::ensure(int nrhs) {
     ec2.alloc((size_t)cap * g2.V * d2);
     tmp1.alloc((size_t)cap * g1.V * d1);
     K2.ensure(g2.V * d2, p.coarsest_iters, cap, false, st);
-    sap_rho.alloc((size_t)cap * g1.V * d1);
-    sap_q.alloc((size_t)cap * g1.V * d1);
-    sap_part.alloc(3 * (size_t)g1.V * cap);
+    for (int k = 0; k < 2; ++k) {
+      sap_rho[k].alloc((size_t)cap * g1.V * d1);
+      sap_q[k].alloc((size_t)cap * g1.V * d1);
+      sap_part[k].alloc(3 * (size_t)g1.V * cap);
+    }
   }
   // coarsest level: persistent GMRES workspace
   {
     const CoarseGeom& gc = nlev >= 3 ? g2 : g1;
     const int dc = nlev >= 3 ? d2 : d1;
     if (nlev >= 2) {
-      cg_dws.alloc(coarsest_ws_doubles(gc.V * dc, cap, p.coarsest_iters, (int)gc.V));
-      cg_iws.alloc(2 * (size_t)cap);
+      (void)dc;
+      cg_dws.alloc(coarsest_ws_doubles(cap, p.coarsest_iters, coarsest_groups(gc.V)));
+      cg_iws.alloc(coarsest_ws_ints(cap));
+      HIPCHK(hipMemsetAsync(cg_iws.p, 0, cg_iws.bytes(), st));   // barrier counters start at zero
     }
   }
+}
+
+template <typename T, typename S>
+std::string Hier<T, S>::stats_line() {
+  std::string out = " level1_iters=" + std::to_string(stats_l2) + " coarsest_iters(generic)=" +
+                    std::to_string(stats_coarsest);
+  stats_l2 = stats_coarsest = 0;
+  if (cg_iws.p) {
+    int h[3] = {0, 0, 0};
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(h, cg_iws.p + 2, sizeof(h), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemsetAsync(cg_iws.p + 2, 0, sizeof(h), c->st));
+    out += " coarsest_calls=" + std::to_string(h[2]) + " coarsest_iters=" + std::to_string(h[1]) +
+           " barrier_timeouts=" + std::to_string(h[0]);
+  }
+  return out;
 }
 
 template <typename T, typename S>
@@ -250,15 +270,18 @@ void Hier<T, S>::sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const 
     }
 }
 
-// Coarse-level SAP: one persistent cooperative launch for all sweeps when
+// Coarse-level SAP: site-per-workgroup launches with fused MR steps when
 // the shape is covered, else one launch per colour and sweep.
 template <typename T, typename S>
 void Hier<T, S>::sap_level1(const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps) {
   const tmamg_params& p = c->par;
+  cplx<T>* const rho[2] = {sap_rho[0].p, sap_rho[1].p};
+  cplx<T>* const q[2] = {sap_q[0].p, sap_q[1].p};
+  double* const part[2] = {sap_part[0].p, sap_part[1].p};
   if (use_coop && sweeps > 0 &&
-      launch_sap_coarse_coop<T, S>(g1, d1, p.sap_block1, Dc1.p, eta, z, nrhs, mu, blist1[0].p, blist1[0].count,
-                                   blist1[1].p, blist1[1].count, sweeps, p.mr_steps, sap_rho.p, sap_q.p, sap_part.p,
-                                   (long)sap_part.n, c->st))
+      launch_sap_coarse_fused<T, S>(g1, d1, p.sap_block1, Dc1.p, eta, z, nrhs, mu, blist1[0].p, blist1[0].count,
+                                    blist1[1].p, blist1[1].count, sweeps, p.mr_steps, rho, q, part,
+                                    (long)sap_part[0].n, c->st))
     return;
   sap(1, eta, z, nrhs, mu, sweeps);
 }
@@ -311,7 +334,7 @@ void Hier<T, S>::coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int n
     const int dc = level == 1 ? d1 : d2;
     const SPair* Dc = level == 1 ? Dc1.p : Dc2.p;
     if (use_coop && launch_coarsest_gmres<T, S>(gc, dc, Dc, rhs, sol, nrhs, mu, p.coarsest_iters, p.coarsest_tol,
-                                                K.V.p, K.w.p, cg_dws.p, cg_dws.n, cg_iws.p, st))
+                                                K.V.p, K.w.p, cg_dws.p, cg_dws.n, cg_iws.p, cg_iws.n, st))
       return;
     int it = krylov_cycle<T>(K, A, nullptr, rhs, sol, nrhs, p.coarsest_iters, p.coarsest_tol, nullptr, false,
                              nullptr, st);

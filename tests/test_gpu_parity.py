@@ -297,3 +297,63 @@ def test_coarse_sap_and_cycle(injected_three_level):
     for r in range(2):
         ref = H.precondition(lvl1, v[r], mus[r])
         assert rel(out.cpu()[r], ref.reshape(Vc1, d1)) < 1e-9
+
+
+def coarse_op_from_export(s, level, cdims):
+    """The library's stored D_c of `level` (exact values of its storage
+    precision) as an oracle CoarseOp."""
+    Vc, d = s.level_info(level)
+    D = torch.empty((Vc, 9, d, d), dtype=torch.complex128, device=DEV)
+    s.export(1, level, D)
+    D = D.cpu().transpose(-1, -2)
+    lx, ly, lz, lt = cdims
+    blk = lambda b: D[:, b].reshape(lt, lz, ly, lx, d, d).contiguous()
+    return mg.CoarseOp(blk(0), torch.stack([blk(1 + 2 * m) for m in range(4)]),
+                       torch.stack([blk(2 + 2 * m) for m in range(4)])), Vc, d
+
+
+def check_coarsest(s, level, cdims, nrhs, mus, iters, tol_rel, seed):
+    Dc, Vc, d = coarse_op_from_export(s, level, cdims)
+    v = mg.random_test_vectors(cdims, d, nrhs, seed)
+    vd = to_dev(v.reshape(nrhs, Vc, d).numpy())
+    out = torch.empty_like(vd)
+    s.apply(tm.OP_COARSEST, level, vd, out, mus)
+    for r in range(nrhs):
+        ref = mg.fgmres(lambda e: Dc.apply(e, mus[r]), v[r], 1e-30, iters, iters).x
+        err = rel(out.cpu()[r], ref.reshape(Vc, d))
+        say(f"  rhs {r} mu {mus[r]}: rel. difference {err:.2e}")
+        assert err < tol_rel
+
+
+# GMRES with a fixed iteration count (tolerance below reach) has a unique
+# iterate, the minimiser over the Krylov space, so the GPU result is
+# compared with the oracle's GMRES on the same stored D_c.  Covered: the
+# one-site-per-workgroup kernel (one RHS, 16-bit storage), the shared-site
+# cooperative kernel (two RHS, FP32 storage, FP64) and the generic path.
+@pytest.mark.parametrize("precision,storage,nrhs", [
+    ("mixed", "bf16", 1), ("mixed", "fp16", 1), ("mixed", "bf16", 2), ("mixed", "fp32", 1),
+    ("mixed", "bf16", 4), ("fp64", "fp64", 1), ("fp64", "fp64", 2)])
+def test_coarsest_gmres_two_level(c1, precision, storage, nrhs):
+    w, m0, U, Ud, op = c1
+    say("coarsest GMRES, 2 levels", precision, storage, nrhs)
+    prec = tm.MIXED if precision == "mixed" else tm.FP64
+    st = {"bf16": tm.STORE_BF16, "fp16": tm.STORE_FP16, "fp32": tm.STORE_FP32, "fp64": tm.STORE_FP64}[storage]
+    s = make_solver(w, precision=prec, storage=st, coarsest_iters=20, coarsest_tol=1e-30)
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    cdims = tuple(a // b for a, b in zip(w.dims, w.agg[0]))
+    mus = [w.mu, -0.05, 0.2, 0.0][:nrhs]
+    check_coarsest(s, 1, cdims, nrhs, mus, 20, 1e-10 if prec == tm.FP64 else 1e-3, 7100 + nrhs)
+
+
+def test_coarsest_gmres_three_level():
+    dims = (8, 8, 16, 16)
+    say("coarsest GMRES, 3 levels", dims)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1236)
+    agg = ((4, 4, 4, 4), (2, 2, 2, 2))
+    p = tm.default_params(nlevels=3, agg=agg, nv=(12, 16), sap_block1=(1, 1, 2, 2), coarsest_iters=24,
+                          coarsest_tol=1e-30, setup_iters=1, precision=tm.MIXED, storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+    cdims = tuple(a // b // c for a, b, c in zip(dims, agg[0], agg[1]))
+    check_coarsest(s, 2, cdims, 1, [0.003], 24, 1e-3, 7200)
