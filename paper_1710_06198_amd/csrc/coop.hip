@@ -319,7 +319,7 @@ bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const
 }
 
 // ------------------------------------------------------------------ coarsest GMRES
-// Barrier over the workgroups of a co-resident launch.  The counter only
+// Barrier over the workgroups of a launch whose workgroups are all resident.  The counter only
 // grows within a launch (epoch e waits for e * gridDim.x arrivals); the
 // last workgroup to leave the kernel sets it back to zero for the next
 // launch on the stream.  The wait is bounded: a timeout raises err and
@@ -996,6 +996,24 @@ size_t coarsest_ws_doubles(int nrhs, int m, int G) {
 // flags and iteration counts of the right-hand sides from [8]
 size_t coarsest_ws_ints(int nrhs) { return 2 * (size_t)nrhs + 8; }
 
+// The persistent kernels synchronise through their own barrier, so every
+// workgroup must be resident at once.  They are launched as ordinary
+// kernels (no separate cooperative queue) after checking that the grid
+// fits the device at the kernel's occupancy; the barrier's bounded wait
+// still lets every wave finish if that ever fails to hold.
+static bool grid_fits(const void* kern, int G, size_t dyn) {
+  int dev = 0, per_cu = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, dyn) != hipSuccess) return false;
+  return (long)per_cu * ncu >= G;
+}
+
+static hipError_t launch_resident(const void* kern, int G, void** args, size_t dyn, hipStream_t st) {
+  if (!grid_fits(kern, G, dyn)) return hipErrorCooperativeLaunchTooLarge;
+  return hipLaunchKernel(kern, dim3(G), dim3(256), args, dyn, st);
+}
+
 template <typename T, typename S, int D>
 static hipError_t gmres_launch(CoopGmres a, size_t coef_bytes, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x,
                                const double* mu_dev, CoopGmresWs ws, hipStream_t st) {
@@ -1006,7 +1024,7 @@ static hipError_t gmres_launch(CoopGmres a, size_t coef_bytes, const SP<S>* Dc, 
     if (e != hipSuccess) return e;
   }
   void* args[] = {&a, (void*)&Dc, (void*)&b, (void*)&x, (void*)&mu_dev, &ws};
-  return hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, (unsigned)coef_bytes, st);
+  return launch_resident(kern, G, args, coef_bytes, st);
 }
 
 template <typename S, int D>
@@ -1023,7 +1041,7 @@ static hipError_t site_gmres_launch(const SiteGmres& a, const SP<S>* Dc, const c
   SiteGmres aa = a;
   SiteGmresWs ww = ws;
   void* args[] = {&aa, (void*)&Dc, (void*)&b, (void*)&x, (void*)&mu_dev, &ww};
-  return hipLaunchCooperativeKernel(kern, dim3((unsigned)a.g.V), dim3(256), args, (unsigned)dyn, st);
+  return launch_resident(kern, (int)a.g.V, args, dyn, st);
 }
 
 // one right-hand side, FP32 over a 16-bit D_c, at most 256 sites

@@ -369,7 +369,7 @@ void Ctx::ensure(int nrhs) {
   mu_dev.alloc(cap);
   abstol_dev.alloc(cap);
   red_partial.alloc(1024 * (size_t)cap);
-  red_out.alloc(cap);
+  red_out.alloc(2 * (size_t)cap);   // room for one complex result per right-hand side
   bool flex = par.nlevels >= 1;
   if (par.precision == TMAMG_FP64) {
     K64.ensure(n, par.restart, cap, flex, st);

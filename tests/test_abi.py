@@ -1,0 +1,156 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/tmamg.h declares, its structs have the layout a C compiler gives
+them, the Python mirrors agree, and the host-side argument checks answer
+before any GPU work.  No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tmamg.h")
+
+
+@pytest.fixture(scope="module")
+def tm():
+    from paper_1710_06198_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1710_06198_amd import build
+        build.build(verbose=False)
+    import paper_1710_06198_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tmamg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve", "tmamg_solve_shifted",
+              "tmamg_force", "tmamg_apply", "tmamg_destroy", "tmamg_last_error", "tmamg_default_params"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(tm):
+    lib = ctypes.CDLL(tm.binding.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", tm.binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (tmamg_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "tmamg.h"
+#define F(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("tmamg_lattice size %zu\n", sizeof(tmamg_lattice));
+  printf("tmamg_params size %zu\n", sizeof(tmamg_params));
+  printf("tmamg_info size %zu\n", sizeof(tmamg_info));
+  F(tmamg_lattice, dims) F(tmamg_lattice, t_antiperiodic)
+  F(tmamg_params, nlevels) F(tmamg_params, agg) F(tmamg_params, nv) F(tmamg_params, setup_iters)
+  F(tmamg_params, init_smooth) F(tmamg_params, sap_block1) F(tmamg_params, sap_sweeps) F(tmamg_params, mr_steps)
+  F(tmamg_params, l2_iters) F(tmamg_params, l2_tol) F(tmamg_params, coarsest_iters) F(tmamg_params, coarsest_tol)
+  F(tmamg_params, restart) F(tmamg_params, max_iter) F(tmamg_params, precision) F(tmamg_params, storage)
+  F(tmamg_params, inner_tol) F(tmamg_params, seed)
+  F(tmamg_info, status) F(tmamg_info, outer_iters) F(tmamg_info, cycles) F(tmamg_info, true_rel_resid)
+  F(tmamg_info, t_setup_s) F(tmamg_info, t_solve_s)
+  printf("enum %d %d %d %d %d %d %d\n", TMAMG_OK, TMAMG_NOT_CONVERGED, TMAMG_EINVAL, TMAMG_ENOMEM, TMAMG_EHIP,
+         TMAMG_ENUMERIC, TMAMG_ESTATE);
+  printf("prec %d %d store %d %d %d %d\n", TMAMG_FP64, TMAMG_MIXED, TMAMG_STORE_FP64, TMAMG_STORE_FP32,
+         TMAMG_STORE_BF16, TMAMG_STORE_FP16);
+  printf("ops %d %d %d %d %d %d %d %d\n", TMAMG_OP_D64, TMAMG_OP_D32, TMAMG_OP_PROLONG, TMAMG_OP_RESTRICT,
+         TMAMG_OP_DC, TMAMG_OP_SAP, TMAMG_OP_PREC, TMAMG_OP_COARSEST);
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_c_compiler(tm, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines()
+    b = tm.binding
+    classes = {"tmamg_lattice": b.Lattice, "tmamg_params": b.Params, "tmamg_info": b.Info}
+    for ln in lines:
+        parts = ln.split()
+        if parts[0] in classes and parts[1] == "size":
+            assert ctypes.sizeof(classes[parts[0]]) == int(parts[2]), ln
+        elif parts[0] in classes:
+            assert getattr(classes[parts[0]], parts[1]).offset == int(parts[2]), ln
+        elif parts[0] == "enum":
+            assert [int(v) for v in parts[1:]] == [0, 1, -1, -2, -3, -4, -5]
+        elif parts[0] == "prec":
+            assert (int(parts[1]), int(parts[2])) == (b.FP64, b.MIXED)
+            assert [int(v) for v in parts[4:]] == [b.STORE_FP64, b.STORE_FP32, b.STORE_BF16, b.STORE_FP16]
+        elif parts[0] == "ops":
+            assert [int(v) for v in parts[1:]] == [b.OP_D64, b.OP_D32, b.OP_PROLONG, b.OP_RESTRICT, b.OP_DC,
+                                                   b.OP_SAP, b.OP_PREC, b.OP_COARSEST]
+
+
+def test_default_params(tm):
+    p = tm.default_params()
+    assert p.nlevels == 2 and list(p.agg[0]) == [4, 4, 4, 4] and p.nv[0] == 12
+    assert p.setup_iters == 3 and p.sap_sweeps[0] == 4 and p.mr_steps == 4 and p.restart == 30
+    assert p.precision == tm.FP64
+    q = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(24, 32), sap_block1=(3, 3, 3, 3))
+    assert q.nlevels == 3 and list(q.agg[1]) == [2, 2, 2, 2] and list(q.nv) == [24, 32]
+    assert list(q.sap_block1) == [3, 3, 3, 3]
+
+
+def _create(tm, dims, **kw):
+    b = tm.binding
+    lat = b.Lattice()
+    for m in range(4):
+        lat.dims[m] = dims[m]
+    lat.t_antiperiodic = 1
+    p = tm.default_params(**kw)
+    h = ctypes.c_void_p()
+    st = b.load().tmamg_create(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(p), None)
+    msg = b.load().tmamg_last_error()
+    return st, h, msg.decode() if isinstance(msg, bytes) else str(msg)
+
+
+@pytest.mark.parametrize("dims,kw,needle", [
+    ((6, 8, 8, 8), {}, "multiples of the first aggregate"),
+    ((8, 8, 8, 8), {"nlevels": 4}, "nlevels"),
+    ((8, 8, 8, 8), {"restart": 0}, "restart"),
+    ((8, 8, 8, 8), {"precision": 1, "storage": 0}, "mixed precision"),
+    ((12, 8, 8, 8), {}, "even number of fine blocks"),
+    ((8, 8, 8, 8), {"agg": ((2, 2, 2, 2), (1, 1, 1, 1))}, "64, 128, 192 or 256"),
+    ((16, 16, 16, 16), {"nlevels": 3, "agg": ((4, 4, 4, 4), (3, 2, 2, 2))}, "second aggregate"),
+])
+def test_create_rejects_bad_parameters(tm, dims, kw, needle):
+    st, h, msg = _create(tm, dims, **kw)
+    assert st == -1, (st, msg)
+    assert not h.value
+    assert needle in msg
+
+
+def test_null_arguments(tm):
+    lib = tm.binding.load()
+    assert lib.tmamg_create(None, None, None, None) == -1
+    assert lib.tmamg_default_params(None) == -1
+    assert lib.tmamg_solve(None, None, None, 1, None, 1e-10, None) == -1
+    lib.tmamg_destroy(None)   # no-op
+
+
+def test_missing_library_fails_loudly(tm):
+    b = tm.binding
+    saved = b._lib
+    try:
+        b._lib = None
+        with pytest.raises(RuntimeError, match="not built"):
+            b.load(os.path.join(ROOT, "no_such_dir", "libtmamg.so"))
+    finally:
+        b._lib = saved
