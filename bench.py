@@ -25,6 +25,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_fp32_c2_traffic.md")
+STENCIL_SOURCES = ("fine_op.hip", "su3.h", "common.h")
+
+
+def stencil_traffic(workload_name):
+    """HBM bytes per stencil launch from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel's readings), or
+    None when the record is for another workload or the stencil sources
+    changed since the counters were taken."""
+    import hashlib
+    if workload_name != "c2" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = None
+    for line in open(TRAFFIC_RECORD):
+        if line.startswith("traffic_record:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1710_06198_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha16"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def log(*a):
@@ -97,6 +121,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the stencil and copy timing loops (for hardware-counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -122,6 +148,13 @@ def main():
         return solver.solve(b, x, tol=w.tol)
 
     mixed = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED), stream=stream)
+    if args.kernels_only:
+        mixed.setup(U, kappa, w.csw, w.mu)
+        d_ms = mixed.time_kernel(tm.K_DSLASH32, 1, 10)
+        c_ms = mixed.time_kernel(tm.K_COPY, 1, 10)
+        print(json.dumps({"dslash_fp32_ms": d_ms, "copy_512MiB_ms": c_ms, "sites": w.volume}), flush=True)
+        mixed.close()
+        return 0
     for i in range(args.warmup):
         log(f"[bench] warmup {i}")
         info = job(mixed)
@@ -198,7 +231,8 @@ def main():
         "speedup_vs_fp64": (fp64["total_s"] / (ms / 1e3)) if fp64 else None,
         "kernel_ms": kern,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stencil_traffic(w.name),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_dslash<float> (fine stencil)", "bytes_per_site": bytes_site, "sites": V},
         "cpu_baseline": cpu,
     }

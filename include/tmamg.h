@@ -178,7 +178,8 @@ enum {
   TMAMG_K_PROLONG0 = 4,   /* level 1 -> fine */
   TMAMG_K_DC1 = 5,        /* coarse operator, level 1 */
   TMAMG_K_DC2 = 6,        /* coarse operator, level 2 */
-  TMAMG_K_SAP1 = 7        /* coarse SAP on level 1, one colour */
+  TMAMG_K_SAP1 = 7,       /* coarse SAP on level 1, one sweep (both colours) */
+  TMAMG_K_COPY = 8        /* plain device copy of 512 MiB (counter calibration) */
 };
 tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms);
 

@@ -7,4 +7,4 @@ package only marshals arguments to it (see binding.py) and builds it
 from .binding import (Solver, Params, Info, default_params, load, TmamgError,  # noqa: F401
                       FP64, MIXED, STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16,
                       OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST, EXPORTS,
-                      K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1)
+                      K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY)

@@ -23,7 +23,7 @@ EXPORTS = [
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
     "tmamg_time_kernel", "tmamg_last_error",
 ]
-K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1 = range(8)
+K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY = range(9)
 
 
 class Lattice(ctypes.Structure):

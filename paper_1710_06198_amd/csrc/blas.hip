@@ -199,6 +199,18 @@ void launch_add_to64(const cplx<T>* x, cplx<double>* y, long count, hipStream_t 
   hipLaunchKernelGGL(k_add_to64<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, count);
 }
 
+// plain streaming copy (16-byte accesses); the reference kernel of known
+// traffic for counter calibration
+__global__ void k_copy16(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4*)in, (uint4*)out, n);
+}
+
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
   size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0u;

@@ -148,10 +148,7 @@ double Hier<T, S>::time_kernel(int kernel, int nrhs, int reps) {
       b.alloc((size_t)nrhs * n);
       launch_random<T>(a.p, (long)nrhs * n, 15, st);
       launch_fill_zero(b.p, b.bytes(), st);
-      return time_launches(st, reps, [&]() {
-        launch_sap_coarse<T, S>(g1, d1, p.sap_block1, Dc1.p, a.p, b.p, nrhs, mu.p, blist1[0].p, blist1[0].count,
-                                p.mr_steps, st);
-      });
+      return time_launches(st, reps, [&]() { sap_level1(a.p, b.p, nrhs, mu.p, 1); });
     }
     default:
       throw TmError{TMAMG_EINVAL, "unknown kernel id"};
@@ -661,6 +658,14 @@ double Ctx::time_kernel(int kernel, int nrhs, int reps) {
     launch_random<float>(a.p, (long)nrhs * n0, 22, st);
     FineOp<float> o = op32();
     return time_launches(st, reps, [&]() { launch_dslash<float>(o, a.p, b.p, nrhs, mu_dev.p, st); });
+  }
+  if (kernel == TMAMG_K_COPY) {
+    const size_t bytes = (size_t)512 << 20;
+    DevArr<unsigned char> a, b;
+    a.alloc(bytes);
+    b.alloc(bytes);
+    launch_fill_zero(a.p, bytes, st);
+    return time_launches(st, reps, [&]() { launch_copy16(a.p, b.p, bytes, st); });
   }
   if (!have_setup) throw TmError{TMAMG_ESTATE, "timing before setup"};
   return hier->time_kernel(kernel, nrhs, reps);
