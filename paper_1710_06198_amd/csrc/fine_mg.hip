@@ -3,6 +3,7 @@
 // fine test vectors, and the Galerkin coarse operator D_c = P^dag D P
 // (Sec. 1.1).  Aggregates are the blocks of the fine site ordering.
 #include "kernels.h"
+#include "solver.h"
 #include "su3.h"
 
 template <typename S> using SP = typename Store<S>::pair;
@@ -149,13 +150,85 @@ void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* 
   hipLaunchKernelGGL((k_gs_fine<T, S>), dim3(g.nblocks, 2), dim3(g.bvol), 0, st, g, tv, nv, P64, P);
 }
 
-// ------------------------------------------------------------------ Galerkin (K8), fine -> first coarse level
-// Workgroup per (aggregate y, coarse column cc = s'*nv + j), one thread per
-// site.  w = column cc of P on y.  Part 0: the aggregate-internal part of D
-// (clover + hops that stay in y) gives D_c[y][0][cc].  Part 1+2mu: forward
-// hops from sites x' = x - mu outside y's lower face pull w(x); they land in
-// y - mu's block 1+2mu.  Part 2+2mu: backward hops at x'' = x + mu from y's
-// upper face land in y + mu's block 2+2mu.
+// ------------------------------------------------------------------ Galerkin, fine -> first coarse level
+// D_c = P^dag D P, block by block: D_c[r][part] (part 0 self, 1+2mu the
+// neighbour r+mu, 2+2mu the neighbour r-mu) = sum over the sites x of the
+// receiving aggregate r of P(x)^dag Z_part(x), with
+//   Z_0(x)      = A(x) P_r(x) + hops of D from x to sites of r,
+//   Z_{mu,+}(x) = hop of D from x to x+mu, for x on r's upper mu face,
+//   Z_{mu,-}(x) = hop of D from x to x-mu, for x on r's lower mu face,
+// where P_r is P restricted to aggregate r (all 2 N_v columns).
+// Two kernels per chunk of CB columns:
+//   k_galerkin_z    one workgroup per (source aggregate y, column), one
+//                   thread per site: applies D to the column and writes every
+//                   piece to the receiving aggregate's slot in Z;
+//   k_galerkin_proj one workgroup per (receiving aggregate, part): the
+//                   (2N_v x CB) block P^dag Z, sites in LDS tiles.
+// Z layout: [aggregate][part][column in chunk][12][site of the part's
+// region], regions of bvol (self) and bvol / B_mu (faces) sites.  Both
+// kernels map workgroups so that all work of one aggregate runs on one XCD.
+struct GalerkinZ {
+  int regoff[9];   // site offset of each part's region in an aggregate's slot
+  int regsz[9];    // sites per region
+  int za;          // sites per aggregate slot (sum of regsz)
+  int c0, cb;      // column chunk
+};
+
+TM_HD GalerkinZ galerkin_layout(const FineGeom& g, int c0, int cb) {
+  GalerkinZ z;
+  int off = 0;
+  for (int p = 0; p < 9; ++p) {
+    const int sz = p == 0 ? g.bvol : g.bvol / g.B[(p - 1) >> 1];
+    z.regoff[p] = off;
+    z.regsz[p] = sz;
+    off += sz;
+  }
+  z.za = off;
+  z.c0 = c0;
+  z.cb = cb;
+  return z;
+}
+
+// index of a face site (local coordinates lc) inside the mu-face region:
+// lexicographic over the three other directions
+TM_D int face_index(const FineGeom& g, const int lc[4], int mu) {
+  int r = 0, st = 1;
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    r += lc[nu] * st;
+    st *= g.B[nu];
+  }
+  return r;
+}
+// inverse: local index (inside the aggregate) of face site r on the face lc_mu = cm
+TM_D int face_local(const FineGeom& g, int r, int mu, int cm) {
+  int lc[4];
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) {
+      lc[nu] = cm;
+      continue;
+    }
+    lc[nu] = r % g.B[nu];
+    r /= g.B[nu];
+  }
+  return ((lc[3] * g.B[2] + lc[2]) * g.B[1] + lc[1]) * g.B[0] + lc[0];
+}
+
+TM_D int block_index(const FineGeom& g, const int bc[4]) {
+  return ((bc[3] * g.NB[2] + bc[2]) * g.NB[1] + bc[1]) * g.NB[0] + bc[0];
+}
+
+// workgroup w of a grid of ceil(n/8)*8*m: the m work items of one
+// aggregate share w % 8, i.e. one XCD
+TM_D bool xcd_decode(int w, int n, int m, int& agg, int& item) {
+  const int x = w & 7, rest = w >> 3;
+  item = rest % m;
+  agg = (rest / m) * 8 + x;
+  return agg < n;
+}
+
 template <int MU, typename T>
 TM_D void lds_spinor(const cplx<T>* wl, int bv, int sp, int nl, cplx<T>* pn) {
 #pragma unroll
@@ -180,6 +253,9 @@ TM_D void intra_hops(const FineOp<T>& op, const cplx<T>* wl, int sp, long s, int
   }
 }
 
+// the hop that carries w(x) out of y through its mu face, for source sites
+// on that face: step > 0 is the forward hop at x - mu (lower face of y),
+// step < 0 the backward hop at x + mu (upper face of y)
 template <int MU, typename T>
 TM_D bool face_hop(const FineOp<T>& op, int step, long s, const int c[4], const cplx<T>* wx, cplx<T>* v, long& tgt_site) {
   const FineGeom& g = op.g;
@@ -188,47 +264,40 @@ TM_D bool face_hop(const FineOp<T>& op, int step, long s, const int c[4], const 
   for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
   if (step > 0) {
     if (lc != 0) return false;
-    tgt_site = fine_neighbour(g, s, c, MU, -1);      // x' = x - mu, forward hop at x' pulls w(x)
+    tgt_site = fine_neighbour(g, s, c, MU, -1);
     M3<T> u = load_link(op.links, MU, tgt_site, g.V);
     hop_fwd<MU>(u, wx, v);
   } else {
     if (lc != g.B[MU] - 1) return false;
-    tgt_site = fine_neighbour(g, s, c, MU, +1);      // x'' = x + mu, backward hop at x'' pulls w(x)
+    tgt_site = fine_neighbour(g, s, c, MU, +1);
     M3<T> u = load_link(op.links, MU, s, g.V);
     hop_bwd<MU>(u, wx, v);
   }
   return true;
 }
 
-// LDS: w (the column's chirality half, 6 x bv), u (one chirality half of the
-// pushed vectors, 6 x bv), the receiving site of every source, a reduction
-// buffer: 48 bv + 8 bv + 4 KB bytes in FP64 (54 KB for 256-site aggregates).
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_galerkin_fine(FineOp<T> op, const SP<S>* __restrict__ P, int nv,
-                                                       SP<S>* Dc) {
-  extern __shared__ unsigned char smem_raw[];
+__global__ void __launch_bounds__(256) k_galerkin_z(FineOp<T> op, const SP<S>* __restrict__ P, int nv, GalerkinZ zl,
+                                                    cplx<T>* __restrict__ Z) {
+  __shared__ cplx<T> wl[6 * 256];
   const FineGeom& g = op.g;
   const long V = g.V;
   const int bv = g.bvol;
-  cplx<T>* wl = reinterpret_cast<cplx<T>*>(smem_raw);   // [6][bv]
-  cplx<T>* u = wl + 6 * bv;                             // [6][bv]
-  long* tgt = reinterpret_cast<long*>(u + 6 * bv);     // [bv]
-  cplx<T>* red = reinterpret_cast<cplx<T>*>(tgt + bv); // [256]
-  const int y = blockIdx.x, cc = blockIdx.y;
-  const int sp = cc / nv, jv = cc - sp * nv;
+  int y, jl;
+  if (!xcd_decode(blockIdx.x, g.nblocks, zl.cb, y, jl)) return;
+  const int cc = zl.c0 + jl, sp = cc / nv, jv = cc - sp * nv;
   const int loc = threadIdx.x;
   const long s = (long)y * bv + loc;
-  const int no = 2 * nv;
   int c[4];
   fine_coords(g, s, c);
   cplx<T> wx[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    bool in_s = (k < 6) == (sp == 0);
+    const bool in_s = (k < 6) == (sp == 0);
     wx[k] = in_s ? Store<S>::template ld<T>(P + (long)jv * 12 * V + tsite((unsigned)s, 12) + k * FT) : mk<T>(0, 0);
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) wl[k * bv + loc] = wx[sp * 6 + k];
+  for (int k = 0; k < 6; ++k) wl[k * bv + loc] = sp ? wx[6 + k] : wx[k];
   __syncthreads();
   int yc[4];
   {
@@ -238,74 +307,150 @@ __global__ void __launch_bounds__(256) k_galerkin_fine(FineOp<T> op, const SP<S>
     yc[2] = b % g.NB[2];
     yc[3] = b / g.NB[2];
   }
+  const long slot = (long)12 * zl.cb * zl.za;   // elements per aggregate
+#pragma unroll 1
   for (int part = 0; part < 9; ++part) {
     cplx<T> v[12];
-    long ts = -1;
+    long recv = y;
+    int r = loc;
+    bool on = true;
     if (part == 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
       clover_block_mv(op.clover, (unsigned)s, V, wx, v);
       clover_block_mv(op.clover + 36 * V, (unsigned)s, V, wx + 6, v + 6);
+      compiler_fence(v);
       intra_hops<0>(op, wl, sp, s, loc, c, v);
+      compiler_fence(v);
       intra_hops<1>(op, wl, sp, s, loc, c, v);
+      compiler_fence(v);
       intra_hops<2>(op, wl, sp, s, loc, c, v);
+      compiler_fence(v);
       intra_hops<3>(op, wl, sp, s, loc, c, v);
-      ts = s;
     } else {
       const int mu = (part - 1) >> 1;
       const int step = ((part - 1) & 1) ? -1 : 1;
-      bool on = false;
+      long ts = 0;
       switch (mu) {
         case 0: on = face_hop<0>(op, step, s, c, wx, v, ts); break;
         case 1: on = face_hop<1>(op, step, s, c, wx, v, ts); break;
         case 2: on = face_hop<2>(op, step, s, c, wx, v, ts); break;
         default: on = face_hop<3>(op, step, s, c, wx, v, ts); break;
       }
-      if (!on) ts = -1;
-    }
-    tgt[loc] = ts;
-    long recv = y;
-    if (part > 0) {
-      const int mu = (part - 1) >> 1;
-      const int step = ((part - 1) & 1) ? -1 : 1;
-      int rc[4] = {yc[0], yc[1], yc[2], yc[3]};
-      rc[mu] = (rc[mu] - step + g.NB[mu]) % g.NB[mu];
-      recv = ((long)(rc[3] * g.NB[2] + rc[2]) * g.NB[1] + rc[1]) * g.NB[0] + rc[0];
-    }
-    // project onto P at the receiving sites, one chirality at a time
-    for (int sc = 0; sc < 2; ++sc) {
+      if (on) {
+        int rc[4];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) u[k * bv + loc] = v[sc * 6 + k];
-      __syncthreads();
-      const int G = max(1, (int)blockDim.x / nv);
-      const int t = threadIdx.x, iv = t % nv, grp = t / nv;
-      cplx<T> acc = mk<T>(0, 0);
-      if (grp < G) {
-        const SP<S>* Pi = P + (long)iv * 12 * V + (long)sc * 6 * FT;
-        for (int l = grp; l < bv; l += G) {
-          long tsl = tgt[l];
-          if (tsl < 0) continue;
+        for (int m = 0; m < 4; ++m) rc[m] = m == mu ? (yc[m] - step + g.NB[m]) % g.NB[m] : yc[m];
+        recv = block_index(g, rc);
+        int tc[4];
+        fine_coords(g, ts, tc);
+        int lc[4];
 #pragma unroll
-          for (int k = 0; k < 6; ++k)
-            cfmac(acc, Store<S>::template ld<T>(Pi + tsite((unsigned)tsl, 12) + k * FT), u[k * bv + l]);
-        }
+        for (int m = 0; m < 4; ++m) lc[m] = tc[m] % g.B[m];
+        r = face_index(g, lc, mu);
       }
-      red[t] = acc;
-      __syncthreads();
-      if (t < nv) {
-        cplx<T> sum = mk<T>(0, 0);
-        for (int k = 0; k < G; ++k) sum += red[k * nv + t];
-        Store<S>::st(Dc + ((recv * 9 + part) * (long)no + cc) * no + sc * nv + t, sum);
-      }
-      __syncthreads();
+    }
+    if (on) {
+      cplx<T>* zo = Z + recv * slot + (long)zl.regoff[part] * 12 * zl.cb + (long)jl * 12 * zl.regsz[part] + r;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) zo[(long)k * zl.regsz[part]] = v[k];
     }
   }
 }
+
+// D_c[r][part][c0 + j][i] = sum_x sum_{k in chirality of i} conj(P_i(x)_k) Z(x)_{k j}
+// thread: column j = t % 16 of the chunk, rows i = t / 16 + 16 a
 template <typename T, typename S>
-void launch_galerkin_fine(const FineOp<T>& op, const SP<S>* P, int nv, SP<S>* Dc, hipStream_t st) {
-  const int bv = op.g.bvol;
-  size_t sh = 12 * (size_t)bv * sizeof(cplx<T>) + bv * sizeof(long) + 256 * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_galerkin_fine<T, S>), dim3(op.g.nblocks, 2 * nv), dim3(bv), sh, st, op, P, nv, Dc);
+__global__ void __launch_bounds__(256) k_galerkin_proj(FineGeom g, const SP<S>* __restrict__ P, int nv, GalerkinZ zl,
+                                                       const cplx<T>* __restrict__ Z, SP<S>* __restrict__ Dc) {
+  constexpr int TS = sizeof(T) == 4 ? 8 : 4;   // sites per LDS tile
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* Pt = reinterpret_cast<cplx<T>*>(smem_raw);   // [TS][12][nv]
+  cplx<T>* Zt = Pt + TS * 12 * nv;                      // [TS][12][cb]
+  int r, part;
+  if (!xcd_decode(blockIdx.x, g.nblocks, 9, r, part)) return;
+  const long V = g.V;
+  const int no = 2 * nv, cb = zl.cb, rs = zl.regsz[part];
+  const int t = threadIdx.x, jg = t & 15, ig = t >> 4;
+  const int na = (no + 15) / 16;
+  int mu = 0, cm = 0;
+  if (part > 0) {
+    mu = (part - 1) >> 1;
+    cm = ((part - 1) & 1) ? 0 : g.B[mu] - 1;   // upper face for the forward neighbour
+  }
+  const cplx<T>* zr = Z + (long)r * 12 * cb * zl.za + (long)zl.regoff[part] * 12 * cb;
+  cplx<T> acc[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) acc[a] = mk<T>(0, 0);
+  for (int x0 = 0; x0 < rs; x0 += TS) {
+    const int nx = min(TS, rs - x0);
+    for (int e = t; e < nx * 12 * nv; e += 256) {
+      const int x = e % nx, rem = e / nx, k = rem % 12, iv = rem / 12;
+      const int loc = part == 0 ? x0 + x : face_local(g, x0 + x, mu, cm);
+      const long site = (long)r * g.bvol + loc;
+      Pt[(x * 12 + k) * nv + iv] = Store<S>::template ld<T>(P + (long)iv * 12 * V + tsite((unsigned)site, 12) + k * FT);
+    }
+    for (int e = t; e < nx * 12 * cb; e += 256) {
+      const int x = e % nx, rem = e / nx, k = rem % 12, j = rem / 12;
+      Zt[(x * 12 + k) * cb + j] = zr[(long)(j * 12 + k) * rs + x0 + x];
+    }
+    __syncthreads();
+    if (jg < cb) {
+#pragma unroll 1
+      for (int x = 0; x < nx; ++x) {
+        cplx<T> zk[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) zk[k] = Zt[(x * 12 + k) * cb + jg];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int i = ig + 16 * a;
+          if (a < na && i < no) {
+            const int sc = i >= nv ? 1 : 0, iv = i - sc * nv;
+            const cplx<T>* pr = Pt + (x * 12 + 6 * sc) * nv + iv;
+#pragma unroll
+            for (int kk = 0; kk < 6; ++kk) cfmac(acc[a], pr[kk * nv], sc ? zk[6 + kk] : zk[kk]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (jg < cb) {
+    const int j = zl.c0 + jg;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int i = ig + 16 * a;
+      if (a < na && i < no) Store<S>::st(Dc + (((long)r * 9 + part) * no + j) * no + i, acc[a]);
+    }
+  }
+}
+
+size_t galerkin_ws_per_column(const FineGeom& g) {
+  const GalerkinZ z = galerkin_layout(g, 0, 1);
+  return (size_t)g.nblocks * 12 * z.za;
+}
+
+// columns per chunk for a Z workspace of ws_elems complex values
+static int galerkin_chunk(const FineGeom& g, int nv, size_t ws_elems) {
+  const size_t per_col = galerkin_ws_per_column(g);
+  return (int)std::max<size_t>(1, std::min<size_t>({(size_t)16, (size_t)(2 * nv), ws_elems / per_col}));
+}
+
+template <typename T, typename S>
+void launch_galerkin_fine(const FineOp<T>& op, const SP<S>* P, int nv, SP<S>* Dc, cplx<T>* zws, size_t zws_elems,
+                          hipStream_t st) {
+  const FineGeom& g = op.g;
+  const int no = 2 * nv;
+  if (zws_elems < galerkin_ws_per_column(g)) throw TmError{TMAMG_EINVAL, "Galerkin workspace too small"};
+  const int cb = galerkin_chunk(g, nv, zws_elems);
+  const int n8 = (g.nblocks + 7) / 8 * 8;
+  constexpr int TS = sizeof(T) == 4 ? 8 : 4;
+  const size_t lds = (size_t)TS * 12 * (nv + cb) * sizeof(cplx<T>);
+  for (int c0 = 0; c0 < no; c0 += cb) {
+    const GalerkinZ zl = galerkin_layout(g, c0, std::min(cb, no - c0));
+    hipLaunchKernelGGL((k_galerkin_z<T, S>), dim3((unsigned)(n8 * zl.cb)), dim3(g.bvol), 0, st, op, P, nv, zl, zws);
+    hipLaunchKernelGGL((k_galerkin_proj<T, S>), dim3((unsigned)(n8 * 9)), dim3(256), lds, st, g, P, nv, zl, zws, Dc);
+  }
 }
 
 // ------------------------------------------------------------------ noise
@@ -357,7 +502,8 @@ void launch_store_from64(const cplx<double>* in, SP<S>* out, long count, hipStre
   template void launch_prolong_fine<T, S>(const FineGeom&, const SP<S>*, int, const cplx<T>*, cplx<T>*, int,     \
                                           hipStream_t);                                                          \
   template void launch_gs_fine<T, S>(const FineGeom&, const cplx<T>*, int, cplx<double>*, SP<S>*, hipStream_t);  \
-  template void launch_galerkin_fine<T, S>(const FineOp<T>&, const SP<S>*, int, SP<S>*, hipStream_t);
+  template void launch_galerkin_fine<T, S>(const FineOp<T>&, const SP<S>*, int, SP<S>*, cplx<T>*, size_t,  \
+                                           hipStream_t);
 INST_TS(double, double)
 INST_TS(float, float)
 INST_TS(float, __hip_bfloat16)

@@ -173,17 +173,8 @@ void launch_clover_build(const FineGeom& g, const cplx<double>* links64, const C
                      clov32);
 }
 
-// ------------------------------------------------------------------ stencil (K1)
-// Compiler-only fence (emits no instruction): memory accesses may not move
-// across it and the accumulator must be fully computed at this point, so
-// each hopping direction's loads and arithmetic stay together.
-template <typename T>
-TM_D void compiler_fence(cplx<T>* acc) {
-#pragma unroll
-  for (int k = 0; k < 12; ++k) __asm__ __volatile__("" : "+v"(acc[k].re), "+v"(acc[k].im));
-  __asm__ __volatile__("" ::: "memory");
-}
 
+// ------------------------------------------------------------------ stencil
 // Every access goes through a wave-uniform base (field + component * V) and
 // the lane's 32-bit site index.
 template <typename T>

@@ -145,10 +145,13 @@ void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* 
 template <typename T, typename S>
 void launch_gs_coarse(const CoarseGeom& g, int d, const int agg[4], const cplx<T>* tv, int nv, cplx<double>* P64,
                       typename Store<S>::pair* P, hipStream_t st);
-// Galerkin D_c = P^dag D P (without the twisted-mass term)
+// Galerkin D_c = P^dag D P (without the twisted-mass term).  zws: workspace
+// of zws_elems complex values, at least galerkin_ws_per_column(g); larger
+// workspaces process more columns per pass (up to 16).
+size_t galerkin_ws_per_column(const FineGeom& g);
 template <typename T, typename S>
 void launch_galerkin_fine(const FineOp<T>& op, const typename Store<S>::pair* P, int nv,
-                          typename Store<S>::pair* Dc, hipStream_t st);
+                          typename Store<S>::pair* Dc, cplx<T>* zws, size_t zws_elems, hipStream_t st);
 template <typename T, typename S>
 void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const typename Store<S>::pair* Dc1,
                             const typename Store<S>::pair* P, int nv, typename Store<S>::pair* Dc2, hipStream_t st);

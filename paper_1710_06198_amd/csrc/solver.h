@@ -141,6 +141,7 @@ struct Hier : HierBase {
   CoarseGeom g1{}, g2{};
   DevArr<int> blist0[2], blist1[2];
   DevArr<cplx<T>> tv0, tv1, tvtmp, tmp1;
+  DevArr<cplx<T>> gal_ws;   // fine Galerkin workspace (columns of D P per receiving aggregate)
   DevArr<SPair> P0, P1, Dc1, Dc2;
   DevArr<cplx<double>> P64;
   DevArr<cplx<T>> rc1, ec1, rc2, ec2;

@@ -371,7 +371,13 @@ void Hier<T, S>::build_inner(int l) {
   const tmamg_params& p = c->par;
   if (l == 0) {
     launch_gs_fine<T, S>(c->fg, tv0.p, nv0, P64.p, P0.p, st);
-    launch_galerkin_fine<T, S>(fop, P0.p, nv0, Dc1.p, st);
+    if (!gal_ws.p) {
+      // up to 16 columns per pass within 4 GiB
+      const size_t per_col = galerkin_ws_per_column(c->fg);
+      const size_t cap_cols = std::max<size_t>(1, ((size_t)4 << 30) / (per_col * sizeof(cplx<T>)));
+      gal_ws.alloc(per_col * std::min<size_t>({cap_cols, (size_t)16, (size_t)(2 * nv0)}));
+    }
+    launch_galerkin_fine<T, S>(fop, P0.p, nv0, Dc1.p, gal_ws.p, gal_ws.n, st);
   } else {
     launch_gs_coarse<T, S>(g1, d1, p.agg[1], tv1.p, nv1, P64.p, P1.p, st);
     launch_galerkin_coarse<T, S>(g1, d1, p.agg[1], Dc1.p, P1.p, nv1, Dc2.p, st);

@@ -191,3 +191,14 @@ TM_D void clover_block_mv(const T* __restrict__ cl, unsigned s, long V, const cp
     acc[i] += row;
   }
 }
+
+// Compiler-only fence (emits no instruction): memory accesses may not move
+// across it and the accumulator must be fully computed at this point, so
+// each hopping direction's loads and arithmetic stay together.
+template <typename T>
+TM_D void compiler_fence(cplx<T>* acc) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) __asm__ __volatile__("" : "+v"(acc[k].re), "+v"(acc[k].im));
+  __asm__ __volatile__("" ::: "memory");
+}
+
