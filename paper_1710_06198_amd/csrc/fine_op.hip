@@ -185,13 +185,13 @@ TM_D void load_spinor(const cplx<T>* __restrict__ f, unsigned s, long V, cplx<T>
 }
 
 // acc = (A + i mu g5) psi
-template <typename T>
+template <typename T, bool STREAM = false>
 TM_D void site_diag(const FineOp<T>& op, unsigned s, T mu, const cplx<T>* psi, cplx<T>* acc) {
   const long V = op.g.V;
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
-  clover_block_mv(op.clover, s, V, psi, acc);
-  clover_block_mv(op.clover + 36 * V, s, V, psi + 6, acc + 6);
+  clover_block_mv<T, STREAM>(op.clover, s, V, psi, acc);
+  clover_block_mv<T, STREAM>(op.clover + 36 * V, s, V, psi + 6, acc + 6);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     acc[k] += mu * times_i(psi[k]);
@@ -235,16 +235,96 @@ TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsig
   site_hops_dir<3>(op, in, s, c, acc);
 }
 
+// One workgroup per block (one thread per site).  The block's spinors are
+// staged in LDS once; hops that stay in the block read them there.  The
+// backward hop is formed by its source: site y computes
+// U_mu(y)^dag (1 + g_mu) psi(y) as a half spinor with the link it already
+// loaded for its forward hop and leaves it in LDS for y + mu, so every
+// link of the block is read once.  Only hops across the block surface read
+// the neighbouring block's spinor (and, backwards, its link) from memory.
+// Workgroups are mapped so that each XCD sweeps a contiguous range of
+// blocks, keeping neighbouring blocks' faces in the same L2.
+template <int MU, typename T>
+TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* psl, cplx<T>* hb, unsigned s,
+                    int loc, const int c[4], const cplx<T>* psi, cplx<T>* acc) {
+  const FineGeom& g = op.g;
+  const long V = g.V;
+  const int bv = g.bvol, ls = g.lstride[MU], B = g.B[MU];
+  const int lc = c[MU] % B;
+  const bool whole = g.NB[MU] == 1;
+  const M3<T> u = load_link_stream<MU>(op.links, s, V);
+  {
+    // half spinor sent to y + mu: U^dag (1 + g) psi
+    cplx<T> h[6], w[6];
+    project<MU, +1>(psi, h);
+    su3_dmv(u, h, w);
+    su3_dmv(u, h + 3, w + 3);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hb[k * bv + loc] = w[k];
+  }
+  {
+    cplx<T> pn[12];
+    const int nl = lc < B - 1 ? loc + ls : (whole ? loc - (B - 1) * ls : -1);
+    if (nl >= 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pn[k] = psl[k * bv + nl];
+    } else {
+      load_spinor(in, (unsigned)fine_neighbour(g, s, c, MU, +1), V, pn);
+    }
+    hop_fwd<MU>(u, pn, acc);
+  }
+  compiler_fence(acc);
+  __syncthreads();
+  {
+    const int nl = lc > 0 ? loc - ls : (whole ? loc + (B - 1) * ls : -1);
+    if (nl >= 0) {
+      cplx<T> w[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = hb[k * bv + nl];
+      reconstruct<MU, +1>(w, acc);
+    } else {
+      cplx<T> pn[12];
+      const unsigned sb = (unsigned)fine_neighbour(g, s, c, MU, -1);
+      load_spinor(in, sb, V, pn);
+      const M3<T> ub = load_link_u<MU>(op.links, sb, V);
+      hop_bwd<MU>(ub, pn, acc);
+    }
+  }
+  compiler_fence(acc);
+  __syncthreads();   // hb is overwritten by the next direction
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out, const double* __restrict__ mu_dev) {
-  const long V = op.g.V;
-  const unsigned s = blockIdx.x * 256u + threadIdx.x;
-  if (s >= V) return;
+  extern __shared__ unsigned char smem_raw[];
+  const FineGeom& g = op.g;
+  const long V = g.V;
+  const int bv = g.bvol;
+  cplx<T>* psl = reinterpret_cast<cplx<T>*>(smem_raw);   // [12][bv]
+  cplx<T>* hb = psl + 12 * bv;                          // [6][bv]
+  // XCD x (= blockIdx.x % 8) takes blocks [x * per, (x + 1) * per)
+  const int per = (g.nblocks + 7) / 8;
+  const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (blk >= g.nblocks) return;
+  const int loc = threadIdx.x;
+  const unsigned s = (unsigned)blk * bv + loc;
   const int r = blockIdx.y;
+  const cplx<T>* inr = in + (long)r * 12 * V;
   const T mu = (T)mu_dev[r];
-  cplx<T> acc[12];
-  site_dslash(op, in + (long)r * 12 * V, s, mu, acc);
+  int c[4];
+  fine_coords(g, s, c);
+  cplx<T> psi[12], acc[12];
+  load_spinor(inr, s, V, psi);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psl[k * bv + loc] = psi[k];
+  site_diag<T, true>(op, s, mu, psi, acc);
+  compiler_fence(acc);
+  __syncthreads();
+  stage_dir<0>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<1>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<2>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<3>(op, inr, psl, hb, s, loc, c, psi, acc);
   cplx<T>* o = out + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
   for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
@@ -253,8 +333,10 @@ __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __r
 template <typename T>
 void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu_dev,
                    hipStream_t st) {
-  dim3 grid((unsigned)((op.g.V + 255) / 256), nrhs);
-  hipLaunchKernelGGL(k_dslash<T>, grid, dim3(256), 0, st, op, in, out, mu_dev);
+  const int per = (op.g.nblocks + 7) / 8;
+  dim3 grid((unsigned)(8 * per), nrhs);
+  const size_t lds = 18 * (size_t)op.g.bvol * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_dslash<T>, grid, dim3(op.g.bvol), lds, st, op, in, out, mu_dev);
 }
 template void launch_dslash<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                     hipStream_t);

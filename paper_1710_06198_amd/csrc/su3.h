@@ -81,6 +81,24 @@ TM_D M3<T> load_link_u(const cplx<T>* __restrict__ links, unsigned s, long V) {
   return load_link(links, MU, s, V);
 }
 
+// Streaming loads (non-temporal hint) for data used once per kernel, so it
+// does not push out of L2 what neighbouring workgroups still read.
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T> TM_D cplx<T> ld_stream(const cplx<T>* p) {
+  const typename Vec2<T>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename Vec2<T>::type*>(p));
+  return mk<T>(v.x, v.y);
+}
+template <int MU, typename T>
+TM_D M3<T> load_link_stream(const cplx<T>* __restrict__ links, unsigned s, long V) {
+  M3<T> u;
+  const cplx<T>* p = links + (size_t)MU * 9 * V + tsite(s, 9);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u.e[k / 3][k % 3] = ld_stream(p + k * FT);
+  return u;
+}
+
 // w = U h (colour), h a colour vector
 template <typename T> TM_D void su3_mv(const M3<T>& u, const cplx<T>* h, cplx<T>* w) {
 #pragma unroll
@@ -168,12 +186,12 @@ template <int MU, typename T> TM_D void hop_bwd(const M3<T>& u, const cplx<T>* p
 TM_HD int herm_idx(int i, int j) { return i * 6 - i * (i + 1) / 2 + (j - i - 1); }
 
 // acc[0..5] += A v[0..5]; cl is one chirality's tiled 36-component array
-template <typename T>
+template <typename T, bool STREAM = false>
 TM_D void clover_block_mv(const T* __restrict__ cl, unsigned s, long V, const cplx<T>* v, cplx<T>* acc) {
   T a[36];
   const T* p = cl + tsite(s, 36);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) a[k] = p[k * FT];
+  for (int k = 0; k < 36; ++k) a[k] = STREAM ? __builtin_nontemporal_load(p + k * FT) : p[k * FT];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     cplx<T> row = a[i] * v[i];
