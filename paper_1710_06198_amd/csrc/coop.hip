@@ -61,35 +61,47 @@ TM_D int cblk_nbr(const CBlk& cb, C4 lc, int mu, int step) {
 TM_D int hop_mu(int b) { return (b - 1) >> 1; }
 TM_D int hop_step(int b) { return ((b - 1) & 1) ? -1 : 1; }
 
-// Partial products of one site's D rows: red[ks][i] summed over ks gives
-// sum_{b in mask} sum_j Dm[b][j][i] vst[b*D + j].  Ends with a workgroup
+// Partial products of one site's D rows for NR right-hand sides:
+// red[q][ks][i] summed over ks gives
+//   sum_{b in mask} sum_j Dm[b][j][i] vst[q][b*D + j].
+// Every thread owns four consecutive rows and a slice of the 9*D-term sum;
+// one 4-wide load of D_c serves all NR vectors.  Ends with a workgroup
 // barrier.
 template <int D> struct SiteMV {
   static constexpr int RG = D / 4;      // row groups of 4 rows
   static constexpr int KS = 256 / RG;   // slices of the 9*D-term sum
 };
-template <typename T, typename S, int D>
+template <typename T, typename S, int D, int NR = 1>
 TM_D void site_mv(const SP<S>* __restrict__ Dm, const cplx<T>* vst, unsigned mask, cplx<T>* red) {
   constexpr int RG = SiteMV<D>::RG, KS = SiteMV<D>::KS, K = 9 * D;
   const int t = threadIdx.x, rg = t % RG, ks = t / RG;
   if (ks < KS) {
-    cplx<T> a0 = mk<T>(0, 0), a1 = a0, a2 = a0, a3 = a0;
+    cplx<T> a[NR][4];
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[q][i] = mk<T>(0, 0);
 #pragma unroll 4
     for (int k = ks; k < K; k += KS) {
       const int b = k / D;
       if (!((mask >> b) & 1u)) continue;
-      const Quad<S> q = *reinterpret_cast<const Quad<S>*>(Dm + (size_t)k * D + 4 * rg);
-      const cplx<T> v = vst[k];
-      cfma(a0, Store<S>::template cvt<T>(q.e[0]), v);
-      cfma(a1, Store<S>::template cvt<T>(q.e[1]), v);
-      cfma(a2, Store<S>::template cvt<T>(q.e[2]), v);
-      cfma(a3, Store<S>::template cvt<T>(q.e[3]), v);
+      const Quad<S> qd = *reinterpret_cast<const Quad<S>*>(Dm + (size_t)k * D + 4 * rg);
+      cplx<T> m4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m4[i] = Store<S>::template cvt<T>(qd.e[i]);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const cplx<T> v = vst[q * K + k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cfma(a[q][i], m4[i], v);
+      }
     }
-    cplx<T>* o = red + ks * D + 4 * rg;
-    o[0] = a0;
-    o[1] = a1;
-    o[2] = a2;
-    o[3] = a3;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      cplx<T>* o = red + (q * KS + ks) * D + 4 * rg;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = a[q][i];
+    }
   }
   __syncthreads();
 }
@@ -108,63 +120,70 @@ struct SapArgs {
   int nrhs;
 };
 
-// unit u -> (block of the colour, site of the block, right-hand side)
-TM_D void sap_unit(const SapArgs& a, int u, int& bi, int& sl, int& r) {
-  r = u % a.nrhs;
-  const int tt = u / a.nrhs;
+// unit u -> (block of the colour, site of the block, group of NR
+// right-hand sides r0 .. r0 + NR - 1)
+template <int NR>
+TM_D void sap_unit(const SapArgs& a, int u, int& bi, int& sl, int& r0) {
+  const int ng = (a.nrhs + NR - 1) / NR;
+  r0 = (u % ng) * NR;
+  const int tt = u / ng;
   sl = tt % a.cb.nbs;
   bi = tt / a.cb.nbs;
 }
 
-// MR step size of a block: alpha = (q, rho) / (q, q), summed over the
-// block's sites in a fixed order from per-site partials (q.q, q^H rho).
-template <typename T>
-TM_D void block_alpha(const double* __restrict__ part, int bi, int nbs, int nrhs, int r, cplx<T>* alpha_s) {
-  const int t = threadIdx.x;
-  if (t < 64) {
+// MR step sizes of a block for NR right-hand sides: alpha = (q, rho) /
+// (q, q), summed over the block's sites in a fixed order from per-site
+// partials (q.q, q^H rho).  Wave q handles right-hand side r0 + q.
+template <typename T, int NR>
+TM_D void block_alpha(const double* __restrict__ part, int bi, int nbs, int nrhs, int r0, cplx<T>* alpha_s) {
+  const int t = threadIdx.x, q = t >> 6, lane = t & 63;
+  for (int qq = q; qq < NR; qq += 4) {
+    const int r = r0 + qq;
     double sq = 0, sre = 0, sim = 0;
-    for (int q = t; q < nbs; q += 64) {
-      const long o = 3L * (((long)bi * nbs + q) * nrhs + r);
-      sq += part[o];
-      sre += part[o + 1];
-      sim += part[o + 2];
-    }
+    if (r < nrhs)
+      for (int p = lane; p < nbs; p += 64) {
+        const long o = 3L * (((long)bi * nbs + p) * nrhs + r);
+        sq += part[o];
+        sre += part[o + 1];
+        sim += part[o + 2];
+      }
     sq = wave_sum(sq);
     sre = wave_sum(sre);
     sim = wave_sum(sim);
-    if (t == 0) *alpha_s = sq > 0 ? mk<T>((T)(sre / sq), (T)(sim / sq)) : mk<T>(0, 0);
+    if (lane == 0) alpha_s[qq] = sq > 0 ? mk<T>((T)(sre / sq), (T)(sim / sq)) : mk<T>(0, 0);
   }
   __syncthreads();
 }
 
 // rho = eta - D_c(mu) z on the sites of the colour's blocks
-template <typename T, typename S, int D>
+template <typename T, typename S, int D, int NR>
 __global__ void __launch_bounds__(256) k_sap1_resid(SapArgs a, const SP<S>* __restrict__ Dc,
                                                     const cplx<T>* __restrict__ eta, const cplx<T>* __restrict__ z,
                                                     cplx<T>* __restrict__ rho, const double* __restrict__ mu_dev) {
-  __shared__ cplx<T> vst[9 * D];
-  __shared__ cplx<T> red[SiteMV<D>::KS * D];
+  __shared__ cplx<T> vst[NR * 9 * D];
+  __shared__ cplx<T> red[NR * SiteMV<D>::KS * D];
   const CoarseGeom& g = a.g;
   const long VD = g.V * D;
   const int t = threadIdx.x;
-  int bi, sl, r;
-  sap_unit(a, blockIdx.x, bi, sl, r);
+  int bi, sl, r0;
+  sap_unit<NR>(a, blockIdx.x, bi, sl, r0);
   C4 c, lc;
   cblk_site(a.cb, a.bl[bi], sl, c, lc);
   const long y = cc_index(g, c);
-  const cplx<T>* zr = z + r * VD;
-  for (int k = t; k < 9 * D; k += 256) {
-    const int b = k / D, j = k - b * D;
+  for (int k = t; k < NR * 9 * D; k += 256) {
+    const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
     const long src = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
-    vst[k] = zr[src * D + j];
+    vst[k] = r0 + q < a.nrhs ? z[(r0 + q) * VD + src * D + j] : mk<T>(0, 0);
   }
   __syncthreads();
-  site_mv<T, S, D>(Dc + y * 9L * D * D, vst, 0x1FFu, red);
-  if (t < D) {
+  site_mv<T, S, D, NR>(Dc + y * 9L * D * D, vst, 0x1FFu, red);
+  for (int e = t; e < NR * D; e += 256) {
+    const int q = e / D, i = e - q * D, r = r0 + q;
+    if (r >= a.nrhs) continue;
     const T mu = (T)mu_dev[r];
-    cplx<T> acc = site_mv_row<T, D>(red, t);
-    acc += (t < D / 2 ? mu : -mu) * times_i(vst[t]);
-    rho[r * VD + y * D + t] = eta[r * VD + y * D + t] - acc;
+    cplx<T> acc = site_mv_row<T, D>(red + q * SiteMV<D>::KS * D, i);
+    acc += (i < D / 2 ? mu : -mu) * times_i(vst[q * 9 * D + i]);
+    rho[r * VD + y * D + i] = eta[r * VD + y * D + i] - acc;
   }
 }
 
@@ -173,65 +192,67 @@ __global__ void __launch_bounds__(256) k_sap1_resid(SapArgs a, const SP<S>* __re
 // alpha_prev q_in for the staged in-block neighbours, z += alpha_prev
 // rho_in on the own site.  Then q = D_B rho, written with rho and the
 // per-site partials of the next alpha.
-template <typename T, typename S, int D>
+template <typename T, typename S, int D, int NR>
 __global__ void __launch_bounds__(256) k_sap1_mr(SapArgs a, const SP<S>* __restrict__ Dc, cplx<T>* __restrict__ z,
                                                  const cplx<T>* __restrict__ rho_in, const cplx<T>* __restrict__ q_in,
                                                  const double* __restrict__ part_in, cplx<T>* __restrict__ rho_out,
                                                  cplx<T>* __restrict__ q_out, double* __restrict__ part_out,
                                                  const double* __restrict__ mu_dev, int first) {
-  __shared__ cplx<T> vst[9 * D];
-  __shared__ cplx<T> red[SiteMV<D>::KS * D];
-  __shared__ cplx<T> alpha_s;
+  __shared__ cplx<T> vst[NR * 9 * D];
+  __shared__ cplx<T> red[NR * SiteMV<D>::KS * D];
+  __shared__ cplx<T> alpha_s[NR];
   const CoarseGeom& g = a.g;
   const CBlk& cb = a.cb;
   const long VD = g.V * D;
   const int t = threadIdx.x;
-  int bi, sl, r;
-  sap_unit(a, blockIdx.x, bi, sl, r);
+  int bi, sl, r0;
+  sap_unit<NR>(a, blockIdx.x, bi, sl, r0);
   const int blk = a.bl[bi];
   C4 c, lc;
   cblk_site(cb, blk, sl, c, lc);
   const long y = cc_index(g, c);
-  if (!first) block_alpha<T>(part_in, bi, cb.nbs, a.nrhs, r, &alpha_s);
-  const cplx<T> alpha = first ? mk<T>(0, 0) : alpha_s;
+  if (!first) block_alpha<T, NR>(part_in, bi, cb.nbs, a.nrhs, r0, alpha_s);
   unsigned mask = 1u;
   for (int b = 1; b < 9; ++b)
     if (cblk_nbr(cb, lc, hop_mu(b), hop_step(b)) >= 0) mask |= 1u << b;
-  const cplx<T>* rr = rho_in + r * VD;
-  const cplx<T>* qr = q_in + r * VD;
-  for (int k = t; k < 9 * D; k += 256) {
-    const int b = k / D, j = k - b * D;
+  for (int k = t; k < NR * 9 * D; k += 256) {
+    const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D, r = r0 + q;
     const int nl = b == 0 ? sl : cblk_nbr(cb, lc, hop_mu(b), hop_step(b));
     cplx<T> v = mk<T>(0, 0);
-    if (nl >= 0) {
+    if (nl >= 0 && r < a.nrhs) {
       long src = y;
       if (b != 0) {
         C4 cn, lcn;
         cblk_site(cb, blk, nl, cn, lcn);
         src = cc_index(g, cn);
       }
-      v = rr[src * D + j];
+      v = rho_in[r * VD + src * D + j];
       if (!first) {
-        const cplx<T> qv = qr[src * D + j];
-        v.re -= alpha.re * qv.re - alpha.im * qv.im;
-        v.im -= alpha.re * qv.im + alpha.im * qv.re;
+        const cplx<T> al = alpha_s[q];
+        const cplx<T> qv = q_in[r * VD + src * D + j];
+        v.re -= al.re * qv.re - al.im * qv.im;
+        v.im -= al.re * qv.im + al.im * qv.re;
       }
     }
     vst[k] = v;
   }
   __syncthreads();
-  site_mv<T, S, D>(Dc + y * 9L * D * D, vst, mask, red);
-  if (t < 64) {
+  site_mv<T, S, D, NR>(Dc + y * 9L * D * D, vst, mask, red);
+  // wave q: right-hand side r0 + q (and q + 4, ...), lanes over rows
+  const int wq = t >> 6, lane = t & 63;
+  for (int q = wq; q < NR; q += 4) {
+    const int r = r0 + q;
+    if (r >= a.nrhs) continue;   // uniform across the wave
     T qq = 0, qre = 0, qim = 0;
-    if (t < D) {
+    if (lane < D) {
       const T mu = (T)mu_dev[r];
-      const cplx<T> rho = vst[t];
-      cplx<T> acc = site_mv_row<T, D>(red, t);
-      acc += (t < D / 2 ? mu : -mu) * times_i(rho);
-      const long o = r * VD + y * D + t;
+      const cplx<T> rho = vst[q * 9 * D + lane];
+      cplx<T> acc = site_mv_row<T, D>(red + q * SiteMV<D>::KS * D, lane);
+      acc += (lane < D / 2 ? mu : -mu) * times_i(rho);
+      const long o = r * VD + y * D + lane;
       q_out[o] = acc;
       rho_out[o] = rho;
-      if (!first) cfma(z[o], alpha, rr[y * D + t]);
+      if (!first) cfma(z[o], alpha_s[q], rho_in[o]);
       qq = norm2(acc);
       const cplx<T> tq = cmulc(acc, rho);
       qre = tq.re;
@@ -240,8 +261,8 @@ __global__ void __launch_bounds__(256) k_sap1_mr(SapArgs a, const SP<S>* __restr
     qq = wave_sum(qq);
     qre = wave_sum(qre);
     qim = wave_sum(qim);
-    if (t == 0) {
-      const long u = blockIdx.x;
+    if (lane == 0) {
+      const long u = ((long)bi * cb.nbs + sl) * a.nrhs + r;
       part_out[3 * u] = qq;
       part_out[3 * u + 1] = qre;
       part_out[3 * u + 2] = qim;
@@ -250,22 +271,27 @@ __global__ void __launch_bounds__(256) k_sap1_mr(SapArgs a, const SP<S>* __restr
 }
 
 // completes the last MR step: z += alpha rho
-template <typename T, int D>
+template <typename T, int D, int NR>
 __global__ void __launch_bounds__(256) k_sap1_fin(SapArgs a, cplx<T>* __restrict__ z,
                                                   const cplx<T>* __restrict__ rho_in,
                                                   const double* __restrict__ part_in) {
-  __shared__ cplx<T> alpha_s;
+  __shared__ cplx<T> alpha_s[NR];
   const CoarseGeom& g = a.g;
-  int bi, sl, r;
-  sap_unit(a, blockIdx.x, bi, sl, r);
-  block_alpha<T>(part_in, bi, a.cb.nbs, a.nrhs, r, &alpha_s);
+  int bi, sl, r0;
+  sap_unit<NR>(a, blockIdx.x, bi, sl, r0);
+  block_alpha<T, NR>(part_in, bi, a.cb.nbs, a.nrhs, r0, alpha_s);
   C4 c, lc;
   cblk_site(a.cb, a.bl[bi], sl, c, lc);
-  const long o = r * g.V * D + cc_index(g, c) * D + threadIdx.x;
-  if (threadIdx.x < D) cfma(z[o], alpha_s, rho_in[o]);
+  const long y = cc_index(g, c);
+  for (int e = threadIdx.x; e < NR * D; e += blockDim.x) {
+    const int q = e / D, i = e - q * D, r = r0 + q;
+    if (r >= a.nrhs) continue;
+    const long o = r * g.V * D + y * D + i;
+    cfma(z[o], alpha_s[q], rho_in[o]);
+  }
 }
 
-template <typename T, typename S, int D>
+template <typename T, typename S, int D, int NR>
 static void sap_fused(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const cplx<T>* eta, cplx<T>* z, int nrhs,
                       const double* mu, const int* const bl[2], const int nb[2], int sweeps, int mr,
                       cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
@@ -273,21 +299,22 @@ static void sap_fused(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, cons
   a.g = g;
   a.cb = cb;
   a.nrhs = nrhs;
+  const int ng = (nrhs + NR - 1) / NR;
   for (int sw = 0; sw < sweeps; ++sw)
     for (int col = 0; col < 2; ++col) {
-      const int units = nb[col] * cb.nbs * nrhs;
+      const int units = nb[col] * cb.nbs * ng;
       if (units == 0) continue;
       a.bl = bl[col];
       // the residual goes to slot 1, the slot step 0 reads
-      hipLaunchKernelGGL((k_sap1_resid<T, S, D>), dim3(units), dim3(256), 0, st, a, Dc, eta, z, rho[1], mu);
+      hipLaunchKernelGGL((k_sap1_resid<T, S, D, NR>), dim3(units), dim3(256), 0, st, a, Dc, eta, z, rho[1], mu);
       for (int k = 0; k < mr; ++k) {
         const int in = (k + 1) & 1, out = k & 1;
-        hipLaunchKernelGGL((k_sap1_mr<T, S, D>), dim3(units), dim3(256), 0, st, a, Dc, z, rho[in], q[in], part[in],
-                           rho[out], q[out], part[out], mu, k == 0 ? 1 : 0);
+        hipLaunchKernelGGL((k_sap1_mr<T, S, D, NR>), dim3(units), dim3(256), 0, st, a, Dc, z, rho[in], q[in],
+                           part[in], rho[out], q[out], part[out], mu, k == 0 ? 1 : 0);
       }
       if (mr > 0) {
         const int in = (mr - 1) & 1;
-        hipLaunchKernelGGL((k_sap1_fin<T, D>), dim3(units), dim3(256), 0, st, a, z, rho[in], part[in]);
+        hipLaunchKernelGGL((k_sap1_fin<T, D, NR>), dim3(units), dim3(256), 0, st, a, z, rho[in], part[in]);
       }
     }
 }
@@ -309,12 +336,18 @@ bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const
   if (units * 3 > part_cap || units > (1L << 30)) return false;
   const int* bl[2] = {bl0, bl1};
   const int nb[2] = {n0, n1};
+  // one right-hand side per workgroup, or four (FP64: two) sharing each D_c load
+#define SAP_CASE(DD)                                                                                   \
+  if (nrhs == 1) sap_fused<T, S, DD, 1>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); \
+  else sap_fused<T, S, DD, sizeof(T) == 4 ? 4 : 2>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q,  \
+                                                     part, st);
   switch (d) {
-    case 24: sap_fused<T, S, 24>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
-    case 32: sap_fused<T, S, 32>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
-    case 48: sap_fused<T, S, 48>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
-    default: sap_fused<T, S, 64>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); break;
+    case 24: SAP_CASE(24) break;
+    case 32: SAP_CASE(32) break;
+    case 48: SAP_CASE(48) break;
+    default: SAP_CASE(64) break;
   }
+#undef SAP_CASE
   return true;
 }
 

@@ -244,7 +244,7 @@ TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsig
 // the neighbouring block's spinor (and, backwards, its link) from memory.
 // Workgroups are mapped so that each XCD sweeps a contiguous range of
 // blocks, keeping neighbouring blocks' faces in the same L2.
-template <int MU, typename T>
+template <int MU, bool STREAM, typename T>
 TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* psl, cplx<T>* hb, unsigned s,
                     int loc, const int c[4], const cplx<T>* psi, cplx<T>* acc) {
   const FineGeom& g = op.g;
@@ -252,7 +252,7 @@ TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const c
   const int bv = g.bvol, ls = g.lstride[MU], B = g.B[MU];
   const int lc = c[MU] % B;
   const bool whole = g.NB[MU] == 1;
-  const M3<T> u = load_link_stream<MU>(op.links, s, V);
+  const M3<T> u = STREAM ? load_link_stream<MU>(op.links, s, V) : load_link_u<MU>(op.links, s, V);
   {
     // half spinor sent to y + mu: U^dag (1 + g) psi
     cplx<T> h[6], w[6];
@@ -294,9 +294,34 @@ TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const c
   __syncthreads();   // hb is overwritten by the next direction
 }
 
-template <typename T>
+template <typename T, bool STREAM>
+TM_D void dslash_block_rhs(const FineOp<T>& op, const cplx<T>* __restrict__ inr, cplx<T>* __restrict__ outr, T mu,
+                           cplx<T>* psl, cplx<T>* hb, unsigned s, int loc, const int c[4]) {
+  const long V = op.g.V;
+  const int bv = op.g.bvol;
+  cplx<T> psi[12], acc[12];
+  load_spinor(inr, s, V, psi);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psl[k * bv + loc] = psi[k];
+  site_diag<T, STREAM>(op, s, mu, psi, acc);
+  compiler_fence(acc);
+  __syncthreads();
+  stage_dir<0, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<1, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<2, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  stage_dir<3, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  cplx<T>* o = outr + tsite(s, 12);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
+}
+
+// A single right-hand side streams links and clover (non-temporal loads).
+// A batch runs all its right-hand sides in one workgroup, one after the
+// other, so the block's links and clover come from L2 after the first.
+template <typename T, bool BATCH>
 __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __restrict__ in,
-                                                cplx<T>* __restrict__ out, const double* __restrict__ mu_dev) {
+                                                cplx<T>* __restrict__ out, const double* __restrict__ mu_dev,
+                                                int nrhs) {
   extern __shared__ unsigned char smem_raw[];
   const FineGeom& g = op.g;
   const long V = g.V;
@@ -309,34 +334,29 @@ __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __r
   if (blk >= g.nblocks) return;
   const int loc = threadIdx.x;
   const unsigned s = (unsigned)blk * bv + loc;
-  const int r = blockIdx.y;
-  const cplx<T>* inr = in + (long)r * 12 * V;
-  const T mu = (T)mu_dev[r];
   int c[4];
   fine_coords(g, s, c);
-  cplx<T> psi[12], acc[12];
-  load_spinor(inr, s, V, psi);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) psl[k * bv + loc] = psi[k];
-  site_diag<T, true>(op, s, mu, psi, acc);
-  compiler_fence(acc);
-  __syncthreads();
-  stage_dir<0>(op, inr, psl, hb, s, loc, c, psi, acc);
-  stage_dir<1>(op, inr, psl, hb, s, loc, c, psi, acc);
-  stage_dir<2>(op, inr, psl, hb, s, loc, c, psi, acc);
-  stage_dir<3>(op, inr, psl, hb, s, loc, c, psi, acc);
-  cplx<T>* o = out + (long)r * 12 * V + tsite(s, 12);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
+  if constexpr (!BATCH) {
+    dslash_block_rhs<T, true>(op, in, out, (T)mu_dev[0], psl, hb, s, loc, c);
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < nrhs; ++r)
+      dslash_block_rhs<T, false>(op, in + (long)r * 12 * V, out + (long)r * 12 * V, (T)mu_dev[r], psl, hb, s, loc,
+                                 c);
+  }
 }
 
 template <typename T>
 void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu_dev,
                    hipStream_t st) {
   const int per = (op.g.nblocks + 7) / 8;
-  dim3 grid((unsigned)(8 * per), nrhs);
   const size_t lds = 18 * (size_t)op.g.bvol * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_dslash<T>, grid, dim3(op.g.bvol), lds, st, op, in, out, mu_dev);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_dslash<T, false>), dim3((unsigned)(8 * per)), dim3(op.g.bvol), lds, st, op, in, out, mu_dev,
+                       nrhs);
+  else
+    hipLaunchKernelGGL((k_dslash<T, true>), dim3((unsigned)(8 * per)), dim3(op.g.bvol), lds, st, op, in, out, mu_dev,
+                       nrhs);
 }
 template void launch_dslash<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                     hipStream_t);
