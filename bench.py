@@ -113,6 +113,118 @@ def _cpu_model():
     return "unknown"
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def bench_batched(args):
+    """32^3 x 64: 12 spin-colour point sources at random sites solved as one
+    batch of D(mu) x = b, plus 8 shifted systems (D D^dag + sigma_k) x = b
+    (sigma_k log-spaced in [1e-5, 1]) on one Gaussian source as a second
+    batch (two-step solves with mu' = sqrt(mu^2 + sigma)), mixed precision
+    against the plain FP64 DD-alpha-AMG.  Restart 12 bounds the Krylov
+    memory of 12-wide batches."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, gaussian_spinor, point_sources, rational_shifts, load_m0
+    w = workload("c3")
+    m0 = load_m0()[w.name]
+    kappa = 1.0 / (2 * m0 + 8)
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload c3 dims {w.dims}: generating inputs")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    npt, nsh = w.extra["n_point"], w.extra["n_shift"]
+    bp = torch.as_tensor(point_sources(w.dims, w.seeds["source"], npt)).to(dev)
+    g1 = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"] + 100, n=1)).to(dev)
+    bs = g1.expand(nsh, *g1.shape[1:]).contiguous()
+    sig = [float(x) for x in rational_shifts(nsh)]
+    res = {}
+    for prec, name in ((tm.MIXED, "mixed"), (tm.FP64, "fp64")):
+        if name == "fp64" and args.no_fp64:
+            continue
+        p = solver_params(tm, w, prec)
+        p.restart = 12
+        s = tm.Solver(w.dims, p)
+        _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
+        xp = torch.empty_like(bp)
+        ip, t_pt = _timed(lambda: s.solve(bp, xp, tol=w.tol))
+        xs = torch.empty_like(bs)
+        ish, t_sh = _timed(lambda: s.solve_shifted(bs, xs, sig, tol=w.tol))
+        res[name] = {"setup_s": t_setup, "point_sources_s": t_pt, "shifted_s": t_sh,
+                     "total_s": t_setup + t_pt + t_sh, "point_outer_iters": ip.outer_iters,
+                     "point_true_rel_resid": ip.true_rel_resid, "shifted_outer_iters": ish.outer_iters,
+                     "shifted_true_rel_resid": ish.true_rel_resid}
+        log(f"[bench]   {name}: {res[name]}")
+        s.close()
+        del xp, xs
+        torch.cuda.empty_cache()
+    m = res["mixed"]
+    out = {"metric": "batched solve time (s) @1e-10 rel. resid: 12 point sources + 8 shifted systems",
+           "value": m["total_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": m["total_s"] * 1e3, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "fp32+bf16 (fp64 outer)", "data": "synthetic",
+           "config": {"workload": "c3: 32x32x32x64, 3-level DD-alpha-AMG, 12 point sources + 8 shifts, restart 12",
+                      "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "shifts": sig},
+           "mixed": m, "fp64_amg": res.get("fp64"),
+           "speedup_vs_fp64": (res["fp64"]["total_s"] / m["total_s"]) if "fp64" in res else None,
+           "per_rhs_s": m["total_s"] / (npt + nsh)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_force(args):
+    """16^3 x 32 force: phi = D xi, S_f = phi^dag (D D^dag)^-1 phi and its
+    force through two multigrid solves and the adjoint kernels, mixed
+    precision against the plain FP64 DD-alpha-AMG.  S_f(phi = D xi) equals
+    |xi|^2 exactly, which checks the whole chain at full size."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
+    w = workload("c4")
+    m0 = load_m0()[w.name]
+    kappa = 1.0 / (2 * m0 + 8)
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload c4 dims {w.dims}: generating inputs")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    xi = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["xi"], n=1)).to(dev)
+    xi2 = float((xi.abs() ** 2).sum())
+    F = torch.empty((4,) + tuple(reversed(w.dims)) + (3, 3), dtype=torch.complex128, device=dev)
+    res = {}
+    for prec, name in ((tm.MIXED, "mixed"), (tm.FP64, "fp64")):
+        if name == "fp64" and args.no_fp64:
+            continue
+        s = tm.Solver(w.dims, solver_params(tm, w, prec))
+        _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
+        phi = torch.empty_like(xi)
+        s.apply(tm.OP_D64, 0, xi, phi, [w.mu])
+        times = []
+        for i in range(max(1, args.steps)):
+            (S, info), t = _timed(lambda: s.force(phi, F, tol=1e-12))
+            times.append(t)
+        res[name] = {"setup_s": t_setup, "force_s": min(times), "S": S, "S_rel_err_vs_xi2": abs(S - xi2) / xi2,
+                     "outer_iters": info.outer_iters, "true_rel_resid": info.true_rel_resid,
+                     "F_norm": float(torch.linalg.vector_norm(F))}
+        log(f"[bench]   {name}: {res[name]}")
+        s.close()
+    m = res["mixed"]
+    out = {"metric": "force time (s): S_f and dS_f/dU with solves to 1e-12",
+           "value": m["setup_s"] + m["force_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": (m["setup_s"] + m["force_s"]) * 1e3, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "fp32+bf16 (fp64 outer, fp64 force kernels)", "data": "synthetic",
+           "config": {"workload": "c4: 16x16x16x32, 3-level DD-alpha-AMG, phi = D xi", "lattice": list(w.dims),
+                      "mu": w.mu, "csw": w.csw},
+           "mixed": m, "fp64_amg": res.get("fp64"),
+           "speedup_vs_fp64": ((res["fp64"]["setup_s"] + res["fp64"]["force_s"]) / (m["setup_s"] + m["force_s"]))
+           if "fp64" in res else None}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +245,10 @@ def main():
     import paper_1710_06198_amd as tm
     from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
 
+    if args.workload == "c3":
+        return bench_batched(args)
+    if args.workload == "c4":
+        return bench_force(args)
     w = workload(args.workload)
     m0 = load_m0()[w.name]
     kappa = 1.0 / (2 * m0 + 8)

@@ -713,7 +713,8 @@ struct SiteGmresWs {
   int* kdone;         // [1] valid columns
   unsigned* bar;      // [2]
   int* err;           // [1]
-  int* stat;          // [2]
+  int* stat;          // [2] iterations, launches
+  int* reorth;        // [1] second Gram-Schmidt passes
 };
 
 constexpr int SITE_SLOTS = 32;   // basis vectors per wave: m + 1 <= 128
@@ -786,6 +787,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float mu = (float)mu_dev[0];
   unsigned epoch = 0;
+  int n_reorth = 0;
   cf Vr[SITE_SLOTS], Pr[SITE_SLOTS];
 #pragma unroll
   for (int s = 0; s < SITE_SLOTS; ++s) Vr[s] = Pr[s] = mk<float>(0, 0);
@@ -901,7 +903,12 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
     }
     __syncthreads();
 
-    // two classical Gram-Schmidt passes; the second also gives |w|^2
+    // Classical Gram-Schmidt with |w|^2 in the same reduction; a second pass
+    // only where the first lost more than half of |w|^2 (the DGKS
+    // criterion, ||w - V c|| < ||w|| / sqrt 2).  Every workgroup takes the
+    // same decision from the same sums.
+    double hn = 0;
+#pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
       double* part = pass ? ws.part2 : ws.part1;
       double* cc = pass ? c2 : c1;
@@ -919,7 +926,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
           }
         }
       }
-      if (pass == 1 && wv == 0) {
+      if (wv == 0) {
         const float n2 = wave_sum(norm2(wv_l));
         if (lane == 0) {
           part[2L * ((long)(j + 1) * G + u)] = n2;
@@ -927,7 +934,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
         }
       }
       gbar(ws.bar, epoch, ws.err);
-      gather_sums(part, j + 1 + pass, G, cc);
+      gather_sums(part, j + 2, G, cc);
       cf acc = mk<float>(0, 0);
 #pragma unroll
       for (int s = 0; s < SITE_SLOTS; ++s) {
@@ -938,12 +945,19 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
       comb[wv][lane] = acc;
       __syncthreads();
       if (t < D) wl[t] = wl[t] - ((comb[0][t] + comb[1][t]) + (comb[2][t] + comb[3][t]));
+      // |w - V c|^2 = |w|^2 - |c|^2 (V orthonormal)
+      const double w2 = cc[2 * (j + 1)];
+      double r2 = w2;
+      for (int l = 0; l <= j; ++l) r2 -= cc[2 * l] * cc[2 * l] + cc[2 * l + 1] * cc[2 * l + 1];
+      hn = r2 > 0 ? sqrt(r2) : 0.0;
+      if (pass == 0 && r2 >= 0.5 * w2) {
+        for (int e = t; e < 2 * (j + 2); e += 256) c2[e] = 0;
+        __syncthreads();
+        break;   // same decision in every workgroup
+      }
+      if (pass == 0) n_reorth++;
       __syncthreads();
     }
-    // h_{j+1,j} = sqrt(|w|^2 - |c2|^2) after the second pass
-    double h2 = c2[2 * (j + 1)];
-    for (int l = 0; l <= j; ++l) h2 -= c2[2 * l] * c2[2 * l] + c2[2 * l + 1] * c2[2 * l + 1];
-    const double hn = h2 > 0 ? sqrt(h2) : 0.0;
     {
       const cf vn = (lane < D && hn > 0) ? (float)(1.0 / hn) * wl[lane] : mk<float>(0, 0);
       if (wv == ((j + 1) & 3)) {
@@ -1004,6 +1018,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
   if (u == 0 && t == 0) {
     atomicAdd(ws.stat, s_kd);
     atomicAdd(ws.stat + 1, 1);
+    atomicAdd(ws.reorth, n_reorth);
   }
   gbar_exit(ws.bar);
 }
@@ -1105,6 +1120,7 @@ static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
     ws.stat = iws + 3;
     ws.flag = iws + 5;
     ws.kdone = iws + 6;
+    ws.reorth = iws + 7;
     hipError_t e;
     switch (d) {
       case 24: e = site_gmres_launch<S, 24>(a, Dc, b, x, mu_dev, ws, st); break;

@@ -238,12 +238,13 @@ std::string Hier<T, S>::stats_line() {
                     std::to_string(stats_coarsest);
   stats_l2 = stats_coarsest = 0;
   if (cg_iws.p) {
-    int h[3] = {0, 0, 0};
+    int h[6] = {0, 0, 0, 0, 0, 0};
     HIPCHK(hipStreamSynchronize(c->st));
     HIPCHK(hipMemcpy(h, cg_iws.p + 2, sizeof(h), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemsetAsync(cg_iws.p + 2, 0, sizeof(h), c->st));
+    HIPCHK(hipMemsetAsync(cg_iws.p + 2, 0, 3 * sizeof(int), c->st));
+    HIPCHK(hipMemsetAsync(cg_iws.p + 7, 0, sizeof(int), c->st));
     out += " coarsest_calls=" + std::to_string(h[2]) + " coarsest_iters=" + std::to_string(h[1]) +
-           " barrier_timeouts=" + std::to_string(h[0]);
+           " coarsest_reorth=" + std::to_string(h[5]) + " barrier_flags=" + std::to_string(h[0]);
   }
   return out;
 }
