@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtmamg.so")
+# TMAMG_LIB selects another build of the library (same ABI)
+LIB_PATH = os.environ.get("TMAMG_LIB", os.path.join(HERE, "libtmamg.so"))
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1

@@ -693,10 +693,13 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres(CoopGmres a, const SP<S>
 //    R_li p_l) / R_ii in registers, wave w holding i = w (mod 4);
 //  * its rows of x = sum_i g_i p_i, updated as soon as column i of the
 //    rotated Hessenberg R and the rotated g_i are final, so no triangular
-//    solve is left at the end.
-// Only the newest basis vector goes through global memory (for the
-// neighbours' matrix-vector products), together with per-workgroup partial
-// sums in pair-major order, [pair][workgroup].
+//    solve is left at the end;
+//  * its own copy of the Givens rotations: every workgroup rotates the
+//    same Hessenberg column from the same sums, so convergence decisions
+//    and R need no broadcast.
+// Only the newest basis vector and per-workgroup partial sums (float
+// pairs, [pair][workgroup]) cross workgroups; both are written with
+// agent-scope stores so that the barrier's cache write-back finds little.
 struct SiteGmres {
   CoarseGeom g;
   int m;
@@ -705,12 +708,8 @@ struct SiteGmres {
 struct SiteGmresWs {
   cplx<float>* vg0;   // [n] newest basis vector, even j
   cplx<float>* vg1;   // [n] odd j
-  double* part1;      // [m+2][G] complex
-  double* part2;      // [m+2][G] complex
-  double* R;          // [m][m] complex, column j at [j][.]
-  double* gv;         // [m] complex, final rotated right-hand side
-  int* flag;          // [1] still iterating
-  int* kdone;         // [1] valid columns
+  float* part1;       // [m+2][Gp] complex float, Gp = G rounded up to even
+  float* part2;       // [m+2][Gp]
   unsigned* bar;      // [2]
   int* err;           // [1]
   int* stat;          // [2] iterations, launches
@@ -719,36 +718,39 @@ struct SiteGmresWs {
 
 constexpr int SITE_SLOTS = 32;   // basis vectors per wave: m + 1 <= 128
 
-// sums[q] (q < P) = sum over workgroups of part[q][wg] (complex).  L lanes
-// share a pair (the largest power of two with L * P <= 256), each with
-// eight loads in flight, combined by shuffles; identical bits in every
-// workgroup.
-TM_D void gather_sums(const double* __restrict__ part, int P, int G, double* out) {
+TM_D void st_agent(float* p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// sums[q] (q < P) = sum over workgroups of part[q][wg] (complex float).
+// L lanes share a pair (the largest power of two with L * P <= 256); a lane
+// loads two workgroups' values per 16-byte access, eight accesses in
+// flight; shuffles combine the lanes.  Identical bits in every workgroup.
+TM_D void gather_sums(const float* __restrict__ part, int P, int Gp, double* out) {
   int L = 64;
   while (L > 1 && L * P > 256) L >>= 1;
   const int t = threadIdx.x, sub = t & (L - 1), slot = t / L, nslot = 256 / L;
+  const int G2 = Gp >> 1;   // float4 = two workgroups
   for (int q0 = 0; q0 < P; q0 += nslot) {
     const int q = q0 + slot;
     double re[8], im[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) re[k] = im[k] = 0;
     if (q < P) {
-      const double2* p = reinterpret_cast<const double2*>(part) + (long)q * G;
-      int wg = sub;
-      for (; wg + 7 * L < G; wg += 8 * L) {
-        double2 v[8];
+      const float4* pp = reinterpret_cast<const float4*>(part) + (long)q * G2;
+      int w2 = sub;
+      for (; w2 + 7 * L < G2; w2 += 8 * L) {
+        float4 v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = p[wg + k * L];
+        for (int k = 0; k < 8; ++k) v[k] = pp[w2 + k * L];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          re[k] += v[k].x;
-          im[k] += v[k].y;
+          re[k] += (double)v[k].x + (double)v[k].z;
+          im[k] += (double)v[k].y + (double)v[k].w;
         }
       }
-      for (; wg < G; wg += L) {
-        const double2 v = p[wg];
-        re[0] += v.x;
-        im[0] += v.y;
+      for (; w2 < G2; w2 += L) {
+        const float4 v = pp[w2];
+        re[0] += (double)v.x + (double)v.z;
+        im[0] += (double)v.y + (double)v.w;
       }
     }
     double sr = ((re[0] + re[1]) + (re[2] + re[3])) + ((re[4] + re[5]) + (re[6] + re[7]));
@@ -778,12 +780,13 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
   __shared__ cf pl[64];
   __shared__ double c1[2 * (4 * SITE_SLOTS + 1)];
   __shared__ double c2[2 * (4 * SITE_SLOTS + 1)];
-  __shared__ double rcol[2 * 4 * SITE_SLOTS];
+  __shared__ double rcol[2 * 4 * SITE_SLOTS];   // rotated column of the last iteration
+  __shared__ double s_g[2];                     // its final rotated g
   __shared__ int s_flag, s_kd;
   extern __shared__ __align__(16) unsigned char dyn[];
   SP<S>* dcl = reinterpret_cast<SP<S>*>(dyn);
   const CoarseGeom& g = a.g;
-  const int m = a.m, G = gridDim.x, u = blockIdx.x;
+  const int m = a.m, G = gridDim.x, Gp = (G + 1) & ~1, u = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const float mu = (float)mu_dev[0];
   unsigned epoch = 0;
@@ -794,7 +797,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
   // wave 0: x rows, the newest basis vector, and v_i of the column i whose
   // p_i is formed at the top of the next iteration
   cf xacc = mk<float>(0, 0), vcur = mk<float>(0, 0), vfin = mk<float>(0, 0);
-  // Givens state, wave 0 of workgroup 0: rotation i in lane i % 64, slot i / 64
+  // Givens state (wave 0): rotation i in lane i % 64, slot i / 64
   double csr0 = 0, csi0 = 0, sn0 = 0, csr1 = 0, csi1 = 0, sn1 = 0, gre = 0, gim = 0, tolabs = 0;
 
   {
@@ -802,49 +805,48 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
     Quad<S>* dst = reinterpret_cast<Quad<S>*>(dcl);
     for (int k = t; k < 9 * D * D / 4; k += 256) dst[k] = src[k];
   }
+  if (u == 0 && (G & 1) && t < 2 * (m + 2)) {
+    // with an odd workgroup count every pair's padding slot reads as zero
+    const int q = t >> 1;
+    float* p = (t & 1) ? ws.part2 : ws.part1;
+    st_agent(p + 2L * ((long)q * Gp + G), 0.f);
+    st_agent(p + 2L * ((long)q * Gp + G) + 1, 0.f);
+  }
   if (t < 64) {
     const cf bv = lane < D ? b[(long)u * D + lane] : mk<float>(0, 0);
     vcur = bv;
     float s2 = norm2(bv);
     s2 = wave_sum(s2);
     if (lane == 0) {
-      ws.part1[2L * u] = s2;
-      ws.part1[2L * u + 1] = 0;
+      st_agent(ws.part1 + 2L * u, s2);
+      st_agent(ws.part1 + 2L * u + 1, 0.f);
     }
   }
   gbar(ws.bar, epoch, ws.err);
-  gather_sums(ws.part1, 1, G, c1);
+  gather_sums(ws.part1, 1, Gp, c1);
   {
     const double beta = sqrt(c1[0]);
     const bool ok = beta > 0 && beta < 1e300;
     if (t < 64) {
       vcur = ok ? (float)(1.0 / beta) * vcur : mk<float>(0, 0);
       Vr[0] = vcur;
-      if (lane < D) ws.vg0[(long)u * D + lane] = vcur;
-    }
-    if (u == 0 && t < 64) {
+      if (lane < D) {
+        float* vp = reinterpret_cast<float*>(ws.vg0 + (long)u * D + lane);
+        st_agent(vp, vcur.re);
+        st_agent(vp + 1, vcur.im);
+      }
       gre = beta;
       tolabs = a.reltol * beta;
-      if (t == 0) {
-        *ws.flag = ok ? 1 : 0;
-        *ws.kdone = 0;
-      }
+    }
+    if (t == 0) {
+      s_flag = ok ? 1 : 0;
+      s_kd = 0;
     }
   }
   gbar(ws.bar, epoch, ws.err);
 
   for (int j = 0;; ++j) {
-    // state written by workgroup 0 before the barrier just passed
-    if (t == 0) {
-      s_flag = __hip_atomic_load(ws.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_kd = __hip_atomic_load(ws.kdone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (j > 0 && t < j) {
-      rcol[2 * t] = ws.R[2L * ((long)(j - 1) * m + t)];
-      rcol[2 * t + 1] = ws.R[2L * ((long)(j - 1) * m + t) + 1];
-    }
-    __syncthreads();
-    const int kd = s_kd;
+    const int kd = s_kd;   // set by this workgroup's own rotation before the barrier
     // column j-1 final: p_{j-1} = (v_{j-1} - sum_{l<j-1} R_{l,j-1} p_l) / R_{j-1,j-1}, x += g_{j-1} p_{j-1}
     if (j > 0 && kd >= j) {
       const int i = j - 1;
@@ -862,10 +864,9 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
         const double dr = rcol[2 * i], di = rcol[2 * i + 1], dd = dr * dr + di * di;
         const cf num = vfin - sum;
         // num / R_ii
-        const cf p = mk<float>((float)((num.re * dr + num.im * di) / dd), (float)((num.im * dr - num.re * di) / dd));
-        pl[lane] = p;
-        const double gr = ws.gv[2 * i], gi = ws.gv[2 * i + 1];
-        cfma(xacc, mk<float>((float)gr, (float)gi), p);
+        const cf pv = mk<float>((float)((num.re * dr + num.im * di) / dd), (float)((num.im * dr - num.re * di) / dd));
+        pl[lane] = pv;
+        cfma(xacc, mk<float>((float)s_g[0], (float)s_g[1]), pv);
       }
       __syncthreads();
       if (wv == (i & 3)) {
@@ -910,7 +911,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
     double hn = 0;
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
-      double* part = pass ? ws.part2 : ws.part1;
+      float* part = pass ? ws.part2 : ws.part1;
       double* cc = pass ? c2 : c1;
       const cf wv_l = lane < D ? wl[lane] : mk<float>(0, 0);
 #pragma unroll
@@ -921,20 +922,20 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
           const cf d = cmulc(Vr[s], wv_l);
           const float dre = wave_sum(d.re), dim = wave_sum(d.im);
           if (lane == 0) {
-            part[2L * ((long)i * G + u)] = dre;
-            part[2L * ((long)i * G + u) + 1] = dim;
+            st_agent(part + 2L * ((long)i * Gp + u), dre);
+            st_agent(part + 2L * ((long)i * Gp + u) + 1, dim);
           }
         }
       }
       if (wv == 0) {
         const float n2 = wave_sum(norm2(wv_l));
         if (lane == 0) {
-          part[2L * ((long)(j + 1) * G + u)] = n2;
-          part[2L * ((long)(j + 1) * G + u) + 1] = 0;
+          st_agent(part + 2L * ((long)(j + 1) * Gp + u), n2);
+          st_agent(part + 2L * ((long)(j + 1) * Gp + u) + 1, 0.f);
         }
       }
       gbar(ws.bar, epoch, ws.err);
-      gather_sums(part, j + 2, G, cc);
+      gather_sums(part, j + 2, Gp, cc);
       cf acc = mk<float>(0, 0);
 #pragma unroll
       for (int s = 0; s < SITE_SLOTS; ++s) {
@@ -968,11 +969,15 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
       if (t < 64) {
         vfin = vcur;
         vcur = vn;
-        if (lane < D) ((j & 1) ? ws.vg0 : ws.vg1)[(long)u * D + lane] = vn;
+        if (lane < D) {
+          float* vp = reinterpret_cast<float*>(((j & 1) ? ws.vg0 : ws.vg1) + (long)u * D + lane);
+          st_agent(vp, vn.re);
+          st_agent(vp + 1, vn.im);
+        }
       }
     }
-    // Givens rotations, wave 0 of workgroup 0
-    if (u == 0 && t < 64) {
+    // Givens rotations (wave 0 of every workgroup, identical inputs)
+    if (t < 64) {
       double ar = c1[0] + c2[0], ai = c1[1] + c2[1];
       for (int i = 0; i < j; ++i) {
         const bool hi = i >= 64;
@@ -981,8 +986,8 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
         const double sn = __shfl(hi ? sn1 : sn0, i & 63, 64);
         const double br = c1[2 * (i + 1)] + c2[2 * (i + 1)], bi = c1[2 * (i + 1) + 1] + c2[2 * (i + 1) + 1];
         if (t == 0) {
-          ws.R[2L * ((long)j * m + i)] = cr * ar - ci * ai + sn * br;
-          ws.R[2L * ((long)j * m + i) + 1] = cr * ai + ci * ar + sn * bi;
+          rcol[2 * i] = cr * ar - ci * ai + sn * br;
+          rcol[2 * i + 1] = cr * ai + ci * ar + sn * bi;
         }
         const double ur = -sn * ar + (cr * br + ci * bi);
         const double ui = -sn * ai + (cr * bi - ci * br);
@@ -991,7 +996,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
       }
       const double den = sqrt(ar * ar + ai * ai + hn * hn);
       if (!(den > 0) || den != den) {
-        if (t == 0) *ws.flag = 0;
+        if (t == 0) s_flag = 0;
       } else {
         const double cr = ar / den, ci = -ai / den, sn = hn / den;
         if (lane == (j & 63)) {
@@ -1000,12 +1005,12 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
         }
         const double res = sn * sqrt(gre * gre + gim * gim);
         if (t == 0) {
-          ws.R[2L * ((long)j * m + j)] = den;
-          ws.R[2L * ((long)j * m + j) + 1] = 0;
-          ws.gv[2 * j] = cr * gre - ci * gim;
-          ws.gv[2 * j + 1] = cr * gim + ci * gre;
-          *ws.kdone = j + 1;
-          if (res <= tolabs || hn <= 1e-15 * den || j + 1 >= m) *ws.flag = 0;
+          rcol[2 * j] = den;
+          rcol[2 * j + 1] = 0;
+          s_g[0] = cr * gre - ci * gim;
+          s_g[1] = cr * gim + ci * gre;
+          s_kd = j + 1;
+          if (res <= tolabs || hn <= 1e-15 * den || j + 1 >= m) s_flag = 0;
         }
         const double ngr = -sn * gre, ngi = -sn * gim;
         gre = ngr;
@@ -1102,7 +1107,8 @@ static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
   } else {
     if (nrhs != 1 || g.V > 256 || m + 1 > 4 * SITE_SLOTS) return false;
     const int G = (int)g.V;
-    if (4 * (size_t)G * (m + 2) + 2 * (size_t)m * m + 2 * (size_t)m > dws_cap || iws_cap < 8) return false;
+    const int Gp = (G + 1) & ~1;
+    if ((size_t)2 * Gp * (m + 2) > dws_cap || iws_cap < 8) return false;
     SiteGmres a;
     a.g = g;
     a.m = m;
@@ -1110,16 +1116,12 @@ static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
     SiteGmresWs ws;
     ws.vg0 = Vbasis;
     ws.vg1 = Vbasis + g.V * d;
-    double* p = dws;
-    ws.part1 = p; p += 2 * (size_t)G * (m + 2);
-    ws.part2 = p; p += 2 * (size_t)G * (m + 2);
-    ws.R = p; p += 2 * (size_t)m * m;
-    ws.gv = p; p += 2 * (size_t)m;
+    float* fp = reinterpret_cast<float*>(dws);
+    ws.part1 = fp;
+    ws.part2 = fp + 2 * (size_t)Gp * (m + 2);
     ws.bar = reinterpret_cast<unsigned*>(iws);
     ws.err = iws + 2;
     ws.stat = iws + 3;
-    ws.flag = iws + 5;
-    ws.kdone = iws + 6;
     ws.reorth = iws + 7;
     hipError_t e;
     switch (d) {
