@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_d(CoarseGeom g, const SP<S
 template <typename T, typename S>
 void launch_coarse_apply(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out, int nrhs,
                          const double* mu_dev, hipStream_t st) {
+  if (launch_coarse_apply_site<T, S>(g, d, Dc, in, out, nrhs, mu_dev, st)) return;
   const int spw = 256 / d;
   dim3 grid((unsigned)((g.V + spw - 1) / spw), nrhs);
   size_t sh = (size_t)spw * 9 * d * sizeof(cplx<T>);

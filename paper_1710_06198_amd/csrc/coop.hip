@@ -112,6 +112,61 @@ TM_D cplx<T> site_mv_row(const cplx<T>* red, int i) {
   return s;
 }
 
+// ------------------------------------------------------------------ coarse operator, one site per workgroup
+// D_c(mu_r) for NR right-hand sides per workgroup (one coarse site), with
+// the slice mapping of site_mv: 16-byte D_c loads, many in flight per
+// thread, shared by the NR vectors.
+template <typename T, typename S, int D, int NR>
+__global__ void __launch_bounds__(256) k_coarse_apply_site(CoarseGeom g, const SP<S>* __restrict__ Dc,
+                                                           const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                           int nrhs, const double* __restrict__ mu_dev) {
+  __shared__ cplx<T> vst[NR * 9 * D];
+  __shared__ cplx<T> red[NR * SiteMV<D>::KS * D];
+  const long y = blockIdx.x;
+  const int r0 = blockIdx.y * NR;
+  const long VD = g.V * D;
+  const int t = threadIdx.x;
+  const C4 c = cc_coords(g, y);
+  for (int k = t; k < NR * 9 * D; k += 256) {
+    const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
+    const long src = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
+    vst[k] = r0 + q < nrhs ? in[(r0 + q) * VD + src * D + j] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  site_mv<T, S, D, NR>(Dc + y * 9L * D * D, vst, 0x1FFu, red);
+  for (int e = t; e < NR * D; e += 256) {
+    const int q = e / D, i = e - q * D, r = r0 + q;
+    if (r >= nrhs) continue;
+    const T mu = (T)mu_dev[r];
+    cplx<T> acc = site_mv_row<T, D>(red + q * SiteMV<D>::KS * D, i);
+    acc += (i < D / 2 ? mu : -mu) * times_i(vst[q * 9 * D + i]);
+    out[r * VD + y * D + i] = acc;
+  }
+}
+
+template <typename T, typename S, int D>
+static void coarse_apply_site(const CoarseGeom& g, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out, int nrhs,
+                              const double* mu_dev, hipStream_t st) {
+  if (nrhs >= 4)
+    hipLaunchKernelGGL((k_coarse_apply_site<T, S, D, 4>), dim3((unsigned)g.V, (nrhs + 3) / 4), dim3(256), 0, st, g,
+                       Dc, in, out, nrhs, mu_dev);
+  else
+    hipLaunchKernelGGL((k_coarse_apply_site<T, S, D, 1>), dim3((unsigned)g.V, nrhs), dim3(256), 0, st, g, Dc, in,
+                       out, nrhs, mu_dev);
+}
+
+template <typename T, typename S>
+bool launch_coarse_apply_site(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out,
+                              int nrhs, const double* mu_dev, hipStream_t st) {
+  switch (d) {
+    case 24: coarse_apply_site<T, S, 24>(g, Dc, in, out, nrhs, mu_dev, st); return true;
+    case 32: coarse_apply_site<T, S, 32>(g, Dc, in, out, nrhs, mu_dev, st); return true;
+    case 48: coarse_apply_site<T, S, 48>(g, Dc, in, out, nrhs, mu_dev, st); return true;
+    case 64: coarse_apply_site<T, S, 64>(g, Dc, in, out, nrhs, mu_dev, st); return true;
+    default: return false;
+  }
+}
+
 // ------------------------------------------------------------------ SAP with fused MR steps
 struct SapArgs {
   CoarseGeom g;
@@ -1189,6 +1244,8 @@ bool launch_coarsest_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
 }
 
 #define INST_COOP(T, S)                                                                                             \
+  template bool launch_coarse_apply_site<T, S>(const CoarseGeom&, int, const SP<S>*, const cplx<T>*, cplx<T>*,    \
+                                               int, const double*, hipStream_t);                                  \
   template bool launch_sap_coarse_fused<T, S>(const CoarseGeom&, int, const int*, const SP<S>*, const cplx<T>*,    \
                                               cplx<T>*, int, const double*, const int*, int, const int*, int, int,  \
                                               int, cplx<T>* const*, cplx<T>* const*, double* const*, long,          \

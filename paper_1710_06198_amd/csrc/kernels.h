@@ -158,6 +158,10 @@ void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const 
 // complex Gaussian noise, E|z|^2 = 1, counter-based (seed, index)
 template <typename T>
 void launch_random(cplx<T>* out, long count, unsigned long long seed, hipStream_t st);
+// D_c(mu_r) with one coarse site per workgroup (false: shape not covered)
+template <typename T, typename S>
+bool launch_coarse_apply_site(const CoarseGeom& g, int d, const typename Store<S>::pair* Dc, const cplx<T>* in,
+                              cplx<T>* out, int nrhs, const double* mu_dev, hipStream_t st);
 // Coarse-level SAP with fused MR launches, and the persistent coarsest
 // GMRES (false: shape not covered, the caller uses the generic kernels)
 template <typename T, typename S>
