@@ -145,9 +145,173 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
     }
   }
 }
+// Cholesky QR, twice (CholQR2), for up to 32 vectors: per (aggregate,
+// chirality) workgroup the K = 6 * bvol rows of V = [v_1 .. v_nv] give the
+// Gram matrix G = V^dag V (FP64, accumulated from LDS tiles of rows), its
+// Cholesky factor G = R^dag R (positive real diagonal), and Q = V R^-1;
+// the second pass repeats this on Q.  Given the same v_i this is the same
+// Q as Gram-Schmidt in index order (the QR factor with positive diagonal
+// is unique) and needs a handful of barriers instead of a chain of nv^2
+// dependent reductions.
+constexpr int GS_NV = 32;   // largest nv of the Cholesky QR kernel
+constexpr int GS_TS = 8;    // sites per LDS tile
+
+TM_D int gs_row_offset(int r, int sc) {   // tile row r = (site in tile, component)
+  return (sc * 6 + r % 6) * FT;
+}
+
+// G = V^dag V over the aggregate's rows (src: nv fields of 12 V), lower
+// triangle mirrored.  tile: [GS_TS*6][nv]; G: [nv][nv] (row-major).
+template <typename U>
+TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int nv, cplx<double>* tile,
+                  cplx<double>* G) {
+  const int t = threadIdx.x;
+  const int np = nv * (nv + 1) / 2;
+  cplx<double> acc[(GS_NV * (GS_NV + 1) / 2 + 255) / 256];
+  constexpr int NPT = (GS_NV * (GS_NV + 1) / 2 + 255) / 256;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) acc[q] = mk(0.0, 0.0);
+  for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
+    const int nrow = GS_TS * 6;
+    for (int e = t; e < nrow * nv; e += blockDim.x) {
+      const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
+      const long s = site0 + x0 + xs;
+      const cplx<U> v = src[(long)c * vs + tsite((unsigned)s, 12) + (sc * 6 + k) * FT];
+      tile[(xs * 6 + k) * nv + c] = mk((double)v.re, (double)v.im);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int pidx = t + q * 256;
+      if (pidx < np) {
+        int b = (int)((sqrtf(8.f * pidx + 1.f) - 1.f) * 0.5f);
+        while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
+        while (b * (b + 1) / 2 > pidx) --b;
+        const int a = pidx - b * (b + 1) / 2;   // a <= b
+        cplx<double> s2 = acc[q];
+        for (int r = 0; r < nrow; ++r) cfmac(s2, tile[r * nv + a], tile[r * nv + b]);
+        acc[q] = s2;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int pidx = t + q * 256;
+    if (pidx < np) {
+      int b = (int)((sqrtf(8.f * pidx + 1.f) - 1.f) * 0.5f);
+      while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
+      while (b * (b + 1) / 2 > pidx) --b;
+      const int a = pidx - b * (b + 1) / 2;
+      G[a * nv + b] = acc[q];
+      G[b * nv + a] = conj(acc[q]);
+    }
+  }
+  __syncthreads();
+}
+
+// In place G -> R (upper, G = R^dag R, real positive diagonal), then
+// Ri = R^-1 (upper).
+TM_D void gs_chol_inv(int nv, cplx<double>* G, cplx<double>* Ri) {
+  const int t = threadIdx.x;
+  for (int j = 0; j < nv; ++j) {
+    __syncthreads();   // previous trailing update done
+    const double d = sqrt(fmax(G[j * nv + j].re, 1e-300));
+    __syncthreads();   // every thread has read the pivot before it is overwritten
+    if (t >= j && t < nv) G[j * nv + t] = (1.0 / d) * G[j * nv + t];   // row j of R (t == j gives d)
+    __syncthreads();
+    // trailing update G[i][l] -= conj(R[j][i]) R[j][l], j < i <= l (upper part only)
+    const int nt = nv - j - 1;
+    for (int e = t; e < nt * nt; e += blockDim.x) {
+      const int i = j + 1 + e / nt, l = j + 1 + e % nt;
+      if (l >= i) G[i * nv + l] -= conj(G[j * nv + i]) * G[j * nv + l];
+    }
+  }
+  __syncthreads();
+  // R^-1, one column per thread: Ri[j][j] = 1 / R[j][j]; Ri[i][j] = -(sum_{i<k<=j} R[i][k] Ri[k][j]) / R[i][i]
+  if (t < nv) {
+    const int j = t;
+    for (int i = 0; i < nv; ++i) Ri[i * nv + j] = mk(0.0, 0.0);
+    Ri[j * nv + j] = mk(1.0 / G[j * nv + j].re, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      cplx<double> s2 = mk(0.0, 0.0);
+      for (int k = i + 1; k <= j; ++k) cfma(s2, G[i * nv + k], Ri[k * nv + j]);
+      Ri[i * nv + j] = (-1.0 / G[i * nv + i].re) * s2;
+    }
+  }
+  __syncthreads();
+}
+
+// Q = V Ri over the aggregate's rows: written to P64 (and P when final)
+template <typename U, typename S>
+TM_D void gs_apply(const cplx<U>* src, long vs, long site0, int bvol, int sc, int nv, const cplx<double>* Ri,
+                   cplx<double>* tile, cplx<double>* P64, SP<S>* P, bool final_pass) {
+  const int t = threadIdx.x;
+  const int nrow = GS_TS * 6;
+  for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
+    for (int e = t; e < nrow * nv; e += blockDim.x) {
+      const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
+      const long s = site0 + x0 + xs;
+      const cplx<U> v = src[(long)c * vs + tsite((unsigned)s, 12) + (sc * 6 + k) * FT];
+      tile[(xs * 6 + k) * nv + c] = mk((double)v.re, (double)v.im);
+    }
+    __syncthreads();
+    // thread e -> (vector c, row r), rows site-fastest so that the stores
+    // of consecutive lanes are contiguous; tile row of (xs, k) is xs*6 + k
+    constexpr int QPT = (GS_TS * 6 * GS_NV + 255) / 256;
+    cplx<double> q[QPT];
+#pragma unroll
+    for (int qq = 0; qq < QPT; ++qq) {
+      const int e = t + qq * 256;
+      q[qq] = mk(0.0, 0.0);
+      if (e < nrow * nv) {
+        const int c = e / nrow, r = e % nrow, tr = (r % GS_TS) * 6 + r / GS_TS;
+        cplx<double> s2 = mk(0.0, 0.0);
+        for (int i = 0; i <= c; ++i) cfma(s2, tile[tr * nv + i], Ri[i * nv + c]);
+        q[qq] = s2;
+      }
+    }
+    __syncthreads();   // src rows of this tile are all read before P64 (possibly src) is written
+#pragma unroll
+    for (int qq = 0; qq < QPT; ++qq) {
+      const int e = t + qq * 256;
+      if (e < nrow * nv) {
+        const int c = e / nrow, r = e % nrow;
+        const long s = site0 + x0 + r % GS_TS;
+        const size_t o = (size_t)c * vs + tsite((unsigned)s, 12) + (sc * 6 + r / GS_TS) * FT;
+        const cplx<double> val = q[qq];
+        if (final_pass) Store<S>::st(P + o, val);
+        P64[o] = val;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T>* __restrict__ tv, int nv,
+                                                        cplx<double>* P64, SP<S>* P) {
+  __shared__ cplx<double> tile[GS_TS * 6 * GS_NV];
+  __shared__ cplx<double> G[GS_NV * GS_NV];
+  __shared__ cplx<double> Ri[GS_NV * GS_NV];
+  const int y = blockIdx.x, sc = blockIdx.y;
+  const long vs = 12 * g.V, site0 = (long)y * g.bvol;
+  // pass 1 on the test vectors
+  gs_gram<T>(tv, vs, site0, g.bvol, sc, nv, tile, G);
+  gs_chol_inv(nv, G, Ri);
+  gs_apply<T, S>(tv, vs, site0, g.bvol, sc, nv, Ri, tile, P64, P, false);
+  // pass 2 on Q1 (in P64, rewritten in place tile by tile)
+  gs_gram<double>(P64, vs, site0, g.bvol, sc, nv, tile, G);
+  gs_chol_inv(nv, G, Ri);
+  gs_apply<double, S>(P64, vs, site0, g.bvol, sc, nv, Ri, tile, P64, P, true);
+}
+
 template <typename T, typename S>
 void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* P64, SP<S>* P, hipStream_t st) {
-  hipLaunchKernelGGL((k_gs_fine<T, S>), dim3(g.nblocks, 2), dim3(g.bvol), 0, st, g, tv, nv, P64, P);
+  if (nv <= GS_NV)
+    hipLaunchKernelGGL((k_gs_fine_cholqr<T, S>), dim3(g.nblocks, 2), dim3(256), 0, st, g, tv, nv, P64, P);
+  else
+    hipLaunchKernelGGL((k_gs_fine<T, S>), dim3(g.nblocks, 2), dim3(g.bvol), 0, st, g, tv, nv, P64, P);
 }
 
 // ------------------------------------------------------------------ Galerkin, fine -> first coarse level
