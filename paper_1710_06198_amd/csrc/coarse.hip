@@ -678,6 +678,136 @@ __global__ void __launch_bounds__(256) k_galerkin_coarse(CoarseGeom g, int d, CA
   }
 }
 
+// The same product with GC columns per workgroup: workgroup (Y, s', group)
+// takes the columns cc = s' nv + g GC + c, c < GC, which all live on the
+// s' half of the aggregate's components.  Each D_c element loaded in stage
+// 1 serves the GC columns (w in LDS, [site][half component][column]);
+// stage 2 gives each thread one output row n for GC / 4 columns.
+constexpr int GAL_GC = 8;
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_galerkin_coarse_cols(CoarseGeom g, int d, CAgg a,
+                                                              const SP<S>* __restrict__ Dc1,
+                                                              const SP<S>* __restrict__ P, int nv,
+                                                              SP<S>* __restrict__ Dc2, CoarseGeom g2) {
+  constexpr int GC = GAL_GC, CPT = GC / 4;   // columns per thread in stage 2 (one wave per CPT columns)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int na = a.na, hd = d / 2, d2 = 2 * nv;
+  cplx<T>* w = reinterpret_cast<cplx<T>*>(smem_raw);   // [na][hd][GC]
+  cplx<T>* u = w + (size_t)na * hd * GC;                // [na][d][GC]
+  long* tgt = reinterpret_cast<long*>(u + (size_t)na * d * GC);
+  const long Y = blockIdx.x;
+  const int sp = blockIdx.y, jv0 = blockIdx.z * GC;
+  const long vs = g.V * d;
+  const int t = threadIdx.x;
+  for (int e = t; e < na * hd * GC; e += 256) {
+    const int c = e % GC, rem = e / GC, k = rem % hd, sl = rem / hd;
+    int lc[4];
+    const long y = cagg_site(g, a, Y, sl, lc);
+    w[e] = jv0 + c < nv ? Store<S>::template ld<T>(P + (long)(jv0 + c) * vs + y * d + sp * hd + k) : mk<T>(0, 0);
+  }
+  __syncthreads();
+  for (int part = 0; part < 9; ++part) {
+    const int mu = (part - 1) >> 1;
+    const int step = ((part - 1) & 1) ? -1 : 1;
+    // stage 1: u = (part of D_c) w, rows (sl, i) over threads
+    for (int row = t; row < na * d; row += 256) {
+      const int sl = row / d, i = row - sl * d;
+      int lc[4];
+      const long y = cagg_site(g, a, Y, sl, lc);
+      int c[4];
+      coarse_coords(g, y, c);
+      cplx<T> acc[GC];
+#pragma unroll
+      for (int q = 0; q < GC; ++q) acc[q] = mk<T>(0, 0);
+      bool any = false;
+      if (part == 0) {
+        if (i == 0) tgt[sl] = y;
+        any = true;
+        for (int b = 0; b < 9; ++b) {
+          int nl;
+          if (b == 0) nl = sl;
+          else {
+            const int m = (b - 1) >> 1, stp = ((b - 1) & 1) ? -1 : 1;
+            const int v = lc[m] + stp;
+            if (v < 0 || v >= a.A[m]) continue;   // leaves the aggregate: a face part
+            int l2[4] = {lc[0], lc[1], lc[2], lc[3]};
+            l2[m] = v;
+            nl = ((l2[3] * a.A[2] + l2[2]) * a.A[1] + l2[1]) * a.A[0] + l2[0];
+          }
+          const SP<S>* Db = Dc1 + (y * 9L + b) * d * d + (long)sp * hd * d + i;
+          const cplx<T>* wn = w + (size_t)nl * hd * GC;
+          for (int k = 0; k < hd; ++k) {
+            const cplx<T> dv = Store<S>::template ld<T>(Db + (long)k * d);
+#pragma unroll
+            for (int q = 0; q < GC; ++q) cfma(acc[q], dv, wn[k * GC + q]);
+          }
+        }
+      } else {
+        const bool face = step > 0 ? (lc[mu] == 0) : (lc[mu] == a.A[mu] - 1);
+        if (face) {
+          const long tt = coarse_neighbour(g, c, mu, -step);
+          if (i == 0) tgt[sl] = tt;
+          any = true;
+          const SP<S>* Db = Dc1 + (tt * 9L + part) * d * d + (long)sp * hd * d + i;
+          const cplx<T>* wn = w + (size_t)sl * hd * GC;
+          for (int k = 0; k < hd; ++k) {
+            const cplx<T> dv = Store<S>::template ld<T>(Db + (long)k * d);
+#pragma unroll
+            for (int q = 0; q < GC; ++q) cfma(acc[q], dv, wn[k * GC + q]);
+          }
+        } else if (i == 0) {
+          tgt[sl] = -1;
+        }
+      }
+      if (any) {
+#pragma unroll
+        for (int q = 0; q < GC; ++q) u[(size_t)row * GC + q] = acc[q];
+      }
+    }
+    __syncthreads();
+    // stage 2: out[n][c] = sum over contributing sites and the n half of conj(P_n) u
+    {
+      const int wv = t >> 6;
+      cplx<T> acc[CPT];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) acc[q] = mk<T>(0, 0);
+      for (int n = t & 63; n < d2; n += 64) {
+        const int s = n / nv, iv = n - s * nv;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) acc[q] = mk<T>(0, 0);
+        for (int sl = 0; sl < na; ++sl) {
+          const long ts = tgt[sl];
+          if (ts < 0) continue;
+          const SP<S>* Pi = P + (long)iv * vs + ts * d + s * hd;
+          const cplx<T>* uu = u + ((size_t)sl * d + s * hd) * GC + wv * CPT;
+          for (int k = 0; k < hd; ++k) {
+            const cplx<T> pv = Store<S>::template ld<T>(Pi + k);
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) cfmac(acc[q], pv, uu[k * GC + q]);
+          }
+        }
+        long recv = Y;
+        if (part > 0) {
+          int yc[4];
+          long b = Y;
+          yc[0] = (int)(b % a.NA[0]); b /= a.NA[0];
+          yc[1] = (int)(b % a.NA[1]); b /= a.NA[1];
+          yc[2] = (int)(b % a.NA[2]);
+          yc[3] = (int)(b / a.NA[2]);
+          recv = coarse_neighbour(g2, yc, mu, -step);
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int jv = jv0 + wv * CPT + q;
+          if (jv < nv) Store<S>::st(Dc2 + ((recv * 9 + part) * (long)d2 + sp * nv + jv) * d2 + n, acc[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, typename S>
 void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const SP<S>* Dc1, const SP<S>* P, int nv,
                             SP<S>* Dc2, hipStream_t st) {
@@ -685,6 +815,18 @@ void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const 
   CoarseGeom g2;
   g2.V = 1;
   for (int m = 0; m < 4; ++m) { g2.L[m] = a.NA[m]; g2.V *= a.NA[m]; }
+  const size_t shc = (size_t)a.na * (d / 2 + d) * GAL_GC * sizeof(cplx<T>) + a.na * sizeof(long);
+  if (shc <= 150 * 1024) {
+    static bool attr = false;   // per instantiation: raise the dynamic LDS limit once
+    if (!attr && shc > 64 * 1024) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_coarse_cols<T, S>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_galerkin_coarse_cols<T, S>), dim3((unsigned)g2.V, 2, (nv + GAL_GC - 1) / GAL_GC),
+                       dim3(256), shc, st, g, d, a, Dc1, P, nv, Dc2, g2);
+    return;
+  }
   size_t sh = 2 * (size_t)a.na * d * sizeof(cplx<T>) + a.na * sizeof(long) + 256 * sizeof(cplx<T>);
   hipLaunchKernelGGL((k_galerkin_coarse<T, S>), dim3((unsigned)g2.V, 2 * nv), dim3(256), sh, st, g, d, a, Dc1, P, nv,
                      Dc2, g2);

@@ -147,65 +147,124 @@ __global__ void __launch_bounds__(256) k_gs_fine(FineGeom g, const cplx<T>* __re
 }
 // Cholesky QR, twice (CholQR2), for up to 32 vectors: per (aggregate,
 // chirality) workgroup the K = 6 * bvol rows of V = [v_1 .. v_nv] give the
-// Gram matrix G = V^dag V (FP64, accumulated from LDS tiles of rows), its
-// Cholesky factor G = R^dag R (positive real diagonal), and Q = V R^-1;
-// the second pass repeats this on Q.  Given the same v_i this is the same
-// Q as Gram-Schmidt in index order (the QR factor with positive diagonal
-// is unique) and needs a handful of barriers instead of a chain of nv^2
-// dependent reductions.
+// Gram matrix G1 = V^dag V (FP64, accumulated from LDS tiles of rows), its
+// Cholesky factor G1 = R1^dag R1 (positive real diagonal) and Q1 = V R1^-1;
+// the second pass takes the Gram matrix of Q1 (formed tile by tile from V,
+// never stored), its factor R2, and the result is Q = V (R1^-1 R2^-1).
+// Given the same v_i this is the Q of Gram-Schmidt in index order (the QR
+// factor with positive diagonal is unique); it reads V three times and
+// needs a handful of barriers instead of a chain of nv^2 dependent
+// reductions.
 constexpr int GS_NV = 32;   // largest nv of the Cholesky QR kernel
 constexpr int GS_TS = 8;    // sites per LDS tile
+constexpr int GS_NR = GS_TS * 6 / 2;   // row pairs per tile
 
-TM_D int gs_row_offset(int r, int sc) {   // tile row r = (site in tile, component)
-  return (sc * 6 + r % 6) * FT;
+// Tiles hold nvp = nv rounded up to 4 columns (the padding columns are
+// zero), rows (site in tile, component) as xs * 6 + k.
+TM_D int gs_nvp(int nv) { return (nv + 3) & ~3; }
+
+template <typename U>
+TM_D void gs_load_tile(const cplx<U>* src, long vs, long site0, int x0, int sc, int nv, int nvp, cplx<double>* tile) {
+  const int nrow = GS_TS * 6;
+  for (int e = threadIdx.x; e < nrow * nvp; e += blockDim.x) {
+    const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
+    cplx<double> v = mk(0.0, 0.0);
+    if (c < nv) {
+      const cplx<U> x = src[(long)c * vs + tsite((unsigned)(site0 + x0 + xs), 12) + (sc * 6 + k) * FT];
+      v = mk((double)x.re, (double)x.im);
+    }
+    tile[(xs * 6 + k) * nvp + c] = v;
+  }
 }
 
-// G = V^dag V over the aggregate's rows (src: nv fields of 12 V), lower
-// triangle mirrored.  tile: [GS_TS*6][nv]; G: [nv][nv] (row-major).
-template <typename U>
-TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int nv, cplx<double>* tile,
-                  cplx<double>* G) {
-  const int t = threadIdx.x;
-  const int np = nv * (nv + 1) / 2;
-  cplx<double> acc[(GS_NV * (GS_NV + 1) / 2 + 255) / 256];
-  constexpr int NPT = (GS_NV * (GS_NV + 1) / 2 + 255) / 256;
+// q = rows r0 and r0 + GS_NR of tile x M, columns 4 cg .. 4 cg + 3 (M upper
+// triangular nv x nv, so column c sums i <= c)
+TM_D void gs_rows_times(const cplx<double>* tile, int nv, int nvp, const cplx<double>* M, int r0, int cg,
+                        cplx<double> q[2][4]) {
 #pragma unroll
-  for (int q = 0; q < NPT; ++q) acc[q] = mk(0.0, 0.0);
-  for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
-    const int nrow = GS_TS * 6;
-    for (int e = t; e < nrow * nv; e += blockDim.x) {
-      const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
-      const long s = site0 + x0 + xs;
-      const cplx<U> v = src[(long)c * vs + tsite((unsigned)s, 12) + (sc * 6 + k) * FT];
-      tile[(xs * 6 + k) * nv + c] = mk((double)v.re, (double)v.im);
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[h][j] = mk(0.0, 0.0);
+  const int iend = min(4 * cg + 4, nv);
+  for (int i = 0; i < iend; ++i) {
+    const cplx<double> v0 = tile[r0 * nvp + i], v1 = tile[(r0 + GS_NR) * nvp + i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * cg + j;
+      const cplx<double> m = (c < nv && i <= c) ? M[i * nv + c] : mk(0.0, 0.0);
+      cfma(q[0][j], v0, m);
+      cfma(q[1][j], v1, m);
     }
-    __syncthreads();
+  }
+}
+
+// G = W^dag W over the aggregate's rows, W = V (XF == false) or V M.
+// Thread (block, slice): a 4x4 block (ba <= bb) of G over the tile rows
+// r = slice (mod nslice), 16 products per 8 values read from LDS; slices
+// are summed in slice order at the end.  G: [nv][nv], both triangles.
+template <typename U, bool XF>
+TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int nv, const cplx<double>* M,
+                  cplx<double>* tile, cplx<double>* G) {
+  const int t = threadIdx.x, nvp = gs_nvp(nv), nb = nvp / 4;
+  const int nblk = nb * (nb + 1) / 2, nslice = 256 / nblk;
+  const int nrow = GS_TS * 6;
+  const bool active = t < nblk * nslice;
+  const int blk = t % nblk, slice = t / nblk;
+  int ba = 0, bb = blk;
+  while (bb >= nb - ba) { bb -= nb - ba; ++ba; }
+  bb += ba;   // blocks (ba, bb), ba <= bb, in row order
+  const int r0 = t % GS_NR, cg = t / GS_NR;   // transform mapping
+  cplx<double> acc[4][4];
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-      const int pidx = t + q * 256;
-      if (pidx < np) {
-        int b = (int)((sqrtf(8.f * pidx + 1.f) - 1.f) * 0.5f);
-        while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
-        while (b * (b + 1) / 2 > pidx) --b;
-        const int a = pidx - b * (b + 1) / 2;   // a <= b
-        cplx<double> s2 = acc[q];
-        for (int r = 0; r < nrow; ++r) cfmac(s2, tile[r * nv + a], tile[r * nv + b]);
-        acc[q] = s2;
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
+  for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
+    gs_load_tile<U>(src, vs, site0, x0, sc, nv, nvp, tile);
+    __syncthreads();
+    if constexpr (XF) {
+      cplx<double> q[2][4];
+      if (cg < nb) gs_rows_times(tile, nv, nvp, M, r0, cg, q);
+      __syncthreads();
+      if (cg < nb) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) tile[(r0 + h * GS_NR) * nvp + 4 * cg + j] = q[h][j];
+      }
+      __syncthreads();
+    }
+    if (active) {
+      for (int r = slice; r < nrow; r += nslice) {
+        cplx<double> va[4], vb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          va[i] = tile[r * nvp + 4 * ba + i];
+          vb[i] = tile[r * nvp + 4 * bb + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cfmac(acc[i][j], va[i], vb[j]);
       }
     }
     __syncthreads();
   }
+  for (int sl = 0; sl < nslice; ++sl) {
+    if (active && slice == sl) {
 #pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    const int pidx = t + q * 256;
-    if (pidx < np) {
-      int b = (int)((sqrtf(8.f * pidx + 1.f) - 1.f) * 0.5f);
-      while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
-      while (b * (b + 1) / 2 > pidx) --b;
-      const int a = pidx - b * (b + 1) / 2;
-      G[a * nv + b] = acc[q];
-      G[b * nv + a] = conj(acc[q]);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 4 * ba + i, b2 = 4 * bb + j;
+          if (a < nv && b2 < nv && a <= b2) G[a * nv + b2] = sl == 0 ? acc[i][j] : G[a * nv + b2] + acc[i][j];
+        }
     }
+    __syncthreads();
+  }
+  for (int e = t; e < nv * nv; e += blockDim.x) {
+    const int a = e / nv, b2 = e % nv;
+    if (a > b2) G[e] = conj(G[b2 * nv + a]);
   }
   __syncthreads();
 }
@@ -242,46 +301,44 @@ TM_D void gs_chol_inv(int nv, cplx<double>* G, cplx<double>* Ri) {
   __syncthreads();
 }
 
-// Q = V Ri over the aggregate's rows: written to P64 (and P when final)
-template <typename U, typename S>
-TM_D void gs_apply(const cplx<U>* src, long vs, long site0, int bvol, int sc, int nv, const cplx<double>* Ri,
-                   cplx<double>* tile, cplx<double>* P64, SP<S>* P, bool final_pass) {
-  const int t = threadIdx.x;
-  const int nrow = GS_TS * 6;
-  for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
-    for (int e = t; e < nrow * nv; e += blockDim.x) {
-      const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
-      const long s = site0 + x0 + xs;
-      const cplx<U> v = src[(long)c * vs + tsite((unsigned)s, 12) + (sc * 6 + k) * FT];
-      tile[(xs * 6 + k) * nv + c] = mk((double)v.re, (double)v.im);
-    }
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T>* __restrict__ tv, int nv,
+                                                        SP<S>* __restrict__ P) {
+  __shared__ cplx<double> tile[GS_TS * 6 * GS_NV];   // nvp <= GS_NV columns
+  __shared__ cplx<double> G[GS_NV * GS_NV];
+  __shared__ cplx<double> Ra[GS_NV * GS_NV];
+  __shared__ cplx<double> Rb[GS_NV * GS_NV];
+  const int y = blockIdx.x, sc = blockIdx.y, t = threadIdx.x;
+  const long vs = 12 * g.V, site0 = (long)y * g.bvol;
+  const int nvp = gs_nvp(nv), nb = nvp / 4;
+  gs_gram<T, false>(tv, vs, site0, g.bvol, sc, nv, nullptr, tile, G);   // V^dag V
+  gs_chol_inv(nv, G, Ra);                                               // Ra = R1^-1
+  gs_gram<T, true>(tv, vs, site0, g.bvol, sc, nv, Ra, tile, G);         // Q1^dag Q1
+  gs_chol_inv(nv, G, Rb);                                               // Rb = R2^-1
+  // G = Ra Rb (upper triangular), the column transform taking V to Q
+  for (int e = t; e < nv * nv; e += 256) {
+    const int i = e / nv, c = e % nv;
+    cplx<double> s2 = mk(0.0, 0.0);
+    for (int l = i; l <= c; ++l) cfma(s2, Ra[i * nv + l], Rb[l * nv + c]);
+    G[e] = s2;
+  }
+  __syncthreads();
+  const int r0 = t % GS_NR, cg = t / GS_NR;
+  for (int x0 = 0; x0 < g.bvol; x0 += GS_TS) {
+    gs_load_tile<T>(tv, vs, site0, x0, sc, nv, nvp, tile);
     __syncthreads();
-    // thread e -> (vector c, row r), rows site-fastest so that the stores
-    // of consecutive lanes are contiguous; tile row of (xs, k) is xs*6 + k
-    constexpr int QPT = (GS_TS * 6 * GS_NV + 255) / 256;
-    cplx<double> q[QPT];
+    if (cg < nb) {
+      cplx<double> q[2][4];
+      gs_rows_times(tile, nv, nvp, G, r0, cg, q);
 #pragma unroll
-    for (int qq = 0; qq < QPT; ++qq) {
-      const int e = t + qq * 256;
-      q[qq] = mk(0.0, 0.0);
-      if (e < nrow * nv) {
-        const int c = e / nrow, r = e % nrow, tr = (r % GS_TS) * 6 + r / GS_TS;
-        cplx<double> s2 = mk(0.0, 0.0);
-        for (int i = 0; i <= c; ++i) cfma(s2, tile[tr * nv + i], Ri[i * nv + c]);
-        q[qq] = s2;
-      }
-    }
-    __syncthreads();   // src rows of this tile are all read before P64 (possibly src) is written
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + h * GS_NR, xs = r / 6, k = r % 6;
+        const size_t o0 = tsite((unsigned)(site0 + x0 + xs), 12) + (sc * 6 + k) * FT;
 #pragma unroll
-    for (int qq = 0; qq < QPT; ++qq) {
-      const int e = t + qq * 256;
-      if (e < nrow * nv) {
-        const int c = e / nrow, r = e % nrow;
-        const long s = site0 + x0 + r % GS_TS;
-        const size_t o = (size_t)c * vs + tsite((unsigned)s, 12) + (sc * 6 + r / GS_TS) * FT;
-        const cplx<double> val = q[qq];
-        if (final_pass) Store<S>::st(P + o, val);
-        P64[o] = val;
+        for (int j = 0; j < 4; ++j) {
+          const int c = 4 * cg + j;
+          if (c < nv) Store<S>::st(P + (size_t)c * vs + o0, q[h][j]);
+        }
       }
     }
     __syncthreads();
@@ -289,27 +346,9 @@ TM_D void gs_apply(const cplx<U>* src, long vs, long site0, int bvol, int sc, in
 }
 
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T>* __restrict__ tv, int nv,
-                                                        cplx<double>* P64, SP<S>* P) {
-  __shared__ cplx<double> tile[GS_TS * 6 * GS_NV];
-  __shared__ cplx<double> G[GS_NV * GS_NV];
-  __shared__ cplx<double> Ri[GS_NV * GS_NV];
-  const int y = blockIdx.x, sc = blockIdx.y;
-  const long vs = 12 * g.V, site0 = (long)y * g.bvol;
-  // pass 1 on the test vectors
-  gs_gram<T>(tv, vs, site0, g.bvol, sc, nv, tile, G);
-  gs_chol_inv(nv, G, Ri);
-  gs_apply<T, S>(tv, vs, site0, g.bvol, sc, nv, Ri, tile, P64, P, false);
-  // pass 2 on Q1 (in P64, rewritten in place tile by tile)
-  gs_gram<double>(P64, vs, site0, g.bvol, sc, nv, tile, G);
-  gs_chol_inv(nv, G, Ri);
-  gs_apply<double, S>(P64, vs, site0, g.bvol, sc, nv, Ri, tile, P64, P, true);
-}
-
-template <typename T, typename S>
 void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* P64, SP<S>* P, hipStream_t st) {
   if (nv <= GS_NV)
-    hipLaunchKernelGGL((k_gs_fine_cholqr<T, S>), dim3(g.nblocks, 2), dim3(256), 0, st, g, tv, nv, P64, P);
+    hipLaunchKernelGGL((k_gs_fine_cholqr<T, S>), dim3(g.nblocks, 2), dim3(256), 0, st, g, tv, nv, P);
   else
     hipLaunchKernelGGL((k_gs_fine<T, S>), dim3(g.nblocks, 2), dim3(g.bvol), 0, st, g, tv, nv, P64, P);
 }
