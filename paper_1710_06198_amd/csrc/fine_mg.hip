@@ -160,20 +160,37 @@ constexpr int GS_TS = 8;    // sites per LDS tile
 constexpr int GS_NR = GS_TS * 6 / 2;   // row pairs per tile
 
 // Tiles hold nvp = nv rounded up to 4 columns (the padding columns are
-// zero), rows (site in tile, component) as xs * 6 + k.
+// zero), rows (site in tile, component) as xs * 6 + k, row stride nvp + 1
+// (an odd stride keeps the lanes of a tile load in different LDS banks).
 TM_D int gs_nvp(int nv) { return (nv + 3) & ~3; }
 
+// A tile is fetched into registers (GS_EPT values per thread) while the
+// previous one is processed, then stored to LDS: the global latency of the
+// next tile overlaps the arithmetic on the current one.
+constexpr int GS_EPT = (GS_TS * 6 * GS_NV + 255) / 256;
+
 template <typename U>
-TM_D void gs_load_tile(const cplx<U>* src, long vs, long site0, int x0, int sc, int nv, int nvp, cplx<double>* tile) {
+TM_D void gs_fetch_tile(const cplx<U>* src, long vs, long site0, int x0, int sc, int nv, int nvp,
+                        cplx<double> (&reg)[GS_EPT]) {
   const int nrow = GS_TS * 6;
-  for (int e = threadIdx.x; e < nrow * nvp; e += blockDim.x) {
+#pragma unroll
+  for (int q = 0; q < GS_EPT; ++q) {
+    const int e = threadIdx.x + 256 * q;
     const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
-    cplx<double> v = mk(0.0, 0.0);
-    if (c < nv) {
+    reg[q] = mk(0.0, 0.0);
+    if (e < nrow * nvp && c < nv) {
       const cplx<U> x = src[(long)c * vs + tsite((unsigned)(site0 + x0 + xs), 12) + (sc * 6 + k) * FT];
-      v = mk((double)x.re, (double)x.im);
+      reg[q] = mk((double)x.re, (double)x.im);
     }
-    tile[(xs * 6 + k) * nvp + c] = v;
+  }
+}
+TM_D void gs_store_tile(int nvp, const cplx<double> (&reg)[GS_EPT], cplx<double>* tile) {
+  const int nrow = GS_TS * 6;
+#pragma unroll
+  for (int q = 0; q < GS_EPT; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int xs = e % GS_TS, rem = e / GS_TS, k = rem % 6, c = rem / 6;
+    if (e < nrow * nvp) tile[(xs * 6 + k) * (nvp + 1) + c] = reg[q];
   }
 }
 
@@ -187,7 +204,7 @@ TM_D void gs_rows_times(const cplx<double>* tile, int nv, int nvp, const cplx<do
     for (int j = 0; j < 4; ++j) q[h][j] = mk(0.0, 0.0);
   const int iend = min(4 * cg + 4, nv);
   for (int i = 0; i < iend; ++i) {
-    const cplx<double> v0 = tile[r0 * nvp + i], v1 = tile[(r0 + GS_NR) * nvp + i];
+    const cplx<double> v0 = tile[r0 * (nvp + 1) + i], v1 = tile[(r0 + GS_NR) * (nvp + 1) + i];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = 4 * cg + j;
@@ -219,9 +236,12 @@ TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = mk(0.0, 0.0);
+  cplx<double> reg[GS_EPT];
+  gs_fetch_tile<U>(src, vs, site0, 0, sc, nv, nvp, reg);
   for (int x0 = 0; x0 < bvol; x0 += GS_TS) {
-    gs_load_tile<U>(src, vs, site0, x0, sc, nv, nvp, tile);
+    gs_store_tile(nvp, reg, tile);
     __syncthreads();
+    if (x0 + GS_TS < bvol) gs_fetch_tile<U>(src, vs, site0, x0 + GS_TS, sc, nv, nvp, reg);
     if constexpr (XF) {
       cplx<double> q[2][4];
       if (cg < nb) gs_rows_times(tile, nv, nvp, M, r0, cg, q);
@@ -230,7 +250,7 @@ TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) tile[(r0 + h * GS_NR) * nvp + 4 * cg + j] = q[h][j];
+          for (int j = 0; j < 4; ++j) tile[(r0 + h * GS_NR) * (nvp + 1) + 4 * cg + j] = q[h][j];
       }
       __syncthreads();
     }
@@ -239,8 +259,8 @@ TM_D void gs_gram(const cplx<U>* src, long vs, long site0, int bvol, int sc, int
         cplx<double> va[4], vb[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          va[i] = tile[r * nvp + 4 * ba + i];
-          vb[i] = tile[r * nvp + 4 * bb + i];
+          va[i] = tile[r * (nvp + 1) + 4 * ba + i];
+          vb[i] = tile[r * (nvp + 1) + 4 * bb + i];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -304,7 +324,7 @@ TM_D void gs_chol_inv(int nv, cplx<double>* G, cplx<double>* Ri) {
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T>* __restrict__ tv, int nv,
                                                         SP<S>* __restrict__ P) {
-  __shared__ cplx<double> tile[GS_TS * 6 * GS_NV];   // nvp <= GS_NV columns
+  __shared__ cplx<double> tile[GS_TS * 6 * (GS_NV + 1)];   // rows of nvp <= GS_NV columns, stride nvp + 1
   __shared__ cplx<double> G[GS_NV * GS_NV];
   __shared__ cplx<double> Ra[GS_NV * GS_NV];
   __shared__ cplx<double> Rb[GS_NV * GS_NV];
@@ -324,9 +344,12 @@ __global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T
   }
   __syncthreads();
   const int r0 = t % GS_NR, cg = t / GS_NR;
+  cplx<double> reg[GS_EPT];
+  gs_fetch_tile<T>(tv, vs, site0, 0, sc, nv, nvp, reg);
   for (int x0 = 0; x0 < g.bvol; x0 += GS_TS) {
-    gs_load_tile<T>(tv, vs, site0, x0, sc, nv, nvp, tile);
+    gs_store_tile(nvp, reg, tile);
     __syncthreads();
+    if (x0 + GS_TS < g.bvol) gs_fetch_tile<T>(tv, vs, site0, x0 + GS_TS, sc, nv, nvp, reg);
     if (cg < nb) {
       cplx<double> q[2][4];
       gs_rows_times(tile, nv, nvp, G, r0, cg, q);
@@ -438,45 +461,59 @@ TM_D void lds_spinor(const cplx<T>* wl, int bv, int sp, int nl, cplx<T>* pn) {
   for (int k = 0; k < 12; ++k) pn[k] = (k / 6 == sp) ? wl[(k % 6) * bv + nl] : mk<T>(0, 0);
 }
 
+// One direction of k_galerkin_z: the two links at x (U_mu(x) and
+// U_mu(x - mu)) serve the aggregate-internal forward and backward hops
+// (accumulated into v0, part 0) and the two face hops that leave the
+// aggregate through its lower (part 1 + 2 mu) and upper (part 2 + 2 mu) mu
+// face, which are written to the receiving aggregate's slot at once.
 template <int MU, typename T>
-TM_D void intra_hops(const FineOp<T>& op, const cplx<T>* wl, int sp, long s, int loc, const int c[4], cplx<T>* acc) {
+TM_D void galerkin_z_dir(const FineOp<T>& op, const cplx<T>* wl, int sp, long s, int loc, const int c[4],
+                         const int yc[4], const cplx<T>* wx, cplx<T>* v0, cplx<T>* Z, const GalerkinZ& zl, int jl,
+                         long slot) {
   const FineGeom& g = op.g;
-  const int bv = g.bvol;
   const int lc = c[MU] % g.B[MU];
+  const long sb = fine_neighbour(g, s, c, MU, -1);
+  const M3<T> uf = load_link(op.links, MU, s, g.V);
+  const M3<T> ub = load_link(op.links, MU, sb, g.V);
   cplx<T> pn[12];
   if (lc < g.B[MU] - 1) {
-    lds_spinor<MU>(wl, bv, sp, loc + g.lstride[MU], pn);
-    M3<T> u = load_link(op.links, MU, s, g.V);
-    hop_fwd<MU>(u, pn, acc);
+    lds_spinor<MU>(wl, g.bvol, sp, loc + g.lstride[MU], pn);
+    hop_fwd<MU>(uf, pn, v0);
   }
   if (lc > 0) {
-    lds_spinor<MU>(wl, bv, sp, loc - g.lstride[MU], pn);
-    M3<T> ub = load_link(op.links, MU, s - g.lstride[MU], g.V);
-    hop_bwd<MU>(ub, pn, acc);
+    lds_spinor<MU>(wl, g.bvol, sp, loc - g.lstride[MU], pn);
+    hop_bwd<MU>(ub, pn, v0);
   }
-}
-
-// the hop that carries w(x) out of y through its mu face, for source sites
-// on that face: step > 0 is the forward hop at x - mu (lower face of y),
-// step < 0 the backward hop at x + mu (upper face of y)
-template <int MU, typename T>
-TM_D bool face_hop(const FineOp<T>& op, int step, long s, const int c[4], const cplx<T>* wx, cplx<T>* v, long& tgt_site) {
-  const FineGeom& g = op.g;
-  const int lc = c[MU] % g.B[MU];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
-  if (step > 0) {
-    if (lc != 0) return false;
-    tgt_site = fine_neighbour(g, s, c, MU, -1);
-    M3<T> u = load_link(op.links, MU, tgt_site, g.V);
-    hop_fwd<MU>(u, wx, v);
-  } else {
-    if (lc != g.B[MU] - 1) return false;
-    tgt_site = fine_neighbour(g, s, c, MU, +1);
-    M3<T> u = load_link(op.links, MU, s, g.V);
-    hop_bwd<MU>(u, wx, v);
+  for (int side = 0; side < 2; ++side) {
+    // side 0: lower face, forward hop at x - mu (step +1); side 1: upper face, backward hop at x + mu (step -1)
+    if (side == 0 ? lc != 0 : lc != g.B[MU] - 1) continue;
+    const int step = side == 0 ? 1 : -1, part = side == 0 ? 1 + 2 * MU : 2 + 2 * MU;
+    cplx<T> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
+    long ts;
+    if (side == 0) {
+      ts = sb;
+      hop_fwd<MU>(ub, wx, v);
+    } else {
+      ts = fine_neighbour(g, s, c, MU, +1);
+      hop_bwd<MU>(uf, wx, v);
+    }
+    int rc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) rc[m] = m == MU ? (yc[m] - step + g.NB[m]) % g.NB[m] : yc[m];
+    const long recv = block_index(g, rc);
+    int tc[4];
+    fine_coords(g, ts, tc);
+    int tl[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) tl[m] = tc[m] % g.B[m];
+    const int r = face_index(g, tl, MU);
+    cplx<T>* zo = Z + recv * slot + (long)zl.regoff[part] * 12 * zl.cb + (long)jl * 12 * zl.regsz[part] + r;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) zo[(long)k * zl.regsz[part]] = v[k];
   }
-  return true;
 }
 
 template <typename T, typename S>
@@ -511,54 +548,22 @@ __global__ void __launch_bounds__(256) k_galerkin_z(FineOp<T> op, const SP<S>* _
     yc[3] = b / g.NB[2];
   }
   const long slot = (long)12 * zl.cb * zl.za;   // elements per aggregate
-#pragma unroll 1
-  for (int part = 0; part < 9; ++part) {
-    cplx<T> v[12];
-    long recv = y;
-    int r = loc;
-    bool on = true;
-    if (part == 0) {
+  cplx<T> v0[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] = mk<T>(0, 0);
-      clover_block_mv(op.clover, (unsigned)s, V, wx, v);
-      clover_block_mv(op.clover + 36 * V, (unsigned)s, V, wx + 6, v + 6);
-      compiler_fence(v);
-      intra_hops<0>(op, wl, sp, s, loc, c, v);
-      compiler_fence(v);
-      intra_hops<1>(op, wl, sp, s, loc, c, v);
-      compiler_fence(v);
-      intra_hops<2>(op, wl, sp, s, loc, c, v);
-      compiler_fence(v);
-      intra_hops<3>(op, wl, sp, s, loc, c, v);
-    } else {
-      const int mu = (part - 1) >> 1;
-      const int step = ((part - 1) & 1) ? -1 : 1;
-      long ts = 0;
-      switch (mu) {
-        case 0: on = face_hop<0>(op, step, s, c, wx, v, ts); break;
-        case 1: on = face_hop<1>(op, step, s, c, wx, v, ts); break;
-        case 2: on = face_hop<2>(op, step, s, c, wx, v, ts); break;
-        default: on = face_hop<3>(op, step, s, c, wx, v, ts); break;
-      }
-      if (on) {
-        int rc[4];
+  for (int k = 0; k < 12; ++k) v0[k] = mk<T>(0, 0);
+  clover_block_mv(op.clover, (unsigned)s, V, wx, v0);
+  clover_block_mv(op.clover + 36 * V, (unsigned)s, V, wx + 6, v0 + 6);
+  // FP64: one direction at a time (the links of all four do not fit in registers)
+  galerkin_z_dir<0>(op, wl, sp, s, loc, c, yc, wx, v0, Z, zl, jl, slot);
+  if constexpr (sizeof(T) == 8) compiler_fence(v0);
+  galerkin_z_dir<1>(op, wl, sp, s, loc, c, yc, wx, v0, Z, zl, jl, slot);
+  if constexpr (sizeof(T) == 8) compiler_fence(v0);
+  galerkin_z_dir<2>(op, wl, sp, s, loc, c, yc, wx, v0, Z, zl, jl, slot);
+  if constexpr (sizeof(T) == 8) compiler_fence(v0);
+  galerkin_z_dir<3>(op, wl, sp, s, loc, c, yc, wx, v0, Z, zl, jl, slot);
+  cplx<T>* zo = Z + (long)y * slot + (long)jl * 12 * zl.regsz[0] + loc;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) rc[m] = m == mu ? (yc[m] - step + g.NB[m]) % g.NB[m] : yc[m];
-        recv = block_index(g, rc);
-        int tc[4];
-        fine_coords(g, ts, tc);
-        int lc[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) lc[m] = tc[m] % g.B[m];
-        r = face_index(g, lc, mu);
-      }
-    }
-    if (on) {
-      cplx<T>* zo = Z + recv * slot + (long)zl.regoff[part] * 12 * zl.cb + (long)jl * 12 * zl.regsz[part] + r;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) zo[(long)k * zl.regsz[part]] = v[k];
-    }
-  }
+  for (int k = 0; k < 12; ++k) zo[(long)k * zl.regsz[0]] = v0[k];
 }
 
 // D_c[r][part][c0 + j][i] = sum_x sum_{k in chirality of i} conj(P_i(x)_k) Z(x)_{k j}
@@ -628,6 +633,105 @@ __global__ void __launch_bounds__(256) k_galerkin_proj(FineGeom g, const SP<S>* 
   }
 }
 
+// The same projection with the site sum split over the four waves and a
+// register block of RPL x 4 outputs per lane: tiles of sites of P (all N_v vectors)
+// and Z (the chunk's columns) in LDS; wave w takes sites x = w (mod 4) of
+// a tile, lane (rg, cgp) the rows of chirality rg / 8, vectors
+// iv = rg % 8 + 8 a (a < RPL), and the columns 4 cgp .. 4 cgp + 3, so each
+// LDS value read feeds several products.  The waves' partial sums meet in LDS at the end.
+template <typename T> constexpr int gp_ts() { return 16; }   // sites per tile (two workgroups per CU)
+
+template <typename T, typename S, int RPL>
+__global__ void __launch_bounds__(256) k_galerkin_proj4(FineGeom g, const SP<S>* __restrict__ P, int nv,
+                                                        GalerkinZ zl, const cplx<T>* __restrict__ Z,
+                                                        SP<S>* __restrict__ Dc) {
+  constexpr int GP_TS = gp_ts<T>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // site strides padded by one element so that the 32 sites of a tile
+  // written by consecutive lanes fall into different LDS banks
+  const int PS = 12 * nv + 1, ZS = 12 * zl.cb + 1;
+  cplx<T>* Pt = reinterpret_cast<cplx<T>*>(smem_raw);   // [GP_TS][PS]: [x][k][iv]
+  cplx<T>* Zt = Pt + GP_TS * PS;                        // [GP_TS][ZS]: [x][k][j]
+  int r, part;
+  if (!xcd_decode(blockIdx.x, g.nblocks, 9, r, part)) return;
+  const long V = g.V;
+  const int no = 2 * nv, cb = zl.cb, rs = zl.regsz[part];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int rg = lane & 15, cgp = lane >> 4, sc = rg >> 3;
+  int mu = 0, cm = 0;
+  if (part > 0) {
+    mu = (part - 1) >> 1;
+    cm = ((part - 1) & 1) ? 0 : g.B[mu] - 1;   // upper face for the forward neighbour
+  }
+  const cplx<T>* zr = Z + (long)r * 12 * cb * zl.za + (long)zl.regoff[part] * 12 * cb;
+  cplx<T> acc[RPL][4];   // RPL = ceil(nv / 8) rows per lane
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = mk<T>(0, 0);
+  // loads: thread t stages site x = t % GP_TS of the tile, pairs (k, iv) or
+  // (k, j) stepping by 256 / GP_TS, so the site index is formed once
+  constexpr int XST = 256 / GP_TS;
+  const int xt = t % GP_TS, pt0 = t / GP_TS;
+  for (int x0 = 0; x0 < rs; x0 += GP_TS) {
+    const int nx = min(GP_TS, rs - x0);
+    if (xt < nx) {
+      const int loc = part == 0 ? x0 + xt : face_local(g, x0 + xt, mu, cm);
+      const SP<S>* pb = P + tsite((unsigned)((long)r * g.bvol + loc), 12);
+      for (int kv = pt0; kv < 12 * nv; kv += XST) {
+        const int k = kv % 12, iv = kv / 12;
+        Pt[xt * PS + k * nv + iv] = Store<S>::template ld<T>(pb + (long)iv * 12 * V + k * FT);
+      }
+      const cplx<T>* zb = zr + x0 + xt;
+      for (int kj = pt0; kj < 12 * cb; kj += XST) {
+        const int k = kj % 12, j = kj / 12;
+        Zt[xt * ZS + k * cb + j] = zb[(long)(j * 12 + k) * rs];
+      }
+    }
+    __syncthreads();
+    for (int x = wv; x < nx; x += 4) {
+#pragma unroll 2
+      for (int kk = 0; kk < 6; ++kk) {
+        const int k = 6 * sc + kk;
+        cplx<T> pv[RPL], zv[4];
+#pragma unroll
+        for (int a = 0; a < RPL; ++a) {
+          const int iv = (rg & 7) + 8 * a;
+          pv[a] = iv < nv ? Pt[x * PS + k * nv + iv] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = 4 * cgp + b;
+          zv[b] = j < cb ? Zt[x * ZS + k * cb + j] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < RPL; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) cfmac(acc[a][b], pv[a], zv[b]);
+      }
+    }
+    __syncthreads();
+  }
+  // partial sums of the four waves: red[w][a][b][lane]
+  cplx<T>* red = Pt;
+#pragma unroll
+  for (int a = 0; a < RPL; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) red[((wv * 4 + a) * 4 + b) * 64 + lane] = acc[a][b];
+  __syncthreads();
+  for (int e = t; e < RPL * 4 * 64; e += 256) {
+    const int ln = e & 63, ab = e >> 6, a = ab >> 2, b = ab & 3;
+    const int rg2 = ln & 15, cg2 = ln >> 4, sc2 = rg2 >> 3;
+    const int iv = (rg2 & 7) + 8 * a, j = 4 * cg2 + b;
+    if (iv < nv && j < cb) {
+      cplx<T> sum = red[(a * 4 + b) * 64 + ln];
+      for (int w2 = 1; w2 < 4; ++w2) sum += red[((w2 * 4 + a) * 4 + b) * 64 + ln];
+      const int i = sc2 * nv + iv;
+      Store<S>::st(Dc + (((long)r * 9 + part) * no + zl.c0 + j) * no + i, sum);
+    }
+  }
+}
+
 size_t galerkin_ws_per_column(const FineGeom& g) {
   const GalerkinZ z = galerkin_layout(g, 0, 1);
   return (size_t)g.nblocks * 12 * z.za;
@@ -649,10 +753,34 @@ void launch_galerkin_fine(const FineOp<T>& op, const SP<S>* P, int nv, SP<S>* Dc
   const int n8 = (g.nblocks + 7) / 8 * 8;
   constexpr int TS = sizeof(T) == 4 ? 8 : 4;
   const size_t lds = (size_t)TS * 12 * (nv + cb) * sizeof(cplx<T>);
+  // the register-blocked projection: up to 32 vectors and 16 columns
+  const size_t lds4 = (size_t)gp_ts<T>() * (12 * (nv + cb) + 2) * sizeof(cplx<T>);
+  // the wave partials (4 waves x RPL x 4 x 64 values) reuse the P and Z tiles
+  const int rpl = nv <= 24 ? 3 : 4;
+  const bool use4 = nv <= 32 && cb <= 16 && lds4 <= 150 * 1024 &&
+                    (size_t)gp_ts<T>() * (12 * (nv + cb) + 2) >= (size_t)rpl * 1024;
+  if (use4 && lds4 > 64 * 1024) {
+    static bool attr = false;
+    if (!attr) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 3>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 4>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      attr = true;
+    }
+  }
   for (int c0 = 0; c0 < no; c0 += cb) {
     const GalerkinZ zl = galerkin_layout(g, c0, std::min(cb, no - c0));
     hipLaunchKernelGGL((k_galerkin_z<T, S>), dim3((unsigned)(n8 * zl.cb)), dim3(g.bvol), 0, st, op, P, nv, zl, zws);
-    hipLaunchKernelGGL((k_galerkin_proj<T, S>), dim3((unsigned)(n8 * 9)), dim3(256), lds, st, g, P, nv, zl, zws, Dc);
+    if (use4 && rpl == 3)
+      hipLaunchKernelGGL((k_galerkin_proj4<T, S, 3>), dim3((unsigned)(n8 * 9)), dim3(256), lds4, st, g, P, nv, zl,
+                         zws, Dc);
+    else if (use4)
+      hipLaunchKernelGGL((k_galerkin_proj4<T, S, 4>), dim3((unsigned)(n8 * 9)), dim3(256), lds4, st, g, P, nv, zl,
+                         zws, Dc);
+    else
+      hipLaunchKernelGGL((k_galerkin_proj<T, S>), dim3((unsigned)(n8 * 9)), dim3(256), lds, st, g, P, nv, zl, zws,
+                         Dc);
   }
 }
 
