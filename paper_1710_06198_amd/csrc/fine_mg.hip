@@ -368,6 +368,10 @@ __global__ void __launch_bounds__(256) k_gs_fine_cholqr(FineGeom g, const cplx<T
   }
 }
 
+// The Cholesky QR path needs no FP64 copy of the vectors; the sequential
+// Gram-Schmidt fallback (more than GS_NV vectors) keeps its pieces in one.
+bool gs_fine_needs_fp64_copy(int nv) { return nv > GS_NV; }
+
 template <typename T, typename S>
 void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* P64, SP<S>* P, hipStream_t st) {
   if (nv <= GS_NV)

@@ -434,17 +434,22 @@ TM_D void block_reduce3(T& a, T& b, T& c, T* red) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                                                   const double* __restrict__ mu_dev, const int* __restrict__ blist,
-                                                  int mr_steps) {
+                                                  int nblk, int nrhs, int mr_steps) {
   extern __shared__ unsigned char smem_raw[];
   const FineGeom& g = op.g;
   const long V = g.V;
   const int bv = g.bvol;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* red = reinterpret_cast<T*>(lds + 12 * bv);
-  const int r = blockIdx.y;
+  // workgroup -> (block, rhs): the right-hand sides of one block run on one
+  // XCD one after the other, so its links and clover come from that L2
+  // after the first; with one right-hand side this is the identity
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int r = rest % nrhs, bi = (rest / nrhs) * 8 + x8;
+  if (bi >= nblk) return;
   const T mu = (T)mu_dev[r];
   const int loc = threadIdx.x;
-  const unsigned s = (unsigned)blist[blockIdx.x] * bv + loc;
+  const unsigned s = (unsigned)blist[bi] * bv + loc;
   const cplx<T>* zr = z + (long)r * 12 * V;
   int c[4];
   fine_coords(g, s, c);
@@ -494,8 +499,9 @@ template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
                      const int* block_list, int nblk, int mr_steps, hipStream_t st) {
   size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
-  dim3 grid(nblk, nrhs);
-  hipLaunchKernelGGL(k_sap_fine<T>, grid, dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list, mr_steps);
+  const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
+  hipLaunchKernelGGL(k_sap_fine<T>, dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list, nblk,
+                     nrhs, mr_steps);
 }
 template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                       const int*, int, int, hipStream_t);

@@ -139,6 +139,7 @@ void launch_sap_coarse(const CoarseGeom& g, int d, const int blk[4], const typen
 template <typename T>
 void launch_gamma5_coarse(long V, int d, const cplx<T>* in, cplx<T>* out, int nrhs, hipStream_t st);
 // block Gram-Schmidt (FP64): tv (T) -> P64 scratch and P (S)
+bool gs_fine_needs_fp64_copy(int nv);
 template <typename T, typename S>
 void launch_gs_fine(const FineGeom& g, const cplx<T>* tv, int nv, cplx<double>* P64, typename Store<S>::pair* P,
                     hipStream_t st);

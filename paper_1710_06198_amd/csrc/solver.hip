@@ -400,14 +400,15 @@ void Hier<T, S>::setup(double mu) {
   tv0.alloc((size_t)nv0 * n0);
   P0.alloc((size_t)nv0 * n0);
   Dc1.alloc((size_t)g1.V * 9 * d1 * d1);
-  size_t p64 = (size_t)nv0 * n0;
+  // FP64 scratch of the orthonormalisation (the fine level's Cholesky QR needs none)
+  size_t p64 = gs_fine_needs_fp64_copy(nv0) ? (size_t)nv0 * n0 : 0;
   if (nlev >= 3) {
     tv1.alloc((size_t)nv1 * g1.V * d1);
     P1.alloc((size_t)nv1 * g1.V * d1);
     Dc2.alloc((size_t)g2.V * 9 * d2 * d2);
     p64 = std::max(p64, (size_t)nv1 * g1.V * d1);
   }
-  P64.alloc(p64);
+  P64.alloc(std::max<size_t>(p64, 1));
   ensure(std::max(nv0, nv1));
   tvtmp.alloc((size_t)nv0 * n0);
   mu_setup.alloc(std::max(nv0, nv1));
