@@ -61,6 +61,36 @@ TM_D int cblk_nbr(const CBlk& cb, C4 lc, int mu, int step) {
 TM_D int hop_mu(int b) { return (b - 1) >> 1; }
 TM_D int hop_step(int b) { return ((b - 1) & 1) ? -1 : 1; }
 
+// Source site of each of the nine blocks of site y (the site itself, then
+// its neighbours), formed once per workgroup in LDS rather than per staged
+// element; ends with a barrier.  The in-block variant gives -1 where the
+// hop leaves the SAP block.
+TM_D void stage_sources(const CoarseGeom& g, long y, const C4& c, long* src9) {
+  if (threadIdx.x < 9) {
+    const int b = threadIdx.x;
+    src9[b] = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
+  }
+  __syncthreads();
+}
+TM_D void stage_block_sources(const CoarseGeom& g, const CBlk& cb, int blk, long y, const C4& lc, long* src9) {
+  if (threadIdx.x < 9) {
+    const int b = threadIdx.x;
+    long v = y;
+    if (b != 0) {
+      const int nl = cblk_nbr(cb, lc, hop_mu(b), hop_step(b));
+      if (nl < 0) {
+        v = -1;
+      } else {
+        C4 cn, lcn;
+        cblk_site(cb, blk, nl, cn, lcn);
+        v = cc_index(g, cn);
+      }
+    }
+    src9[b] = v;
+  }
+  __syncthreads();
+}
+
 // Partial products of one site's D rows for NR right-hand sides:
 // red[q][ks][i] summed over ks gives
 //   sum_{b in mask} sum_j Dm[b][j][i] vst[q][b*D + j].
@@ -112,6 +142,181 @@ TM_D cplx<T> site_mv_row(const cplx<T>* red, int i) {
   return s;
 }
 
+// ------------------------------------------------------------------ batched site rows on the matrix cores
+// With 16 right-hand sides and a bf16 D_c the product of site_mv,
+//   out[q][i] = sum_{b in mask} sum_j D_b(i, j) v[q][b D + j],
+// is a complex (D x 9D) x (9D x 16) matrix product.  It runs as real
+// 16x16x16 bf16 MFMA products with FP32 accumulation:
+//   Re out = Re D Re v - Im D Im v,   Im out = Re D Im v + Im D Re v.
+// The D_c entries are exact in bf16.  Each FP32 vector entry is split as
+// v = v_hi + v_lo, v_hi = bf16(v), v_lo = bf16(v - v_hi), which keeps v to
+// 2^-18 of its size, so a 16x16 tile takes 8 products per 16 terms of the
+// sum.  Wave w takes the blocks b = w (mod 4) for all row tiles; the four
+// partial sums are left in the slots of blocks 1..4 of vst (the own-site
+// slot, block 0, keeps the input) and summed by the reader.
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+constexpr int MF_NR = 16;   // right-hand sides per workgroup on the matrix cores
+
+template <typename T, typename S, int D> constexpr bool mf_ok() {
+  return std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value && D % 16 == 0;
+}
+
+TM_D unsigned short bf16_bits_rne(float x) {   // round to nearest even
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);   // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+TM_D float bf16_bits_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+struct MfSplit {
+  mf_s4 rh, rl, ih, il, nih, nil;   // hi/lo parts of Re v, Im v and -Im v
+};
+TM_D MfSplit mf_split(const cplx<float>* v) {
+  MfSplit o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const unsigned short rh = bf16_bits_rne(v[e].re), ih = bf16_bits_rne(v[e].im);
+    const unsigned short rl = bf16_bits_rne(v[e].re - bf16_bits_float(rh));
+    const unsigned short il = bf16_bits_rne(v[e].im - bf16_bits_float(ih));
+    o.rh[e] = (short)rh;
+    o.rl[e] = (short)rl;
+    o.ih[e] = (short)ih;
+    o.il[e] = (short)il;
+    o.nih[e] = (short)(ih ^ 0x8000u);
+    o.nil[e] = (short)(il ^ 0x8000u);
+  }
+  return o;
+}
+
+// vst: [16][9D] staged inputs; on return (after a barrier) the partial
+// sums of wave w are at vst[q * 9D + (1 + w) D + i]
+template <int D>
+TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsigned mask) {
+  constexpr int MT = D / 16, KS = D / 16, K9 = 9 * D;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  const unsigned* __restrict__ Du = reinterpret_cast<const unsigned*>(Dm);
+  mf_f4 accr[MT], acci[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = mf_f4{0.f, 0.f, 0.f, 0.f};
+  // this wave's blocks b = w (mod 4) that are in the mask, 4 bits each
+  int blocks = 0, nb = 0;
+  for (int b = w; b < 9; b += 4)
+    if ((mask >> b) & 1u) blocks |= b << (4 * nb++);
+  // all D_c fragments of the next block are loaded while the current block
+  // runs on the matrix cores
+  unsigned an[KS][MT][4];
+  auto load_a = [&](int ib) {
+    const int b = (blocks >> (4 * ib)) & 15;
+    const unsigned* dp = Du + (size_t)(b * D + 4 * lk) * D + lr;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) an[ks][mt][e] = dp[(16 * ks + e) * D + 16 * mt];
+  };
+  if (nb > 0) load_a(0);
+  for (int ib = 0; ib < nb; ++ib) {
+    unsigned ac[KS][MT][4];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ac[ks][mt][e] = an[ks][mt][e];
+    if (ib + 1 < nb) load_a(ib + 1);
+    const int b = (blocks >> (4 * ib)) & 15;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int j0 = 16 * ks + 4 * lk;
+      cplx<float> v4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v4[e] = vst[lr * K9 + b * D + j0 + e];
+      const MfSplit bb = mf_split(v4);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        mf_s4 ar, ai;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ar[e] = (short)(ac[ks][mt][e] & 0xffffu);
+          ai[e] = (short)(ac[ks][mt][e] >> 16);
+        }
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci[mt], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();   // every wave has read the neighbour slots
+  // C tile layout: lane l holds rows 4 (l / 16) + v of the tile, column l % 16
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vst[lr * K9 + (1 + w) * D + 16 * mt + 4 * lk + v] = mk(accr[mt][v], acci[mt][v]);
+  __syncthreads();
+}
+template <int D>
+TM_D cplx<float> site_mv_mfma_row(const cplx<float>* vst, int q, int i) {
+  const cplx<float>* p = vst + q * 9 * D + D + i;
+  return (p[0] + p[D]) + (p[2 * D] + p[3 * D]);
+}
+
+// D_c(mu_r) for 16 right-hand sides per workgroup (one coarse site) on the
+// matrix cores; vst is dynamic LDS of 16 * 9 D complex values
+template <int D>
+__global__ void __launch_bounds__(256) k_coarse_apply_mf(CoarseGeom g, const bf16pair* __restrict__ Dc,
+                                                         const cplx<float>* __restrict__ in,
+                                                         cplx<float>* __restrict__ out, int nrhs,
+                                                         const double* __restrict__ mu_dev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<float>* vst = reinterpret_cast<cplx<float>*>(smem_raw);
+  const long y = blockIdx.x;
+  const int r0 = blockIdx.y * MF_NR;
+  const long VD = g.V * D;
+  const int t = threadIdx.x;
+  const C4 c = cc_coords(g, y);
+  __shared__ long src9[9];
+  stage_sources(g, y, c, src9);
+  for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
+    const int k = 2 * k2, q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
+    const long src = src9[b];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + q < nrhs) v = *reinterpret_cast<const float4*>(in + (r0 + q) * VD + src * D + j);
+    *reinterpret_cast<float4*>(vst + k) = v;
+  }
+  __syncthreads();
+  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, 0x1FFu);
+  for (int e = t; e < MF_NR * D; e += 256) {
+    const int q = e / D, i = e - q * D, r = r0 + q;
+    if (r >= nrhs) continue;
+    const float mu = (float)mu_dev[r];
+    cplx<float> acc = site_mv_mfma_row<D>(vst, q, i);
+    acc += (i < D / 2 ? mu : -mu) * times_i(vst[q * 9 * D + i]);
+    out[r * VD + y * D + i] = acc;
+  }
+}
+
+template <int D>
+static void coarse_apply_mf(const CoarseGeom& g, const bf16pair* Dc, const cplx<float>* in, cplx<float>* out,
+                            int nrhs, const double* mu_dev, hipStream_t st) {
+  const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
+  static bool attr = false;
+  if (!attr && lds > 64 * 1024) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_apply_mf<D>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_coarse_apply_mf<D>), dim3((unsigned)g.V, (nrhs + MF_NR - 1) / MF_NR), dim3(256), lds, st, g,
+                     Dc, in, out, nrhs, mu_dev);
+}
+
 // ------------------------------------------------------------------ coarse operator, one site per workgroup
 // D_c(mu_r) for NR right-hand sides per workgroup (one coarse site), with
 // the slice mapping of site_mv: 16-byte D_c loads, many in flight per
@@ -127,9 +332,11 @@ __global__ void __launch_bounds__(256) k_coarse_apply_site(CoarseGeom g, const S
   const long VD = g.V * D;
   const int t = threadIdx.x;
   const C4 c = cc_coords(g, y);
+  __shared__ long src9[9];
+  stage_sources(g, y, c, src9);
   for (int k = t; k < NR * 9 * D; k += 256) {
     const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
-    const long src = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
+    const long src = src9[b];
     vst[k] = r0 + q < nrhs ? in[(r0 + q) * VD + src * D + j] : mk<T>(0, 0);
   }
   __syncthreads();
@@ -147,6 +354,12 @@ __global__ void __launch_bounds__(256) k_coarse_apply_site(CoarseGeom g, const S
 template <typename T, typename S, int D>
 static void coarse_apply_site(const CoarseGeom& g, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out, int nrhs,
                               const double* mu_dev, hipStream_t st) {
+  if constexpr (mf_ok<T, S, D>()) {
+    if (nrhs >= 8) {
+      coarse_apply_mf<D>(g, Dc, in, out, nrhs, mu_dev, st);
+      return;
+    }
+  }
   if (nrhs >= 4)
     hipLaunchKernelGGL((k_coarse_apply_site<T, S, D, 4>), dim3((unsigned)g.V, (nrhs + 3) / 4), dim3(256), 0, st, g,
                        Dc, in, out, nrhs, mu_dev);
@@ -225,9 +438,11 @@ __global__ void __launch_bounds__(256) k_sap1_resid(SapArgs a, const SP<S>* __re
   C4 c, lc;
   cblk_site(a.cb, a.bl[bi], sl, c, lc);
   const long y = cc_index(g, c);
+  __shared__ long src9[9];
+  stage_sources(g, y, c, src9);
   for (int k = t; k < NR * 9 * D; k += 256) {
     const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
-    const long src = b == 0 ? y : cc_nbr(g, c, hop_mu(b), hop_step(b));
+    const long src = src9[b];
     vst[k] = r0 + q < a.nrhs ? z[(r0 + q) * VD + src * D + j] : mk<T>(0, 0);
   }
   __syncthreads();
@@ -267,20 +482,16 @@ __global__ void __launch_bounds__(256) k_sap1_mr(SapArgs a, const SP<S>* __restr
   cblk_site(cb, blk, sl, c, lc);
   const long y = cc_index(g, c);
   if (!first) block_alpha<T, NR>(part_in, bi, cb.nbs, a.nrhs, r0, alpha_s);
-  unsigned mask = 1u;
-  for (int b = 1; b < 9; ++b)
-    if (cblk_nbr(cb, lc, hop_mu(b), hop_step(b)) >= 0) mask |= 1u << b;
+  __shared__ long src9[9];
+  stage_block_sources(g, cb, blk, y, lc, src9);
+  unsigned mask = 0u;
+  for (int b = 0; b < 9; ++b)
+    if (src9[b] >= 0) mask |= 1u << b;
   for (int k = t; k < NR * 9 * D; k += 256) {
     const int q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D, r = r0 + q;
-    const int nl = b == 0 ? sl : cblk_nbr(cb, lc, hop_mu(b), hop_step(b));
     cplx<T> v = mk<T>(0, 0);
-    if (nl >= 0 && r < a.nrhs) {
-      long src = y;
-      if (b != 0) {
-        C4 cn, lcn;
-        cblk_site(cb, blk, nl, cn, lcn);
-        src = cc_index(g, cn);
-      }
+    const long src = src9[b];
+    if (src >= 0 && r < a.nrhs) {
       v = rho_in[r * VD + src * D + j];
       if (!first) {
         const cplx<T> al = alpha_s[q];
@@ -346,6 +557,162 @@ __global__ void __launch_bounds__(256) k_sap1_fin(SapArgs a, cplx<T>* __restrict
   }
 }
 
+// The residual and MR steps for 16 right-hand sides per workgroup on the
+// matrix cores (bf16 D_c, FP32 vectors); same data flow as k_sap1_resid
+// and k_sap1_mr, vst in dynamic LDS.
+template <int D>
+__global__ void __launch_bounds__(256) k_sap1_resid_mf(SapArgs a, const bf16pair* __restrict__ Dc,
+                                                       const cplx<float>* __restrict__ eta,
+                                                       const cplx<float>* __restrict__ z,
+                                                       cplx<float>* __restrict__ rho,
+                                                       const double* __restrict__ mu_dev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<float>* vst = reinterpret_cast<cplx<float>*>(smem_raw);
+  const CoarseGeom& g = a.g;
+  const long VD = g.V * D;
+  const int t = threadIdx.x;
+  int bi, sl, r0;
+  sap_unit<MF_NR>(a, blockIdx.x, bi, sl, r0);
+  C4 c, lc;
+  cblk_site(a.cb, a.bl[bi], sl, c, lc);
+  const long y = cc_index(g, c);
+  __shared__ long src9[9];
+  stage_sources(g, y, c, src9);
+  for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
+    const int k = 2 * k2, q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D;
+    const long src = src9[b];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + q < a.nrhs) v = *reinterpret_cast<const float4*>(z + (r0 + q) * VD + src * D + j);
+    *reinterpret_cast<float4*>(vst + k) = v;
+  }
+  __syncthreads();
+  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, 0x1FFu);
+  for (int e = t; e < MF_NR * D; e += 256) {
+    const int q = e / D, i = e - q * D, r = r0 + q;
+    if (r >= a.nrhs) continue;
+    const float mu = (float)mu_dev[r];
+    cplx<float> acc = site_mv_mfma_row<D>(vst, q, i);
+    acc += (i < D / 2 ? mu : -mu) * times_i(vst[q * 9 * D + i]);
+    rho[r * VD + y * D + i] = eta[r * VD + y * D + i] - acc;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* __restrict__ Dc,
+                                                    cplx<float>* __restrict__ z,
+                                                    const cplx<float>* __restrict__ rho_in,
+                                                    const cplx<float>* __restrict__ q_in,
+                                                    const double* __restrict__ part_in,
+                                                    cplx<float>* __restrict__ rho_out, cplx<float>* __restrict__ q_out,
+                                                    double* __restrict__ part_out, const double* __restrict__ mu_dev,
+                                                    int first) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<float>* vst = reinterpret_cast<cplx<float>*>(smem_raw);
+  __shared__ cplx<float> alpha_s[MF_NR];
+  const CoarseGeom& g = a.g;
+  const CBlk& cb = a.cb;
+  const long VD = g.V * D;
+  const int t = threadIdx.x;
+  int bi, sl, r0;
+  sap_unit<MF_NR>(a, blockIdx.x, bi, sl, r0);
+  const int blk = a.bl[bi];
+  C4 c, lc;
+  cblk_site(cb, blk, sl, c, lc);
+  const long y = cc_index(g, c);
+  if (!first) block_alpha<float, MF_NR>(part_in, bi, cb.nbs, a.nrhs, r0, alpha_s);
+  __shared__ long src9[9];
+  stage_block_sources(g, cb, blk, y, lc, src9);
+  unsigned mask = 0u;
+  for (int b = 0; b < 9; ++b)
+    if (src9[b] >= 0) mask |= 1u << b;
+  for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
+    const int k = 2 * k2, q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D, r = r0 + q;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const long src = src9[b];
+    if (src >= 0 && r < a.nrhs) {
+      v = *reinterpret_cast<const float4*>(rho_in + r * VD + src * D + j);
+      if (!first) {
+        const cplx<float> al = alpha_s[q];
+        const float4 qv = *reinterpret_cast<const float4*>(q_in + r * VD + src * D + j);
+        v.x -= al.re * qv.x - al.im * qv.y;
+        v.y -= al.re * qv.y + al.im * qv.x;
+        v.z -= al.re * qv.z - al.im * qv.w;
+        v.w -= al.re * qv.w + al.im * qv.z;
+      }
+    }
+    *reinterpret_cast<float4*>(vst + k) = v;
+  }
+  __syncthreads();
+  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, mask);
+  // wave q: right-hand sides r0 + q, r0 + q + 4, ...; lanes over rows
+  const int wq = t >> 6, lane = t & 63;
+  for (int q = wq; q < MF_NR; q += 4) {
+    const int r = r0 + q;
+    if (r >= a.nrhs) continue;   // uniform across the wave
+    float qq = 0, qre = 0, qim = 0;
+    if (lane < D) {
+      const float mu = (float)mu_dev[r];
+      const cplx<float> rho = vst[q * 9 * D + lane];
+      cplx<float> acc = site_mv_mfma_row<D>(vst, q, lane);
+      acc += (lane < D / 2 ? mu : -mu) * times_i(rho);
+      const long o = r * VD + y * D + lane;
+      q_out[o] = acc;
+      rho_out[o] = rho;
+      if (!first) cfma(z[o], alpha_s[q], rho_in[o]);
+      qq = norm2(acc);
+      const cplx<float> tq = cmulc(acc, rho);
+      qre = tq.re;
+      qim = tq.im;
+    }
+    qq = wave_sum(qq);
+    qre = wave_sum(qre);
+    qim = wave_sum(qim);
+    if (lane == 0) {
+      const long u = ((long)bi * cb.nbs + sl) * a.nrhs + r;
+      part_out[3 * u] = qq;
+      part_out[3 * u + 1] = qre;
+      part_out[3 * u + 2] = qim;
+    }
+  }
+}
+
+template <int D>
+static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc, const cplx<float>* eta,
+                         cplx<float>* z, int nrhs, const double* mu, const int* const bl[2], const int nb[2],
+                         int sweeps, int mr, cplx<float>* const rho[2], cplx<float>* const q[2],
+                         double* const part[2], hipStream_t st) {
+  const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
+  static bool attr = false;
+  if (!attr && lds > 60 * 1024) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr = true;
+  }
+  SapArgs a;
+  a.g = g;
+  a.cb = cb;
+  a.nrhs = nrhs;
+  const int ng = (nrhs + MF_NR - 1) / MF_NR;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int col = 0; col < 2; ++col) {
+      const int units = nb[col] * cb.nbs * ng;
+      if (units == 0) continue;
+      a.bl = bl[col];
+      hipLaunchKernelGGL((k_sap1_resid_mf<D>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
+      for (int k = 0; k < mr; ++k) {
+        const int in = (k + 1) & 1, out = k & 1;
+        hipLaunchKernelGGL((k_sap1_mr_mf<D>), dim3(units), dim3(256), lds, st, a, Dc, z, rho[in], q[in], part[in],
+                           rho[out], q[out], part[out], mu, k == 0 ? 1 : 0);
+      }
+      if (mr > 0) {
+        const int in = (mr - 1) & 1;
+        hipLaunchKernelGGL((k_sap1_fin<float, D, MF_NR>), dim3(units), dim3(256), 0, st, a, z, rho[in], part[in]);
+      }
+    }
+}
+
 template <typename T, typename S, int D, int NR>
 static void sap_fused(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const cplx<T>* eta, cplx<T>* z, int nrhs,
                       const double* mu, const int* const bl[2], const int nb[2], int sweeps, int mr,
@@ -374,6 +741,19 @@ static void sap_fused(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, cons
     }
 }
 
+template <typename T, typename S, int D>
+static bool sap_mf(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const cplx<T>* eta, cplx<T>* z, int nrhs,
+                   const double* mu, const int* const bl[2], const int nb[2], int sweeps, int mr,
+                   cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
+  if constexpr (mf_ok<T, S, D>()) {
+    if (nrhs >= 8) {
+      sap_fused_mf<D>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, rho, q, part, st);
+      return true;
+    }
+  }
+  return false;
+}
+
 template <typename T, typename S>
 bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const SP<S>* Dc, const cplx<T>* eta,
                              cplx<T>* z, int nrhs, const double* mu_dev, const int* bl0, int n0, const int* bl1,
@@ -392,10 +772,12 @@ bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const
   const int* bl[2] = {bl0, bl1};
   const int nb[2] = {n0, n1};
   // one right-hand side per workgroup, or four (FP64: two) sharing each D_c load
+  // eight or more right-hand sides with a bf16 D_c: 16 per workgroup on the matrix cores
 #define SAP_CASE(DD)                                                                                   \
   if (nrhs == 1) sap_fused<T, S, DD, 1>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); \
-  else sap_fused<T, S, DD, sizeof(T) == 4 ? 4 : 2>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q,  \
-                                                     part, st);
+  else if (!sap_mf<T, S, DD>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st))            \
+    sap_fused<T, S, DD, sizeof(T) == 4 ? 4 : 2>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q,     \
+                                                  part, st);
   switch (d) {
     case 24: SAP_CASE(24) break;
     case 32: SAP_CASE(32) break;

@@ -357,3 +357,64 @@ def test_coarsest_gmres_three_level():
     s.setup(Ud, kappa_of(m0), 1.6, 0.003)
     cdims = tuple(a // b // c for a, b, c in zip(dims, agg[0], agg[1]))
     check_coarsest(s, 2, cdims, 1, [0.003], 24, 1e-3, 7200)
+
+
+# The batched coarse operator and level-1 SAP on the matrix cores: 16
+# right-hand sides per workgroup, bf16 D_c, each FP32 vector entry split
+# into two bf16 parts (kept to 2^-18 of its size), FP32 accumulation.
+# Checked against the oracle's FP64 arithmetic on the same stored D_c,
+# with 20 right-hand sides (one full group of 16 and a ragged one) and
+# per-RHS signed mu; 4 right-hand sides take the vector-ALU kernels on the
+# same data.  Bars from the arithmetic: the split keeps each input to
+# 4e-6, sums of a few hundred FP32 products add 1e-6.
+@pytest.fixture(scope="module")
+def mixed_three_level_d48():
+    dims = (8, 8, 16, 16)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1237)
+    agg = ((4, 4, 4, 4), (2, 2, 2, 2))
+    sap1 = (1, 1, 2, 2)
+    p = tm.default_params(nlevels=3, agg=agg, nv=(24, 32), sap_block1=sap1, setup_iters=1, precision=tm.MIXED,
+                          storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+    cd1 = tuple(a // b for a, b in zip(dims, agg[0]))
+    cd2 = tuple(a // b for a, b in zip(cd1, agg[1]))
+    return s, cd1, cd2, sap1
+
+
+@pytest.mark.parametrize("level,nrhs", [(1, 20), (2, 20), (1, 4), (2, 4)])
+def test_coarse_operator_batched_mixed(mixed_three_level_d48, level, nrhs):
+    s, cd1, cd2, sap1 = mixed_three_level_d48
+    cdims = cd1 if level == 1 else cd2
+    Dc, Vc, d = coarse_op_from_export(s, level, cdims)
+    say(f"batched D_c, level {level} (d = {d}), {nrhs} RHS, mixed bf16")
+    mus = [0.003 * (1 + r) * (-1) ** r for r in range(nrhs)]
+    v = mg.random_test_vectors(cdims, d, nrhs, 7300 + level)
+    vd = to_dev(v.reshape(nrhs, Vc, d).numpy())
+    out = torch.empty_like(vd)
+    s.apply(tm.OP_DC, level, vd, out, mus)
+    worst = 0.0
+    for r in range(nrhs):
+        ref = Dc.apply(v[r], mus[r])
+        worst = max(worst, rel(out.cpu()[r], ref.reshape(Vc, d)))
+    say(f"  worst rel. difference {worst:.2e}")
+    assert worst < 2e-5
+
+
+@pytest.mark.parametrize("nrhs", [20, 4])
+def test_coarse_sap_batched_mixed(mixed_three_level_d48, nrhs):
+    s, cd1, cd2, sap1 = mixed_three_level_d48
+    Dc, Vc, d = coarse_op_from_export(s, 1, cd1)
+    say(f"batched level-1 SAP (d = {d}), {nrhs} RHS, mixed bf16")
+    mus = [0.003 * (1 + r) * (-1) ** r for r in range(nrhs)]
+    v = mg.random_test_vectors(cd1, d, nrhs, 7310)
+    vd = to_dev(v.reshape(nrhs, Vc, d).numpy())
+    out = torch.empty_like(vd)
+    s.apply(tm.OP_SAP, 1, vd, out, mus)
+    worst = 0.0
+    for r in range(nrhs):
+        ref = mg.sap(Dc, v[r], torch.zeros_like(v[r]), mus[r], sap1, 2, 4)
+        worst = max(worst, rel(out.cpu()[r], ref.reshape(Vc, d)))
+    say(f"  worst rel. difference {worst:.2e}")
+    assert worst < 1e-4
