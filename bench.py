@@ -51,6 +51,27 @@ def stencil_traffic(workload_name):
     return rec["bytes_per_launch"]
 
 
+MFMA_BF16_PEAK_TFS = 2500.0   # MI355X dense bf16 matrix peak
+
+
+def batched_coarse(tm, solver, reps):
+    """The level-1 coarse operator with 16 right-hand sides (one workgroup
+    per coarse site, 16 RHS on the matrix cores) timed with HIP events.
+    Executed MFMA work per launch: sites x 9 blocks x d^2 x 16 RHS complex
+    products, each as 4 real products on a 2-part bf16 split of the FP32
+    input, i.e. 16 flops per complex product (the useful complex arithmetic
+    is half of that)."""
+    nrhs = 16
+    vc, d = solver.level_info(1)
+    ms = solver.time_kernel(tm.K_DC1, nrhs, reps)
+    sap_ms = solver.time_kernel(tm.K_SAP1, nrhs, max(2, reps // 4))
+    flops = vc * 9 * d * d * nrhs * 16
+    tfs = flops / (ms * 1e-3) / 1e12
+    return {"kernel": f"k_coarse_apply_mf<{d}>", "rhs": nrhs, "sites": vc, "d": d, "ms": round(ms, 4),
+            "flops_per_launch": flops, "achieved": round(tfs, 2), "peak": MFMA_BF16_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(tfs / MFMA_BF16_PEAK_TFS, 4), "sap1_sweep_16rhs_ms": round(sap_ms, 4)}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -275,7 +296,9 @@ def main():
         mixed.setup(U, kappa, w.csw, w.mu)
         d_ms = mixed.time_kernel(tm.K_DSLASH32, 1, 10)
         c_ms = mixed.time_kernel(tm.K_COPY, 1, 10)
-        print(json.dumps({"dslash_fp32_ms": d_ms, "copy_512MiB_ms": c_ms, "sites": w.volume}), flush=True)
+        mf = batched_coarse(tm, mixed, 10)
+        print(json.dumps({"dslash_fp32_ms": d_ms, "copy_512MiB_ms": c_ms, "sites": w.volume, "mfma": mf}),
+              flush=True)
         mixed.close()
         return 0
     for i in range(args.warmup):
@@ -308,6 +331,7 @@ def main():
         except tm.TmamgError:
             pass
     kern["dslash_fp32"] = round(st_ms, 4)
+    mfma = batched_coarse(tm, mixed, 20)
 
     fp64 = None
     if not args.no_fp64:
@@ -357,6 +381,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stencil_traffic(w.name),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_dslash<float> (fine stencil)", "bytes_per_site": bytes_site, "sites": V},
+        "mfma_batched_coarse": mfma,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
