@@ -78,15 +78,16 @@ def log(*a):
 
 def solver_params(tm, w, precision):
     """The workload's hierarchy.  With three levels the intermediate FGMRES
-    takes at most 5 steps and the coarsest GMRES at most 20: a sweep on the
-    24^3 x 48 job (intermediate 3-15, coarsest 10-70 steps) showed the outer
-    iteration count barely moving (14 at 10/50, 19 at 5/20) while the
-    coarse solves' time fell by two thirds.  Both precisions use the same
-    hierarchy, so the FP64 comparison solver gets the same saving."""
+    takes at most 6 steps and the coarsest GMRES at most 10: sweeps on the
+    24^3 x 48 job (intermediate 3-15, coarsest 10-70 steps) moved the outer
+    iteration count only between 14 and 26 while the coarse solves got
+    several times cheaper (14 outer iterations at 10/50, 17 at 6/10).  Both
+    precisions use the same hierarchy, so the FP64 comparison solver gets
+    the same saving."""
     p = dict(nlevels=w.nlevels, agg=w.agg, nv=w.nv, setup_iters=w.setup_iters, init_smooth=w.init_smooth,
              sap_sweeps=w.sap_sweeps, mr_steps=w.mr_steps, restart=w.restart, precision=precision,
-             storage=tm.STORE_BF16, coarsest_iters=20 if w.nlevels == 3 else 100,
-             l2_iters=5 if w.nlevels == 3 else 10)
+             storage=tm.STORE_BF16, coarsest_iters=10 if w.nlevels == 3 else 100,
+             l2_iters=6 if w.nlevels == 3 else 10)
     if w.nlevels == 3:
         p["sap_block1"] = w.sap_block[1]
     return tm.default_params(**p)
