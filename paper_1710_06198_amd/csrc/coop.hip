@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "mfma.h"
 
 template <typename S> using SP = typename Store<S>::pair;
 
@@ -154,40 +155,10 @@ TM_D cplx<T> site_mv_row(const cplx<T>* red, int i) {
 // sum.  Wave w takes the blocks b = w (mod 4) for all row tiles; the four
 // partial sums are left in the slots of blocks 1..4 of vst (the own-site
 // slot, block 0, keeps the input) and summed by the reader.
-typedef short mf_s4 __attribute__((ext_vector_type(4)));
-typedef float mf_f4 __attribute__((ext_vector_type(4)));
 constexpr int MF_NR = 16;   // right-hand sides per workgroup on the matrix cores
 
 template <typename T, typename S, int D> constexpr bool mf_ok() {
   return std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value && D % 16 == 0;
-}
-
-TM_D unsigned short bf16_bits_rne(float x) {   // round to nearest even
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);   // NaN stays NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-TM_D float bf16_bits_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
-
-struct MfSplit {
-  mf_s4 rh, rl, ih, il, nih, nil;   // hi/lo parts of Re v, Im v and -Im v
-};
-TM_D MfSplit mf_split(const cplx<float>* v) {
-  MfSplit o;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const unsigned short rh = bf16_bits_rne(v[e].re), ih = bf16_bits_rne(v[e].im);
-    const unsigned short rl = bf16_bits_rne(v[e].re - bf16_bits_float(rh));
-    const unsigned short il = bf16_bits_rne(v[e].im - bf16_bits_float(ih));
-    o.rh[e] = (short)rh;
-    o.rl[e] = (short)rl;
-    o.ih[e] = (short)ih;
-    o.il[e] = (short)il;
-    o.nih[e] = (short)(ih ^ 0x8000u);
-    o.nil[e] = (short)(il ^ 0x8000u);
-  }
-  return o;
 }
 
 // vst: [16][9D] staged inputs; on return (after a barrier) the partial

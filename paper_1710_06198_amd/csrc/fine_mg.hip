@@ -2,7 +2,10 @@
 // the fine lattice and the first coarse level, block Gram-Schmidt of the
 // fine test vectors, and the Galerkin coarse operator D_c = P^dag D P
 // (Sec. 1.1).  Aggregates are the blocks of the fine site ordering.
+#include <type_traits>
+
 #include "kernels.h"
+#include "mfma.h"
 #include "solver.h"
 #include "su3.h"
 
@@ -736,6 +739,99 @@ __global__ void __launch_bounds__(256) k_galerkin_proj4(FineGeom g, const SP<S>*
   }
 }
 
+// The projection on the matrix cores (bf16 P, FP32 Z, N_v <= 32, at most
+// 16 columns): per chirality s the block is a (N_v x K) x (K x cb) product
+// over K = sites x 6 components,
+//   Re = Re P . Re Z + Im P . Im Z,   Im = Re P . Im Z - Im P . Re Z,
+// with P exact in bf16 and Z split into two bf16 parts (Z to 2^-18 of its
+// size), run as 16x16x16 bf16 MFMA tiles with FP32 accumulation.  Wave w
+// owns chirality w / 2 and row tile w % 2 (vectors 16 (w % 2) ..), so the
+// waves need no reduction.  Tiles of 16 sites of P (raw bf16 pairs) and Z
+// in LDS, loaded as in k_galerkin_proj4.
+constexpr int GPM_TS = 16;
+
+__global__ void __launch_bounds__(256) k_galerkin_proj_mf(FineGeom g, const bf16pair* __restrict__ P, int nv,
+                                                          GalerkinZ zl, const cplx<float>* __restrict__ Z,
+                                                          bf16pair* __restrict__ Dc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int PS = 12 * nv + 1, ZS = 12 * zl.cb + 1;
+  unsigned* Pt = reinterpret_cast<unsigned*>(smem_raw);                 // [GPM_TS][PS]: [x][k][iv], bf16 pairs
+  cplx<float>* Zt = reinterpret_cast<cplx<float>*>(Pt + ((GPM_TS * PS + 1) & ~1));   // [GPM_TS][ZS]: [x][k][j]
+  int r, part;
+  if (!xcd_decode(blockIdx.x, g.nblocks, 9, r, part)) return;
+  const long V = g.V;
+  const int no = 2 * nv, cb = zl.cb, rs = zl.regsz[part];
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  const int sc = wv >> 1, mt = wv & 1;   // chirality and row tile of this wave
+  int mu = 0, cm = 0;
+  if (part > 0) {
+    mu = (part - 1) >> 1;
+    cm = ((part - 1) & 1) ? 0 : g.B[mu] - 1;
+  }
+  const cplx<float>* zr = Z + (long)r * 12 * cb * zl.za + (long)zl.regoff[part] * 12 * cb;
+  const unsigned* Pu = reinterpret_cast<const unsigned*>(P);
+  mf_f4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  constexpr int XST = 256 / GPM_TS;
+  const int xt = t % GPM_TS, pt0 = t / GPM_TS;
+  const int iv = 16 * mt + lr;   // this lane's row of A
+  for (int x0 = 0; x0 < rs; x0 += GPM_TS) {
+    const int nx = min(GPM_TS, rs - x0);
+    if (xt < nx) {
+      const int loc = part == 0 ? x0 + xt : face_local(g, x0 + xt, mu, cm);
+      const unsigned* pb = Pu + tsite((unsigned)((long)r * g.bvol + loc), 12);
+      for (int kv = pt0; kv < 12 * nv; kv += XST) {
+        const int k = kv % 12, v = kv / 12;
+        Pt[xt * PS + k * nv + v] = pb[(long)v * 12 * V + k * FT];
+      }
+      const cplx<float>* zb = zr + x0 + xt;
+      for (int kj = pt0; kj < 12 * cb; kj += XST) {
+        const int k = kj % 12, j = kj / 12;
+        Zt[xt * ZS + k * cb + j] = zb[(long)(j * 12 + k) * rs];
+      }
+    }
+    __syncthreads();
+    // K steps of 16 over (site, component of chirality sc): kk = x * 6 + k
+    const int nk = nx * 6;
+    for (int k0 = 0; k0 < nk; k0 += 16) {
+      mf_s4 ar, ai;
+      cplx<float> zv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = k0 + 4 * lk + e;
+        const int x = kk / 6, kc = 6 * sc + kk % 6;
+        unsigned u = 0u;
+        cplx<float> z = mk<float>(0, 0);
+        if (kk < nk) {
+          if (iv < nv) u = Pt[x * PS + kc * nv + iv];
+          if (lr < cb) z = Zt[x * ZS + kc * cb + lr];
+        }
+        ar[e] = (short)(u & 0xffffu);
+        ai[e] = (short)(u >> 16);
+        zv[e] = z;
+      }
+      const MfSplit bb = mf_split(zv);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // C tile: lane l holds rows 4 (l / 16) + v (vector 16 mt + ...), column j = l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int ivo = 16 * mt + 4 * lk + v, j = lr;
+    if (ivo < nv && j < cb) {
+      const int i = sc * nv + ivo;
+      Store<__hip_bfloat16>::st(Dc + (((long)r * 9 + part) * no + zl.c0 + j) * no + i, mk(accr[v], acci[v]));
+    }
+  }
+}
+
 size_t galerkin_ws_per_column(const FineGeom& g) {
   const GalerkinZ z = galerkin_layout(g, 0, 1);
   return (size_t)g.nblocks * 12 * z.za;
@@ -776,6 +872,13 @@ void launch_galerkin_fine(const FineOp<T>& op, const SP<S>* P, int nv, SP<S>* Dc
   for (int c0 = 0; c0 < no; c0 += cb) {
     const GalerkinZ zl = galerkin_layout(g, c0, std::min(cb, no - c0));
     hipLaunchKernelGGL((k_galerkin_z<T, S>), dim3((unsigned)(n8 * zl.cb)), dim3(g.bvol), 0, st, op, P, nv, zl, zws);
+    if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
+      if (nv <= 32 && zl.cb <= 16) {
+        const size_t ldsm = ((size_t)GPM_TS * (12 * nv + 1) + 1) / 2 * 2 * 4 + (size_t)GPM_TS * (12 * zl.cb + 1) * 8;
+        hipLaunchKernelGGL(k_galerkin_proj_mf, dim3((unsigned)(n8 * 9)), dim3(256), ldsm, st, g, P, nv, zl, zws, Dc);
+        continue;
+      }
+    }
     if (use4 && rpl == 3)
       hipLaunchKernelGGL((k_galerkin_proj4<T, S, 3>), dim3((unsigned)(n8 * 9)), dim3(256), lds4, st, g, P, nv, zl,
                          zws, Dc);

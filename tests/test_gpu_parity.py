@@ -120,6 +120,43 @@ def test_prolongation_and_galerkin(c1, injected_c1):
         assert rel(D[:, 2 + 2 * m], Dc.B[m].reshape(-1, d, d)) < 1e-12
 
 
+# Mixed precision with bf16 storage: P is the oracle's block Gram-Schmidt
+# rounded to bf16, and D_c is the library's FP32 Galerkin product (its
+# projection on the matrix cores) from that rounded P, rounded to bf16.
+# Checked against the oracle's FP64 product from the library's own rounded
+# P.  Bars from the arithmetic: bf16 rounding (2^-9 relative per entry)
+# dominates both.
+@pytest.mark.parametrize("nv", [24, 16])
+def test_prolongation_and_galerkin_mixed_bf16(c1, nv):
+    w, m0, U, Ud, op = c1
+    say("P / D_c parity c1, mixed bf16, nv", nv)
+    s = make_solver(w, precision=tm.MIXED, storage=tm.STORE_BF16, setup_iters=0, init_smooth=0, nv=(nv, 0))
+    tv, tvd = spinors(w.dims, 4331 + nv, nv)
+    s.set_test_vectors(0, tvd)
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    lx, ly, lz, lt = w.dims
+    Pg = torch.empty((nv, lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device=DEV)
+    s.export(0, 0, Pg)
+    Vr = field(Pg.cpu())                                   # the library's rounded P as nv fields
+    P64 = mg.build_prolongation(field(tv), w.agg[0], w.dims, 12)
+    Q = mg.to_blocks(Vr, w.agg[0], True).movedim(0, -1).contiguous()
+    Pr = mg.Prolongation(Q, w.agg[0], w.dims, 12)
+    err_p = rel(Pr.Q, P64.Q)
+    say(f"  P vs FP64 Gram-Schmidt: {err_p:.2e}")
+    assert err_p < 4e-3
+    Dc = mg.galerkin(op, Pr)
+    Vc, d = s.level_info(1)
+    D = torch.empty((Vc, 9, d, d), dtype=torch.complex128, device=DEV)
+    s.export(1, 1, D)
+    D = D.cpu().transpose(-1, -2)
+    errs = [rel(D[:, 0], Dc.S.reshape(-1, d, d))]
+    for m in range(4):
+        errs.append(rel(D[:, 1 + 2 * m], Dc.F[m].reshape(-1, d, d)))
+        errs.append(rel(D[:, 2 + 2 * m], Dc.B[m].reshape(-1, d, d)))
+    say(f"  D_c blocks, worst rel. difference {max(errs):.2e}")
+    assert max(errs) < 4e-3
+
+
 def test_transfers_and_coarse_operator(c1, injected_c1):
     w, m0, U, Ud, op = c1
     s, P, Dc = injected_c1
