@@ -1313,9 +1313,11 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
     __syncthreads();
 
     // Classical Gram-Schmidt with |w|^2 in the same reduction; a second pass
-    // only where the first lost more than half of |w|^2 (the DGKS
-    // criterion, ||w - V c|| < ||w|| / sqrt 2).  Every workgroup takes the
-    // same decision from the same sums.
+    // only where the first cancelled more than one digit of w
+    // (||w - V c|| < ||w|| / 10, a DGKS-type test with a threshold of 0.1: the
+    // short coarsest solves, at most a few dozen steps to a relative 1e-1,
+    // do not need the classical 1/sqrt 2).  Every workgroup takes the same
+    // decision from the same sums.
     double hn = 0;
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
@@ -1359,7 +1361,7 @@ __global__ void __launch_bounds__(256) k_coarsest_gmres_site(SiteGmres a, const 
       double r2 = w2;
       for (int l = 0; l <= j; ++l) r2 -= cc[2 * l] * cc[2 * l] + cc[2 * l + 1] * cc[2 * l + 1];
       hn = r2 > 0 ? sqrt(r2) : 0.0;
-      if (pass == 0 && r2 >= 0.5 * w2) {
+      if (pass == 0 && r2 >= 0.01 * w2) {
         for (int e = t; e < 2 * (j + 2); e += 256) c2[e] = 0;
         __syncthreads();
         break;   // same decision in every workgroup

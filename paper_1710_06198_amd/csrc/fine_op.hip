@@ -431,8 +431,10 @@ TM_D void block_reduce3(T& a, T& b, T& c, T* red) {
   __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
+// MINB: workgroups per CU the register allocation aims for (3 for
+// batches, where more resident blocks hide more of the L2 latency)
+template <typename T, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                                                   const double* __restrict__ mu_dev, const int* __restrict__ blist,
                                                   int nblk, int nrhs, int mr_steps) {
   extern __shared__ unsigned char smem_raw[];
@@ -500,8 +502,15 @@ void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nr
                      const int* block_list, int nblk, int mr_steps, hipStream_t st) {
   size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
   const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
-  hipLaunchKernelGGL(k_sap_fine<T>, dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list, nblk,
-                     nrhs, mr_steps);
+  if constexpr (sizeof(T) == 4) {
+    if (nrhs > 1) {
+      hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
+                         block_list, nblk, nrhs, mr_steps);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_sap_fine<T, 1>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list,
+                     nblk, nrhs, mr_steps);
 }
 template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                       const int*, int, int, hipStream_t);
