@@ -16,11 +16,17 @@ template <typename S> using SP = typename Store<S>::pair;
 // out(y, s*nv + i) = sum_{x in y} sum_{k in s} conj(P_i[k](x)) in[k](x)
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_restrict_fine(FineGeom g, const SP<S>* __restrict__ P, int nv,
-                                                       const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out) {
+                                                       const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                       int nrhs) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* red = reinterpret_cast<cplx<T>*>(smem_raw);   // [nwaves][2nv]
   const long V = g.V;
-  const int y = blockIdx.x, r = blockIdx.y;
+  // workgroup -> (aggregate, rhs): the right-hand sides of one aggregate run
+  // on one XCD back to back, so its rows of P come from that L2 after the
+  // first; with one right-hand side this is the identity
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int r = rest % nrhs, y = (rest / nrhs) * 8 + x8;
+  if (y >= g.nblocks) return;
   const long s = (long)y * g.bvol + threadIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int no = 2 * nv;
@@ -51,17 +57,24 @@ template <typename T, typename S>
 void launch_restrict_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<T>* in, cplx<T>* out, int nrhs,
                           hipStream_t st) {
   size_t sh = (size_t)(g.bvol / 64) * 2 * nv * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_restrict_fine<T, S>), dim3(g.nblocks, nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out);
+  const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_restrict_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 
 // ------------------------------------------------------------------ prolongation (K5)
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_prolong_fine(FineGeom g, const SP<S>* __restrict__ P, int nv,
-                                                      const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out) {
+                                                      const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                      int nrhs) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* e = reinterpret_cast<cplx<T>*>(smem_raw);
   const long V = g.V;
-  const int y = blockIdx.x, r = blockIdx.y;
+  // workgroup -> (aggregate, rhs): the right-hand sides of one aggregate run
+  // on one XCD back to back, so its rows of P come from that L2 after the
+  // first; with one right-hand side this is the identity
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int r = rest % nrhs, y = (rest / nrhs) * 8 + x8;
+  if (y >= g.nblocks) return;
   const int no = 2 * nv;
   for (int k = threadIdx.x; k < no; k += blockDim.x) e[k] = in[((long)r * g.nblocks + y) * no + k];
   __syncthreads();
@@ -86,7 +99,8 @@ template <typename T, typename S>
 void launch_prolong_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<T>* in, cplx<T>* out, int nrhs,
                          hipStream_t st) {
   size_t sh = (size_t)2 * nv * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_prolong_fine<T, S>), dim3(g.nblocks, nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out);
+  const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_prolong_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 
 // ------------------------------------------------------------------ block Gram-Schmidt (K7)
