@@ -11,6 +11,150 @@
 
 template <typename S> using SP = typename Store<S>::pair;
 
+constexpr int GPM_TS = 16;   // sites per LDS tile of the matrix-core products
+
+// ------------------------------------------------------------------ batched transfers on the matrix cores
+// With 8 or more right-hand sides (FP32 vectors, bf16 P, N_v <= 32) the
+// transfers are dense products over an aggregate, 16 right-hand sides per
+// workgroup:
+//   P^dag:  out[(s, i)][r] = sum_{x, k in s} conj(P_i(x)_k) in_r(x)_k,
+//           per chirality an (N_v x 1536) x (1536 x 16) product;
+//   P:      out_r(x)_k     = sum_i P_i(x)_k e_r[(s(k), i)],
+//           a (3072 x N_v) x (N_v x 16) product.
+// P is exact in bf16; the FP32 vectors are split into two bf16 parts (kept
+// to 2^-18 of their size); 16x16x16 bf16 MFMA tiles, FP32 accumulation.
+constexpr int TR_NR = 16;
+
+TM_D bool tr_unit(const FineGeom& g, int nrhs, int& y, int& r0) {
+  // workgroup -> (aggregate, group of 16 right-hand sides), the groups of
+  // one aggregate on one XCD back to back
+  const int ng = (nrhs + TR_NR - 1) / TR_NR;
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  r0 = (rest % ng) * TR_NR;
+  y = (rest / ng) * 8 + x8;
+  return y < g.nblocks;
+}
+
+__global__ void __launch_bounds__(256) k_restrict_mf(FineGeom g, const bf16pair* __restrict__ P, int nv,
+                                                     const cplx<float>* __restrict__ in, cplx<float>* __restrict__ out,
+                                                     int nrhs) {
+  int y, r0;
+  if (!tr_unit(g, nrhs, y, r0)) return;
+  const long V = g.V;
+  const int no = 2 * nv;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  const int sc = wv >> 1, mt = wv & 1;   // chirality and row (vector) tile of this wave
+  const int iv = 16 * mt + lr, r = r0 + lr;
+  const unsigned* Pu = reinterpret_cast<const unsigned*>(P);
+  // K steps: component k of chirality sc, 16 consecutive sites; lane group
+  // lk holds sites 4 lk .. 4 lk + 3, one 16-byte load of P and two of the
+  // input per step, straight from memory (no LDS, no barrier)
+  const unsigned* pbase = Pu + (long)(iv < nv ? iv : 0) * 12 * V;
+  const cplx<float>* ibase = in + (long)(r < nrhs ? r : r0) * 12 * V;
+  mf_f4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  const int nxt = g.bvol / 16;
+  for (int step = 0; step < 6 * nxt; ++step) {
+    const int kk = step / nxt, xb = step - kk * nxt, k = 6 * sc + kk;
+    const size_t o = tsite((unsigned)((long)y * g.bvol + 16 * xb + 4 * lk), 12) + k * FT;
+    uint4 pu = make_uint4(0u, 0u, 0u, 0u);
+    if (iv < nv) pu = *reinterpret_cast<const uint4*>(pbase + o);
+    float4 z01 = make_float4(0.f, 0.f, 0.f, 0.f), z23 = z01;
+    if (r < nrhs) {
+      z01 = reinterpret_cast<const float4*>(ibase + o)[0];
+      z23 = reinterpret_cast<const float4*>(ibase + o)[1];
+    }
+    const unsigned pw[4] = {pu.x, pu.y, pu.z, pu.w};
+    mf_s4 ar, ai;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ar[e] = (short)(pw[e] & 0xffffu);
+      ai[e] = (short)(pw[e] >> 16);
+    }
+    const cplx<float> zv[4] = {mk(z01.x, z01.y), mk(z01.z, z01.w), mk(z23.x, z23.y), mk(z23.z, z23.w)};
+    const MfSplit bb = mf_split(zv);
+    // Re(conj(P) z) = Re P Re z + Im P Im z, Im(conj(P) z) = Re P Im z - Im P Re z
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+  }
+  // C tile: lane l holds rows (vectors) 16 mt + 4 (l / 16) + v, column (rhs) l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int ivo = 16 * mt + 4 * lk + v, rr = r0 + lr;
+    if (ivo < nv && rr < nrhs) out[((long)rr * g.nblocks + y) * no + sc * nv + ivo] = mk(accr[v], acci[v]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_prolong_mf(FineGeom g, const bf16pair* __restrict__ P, int nv,
+                                                    const cplx<float>* __restrict__ in, cplx<float>* __restrict__ out,
+                                                    int nrhs) {
+  __shared__ cplx<float> ev[TR_NR * 64];          // [rhs][s nv + i], nv <= 32
+  __shared__ cplx<float> sb[4][TR_NR * 16];       // per wave: [rhs][site of the tile]
+  int y, r0;
+  if (!tr_unit(g, nrhs, y, r0)) return;
+  const long V = g.V;
+  const int no = 2 * nv;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  for (int e = t; e < TR_NR * no; e += 256) {
+    const int j = e / no, i = e - j * no;
+    ev[j * 64 + i] = r0 + j < nrhs ? in[((long)(r0 + j) * g.nblocks + y) * no + i] : mk<float>(0, 0);
+  }
+  __syncthreads();
+  const unsigned* Pu = reinterpret_cast<const unsigned*>(P);
+  const int nxt = g.bvol / 16;   // 16-site tiles of the aggregate
+  // row tiles (component k, 16 consecutive sites); wave wv takes every fourth
+  for (int tile = wv; tile < 12 * nxt; tile += 4) {
+    const int k = tile / nxt, xb = tile - k * nxt, sc = k / 6;
+    const size_t ts = tsite((unsigned)((long)y * g.bvol + 16 * xb + lr), 12) + k * FT;
+    mf_f4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+    for (int i0 = 0; i0 < nv; i0 += 16) {
+      mf_s4 ar, ai;
+      cplx<float> bv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 4 * lk + e;
+        const unsigned u = i < nv ? Pu[(long)i * 12 * V + ts] : 0u;
+        ar[e] = (short)(u & 0xffffu);
+        ai[e] = (short)(u >> 16);
+        bv[e] = i < nv ? ev[lr * 64 + sc * nv + i] : mk<float>(0, 0);
+      }
+      const MfSplit bb = mf_split(bv);
+      // Re(P e) = Re P Re e - Im P Im e, Im(P e) = Re P Im e + Im P Re e
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci, 0, 0, 0);
+    }
+    // C: lane l holds sites 4 (l / 16) + v of the tile for rhs l % 16; staged
+    // in LDS so that each lane stores four consecutive sites of one rhs
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sb[wv][lr * 16 + 4 * lk + v] = mk(accr[v], acci[v]);
+    __builtin_amdgcn_wave_barrier();
+    {
+      const int j = l >> 2, xq = 4 * (l & 3), r = r0 + j;
+      if (r < nrhs) {
+        cplx<float>* o = out + (long)r * 12 * V + tsite((unsigned)((long)y * g.bvol + 16 * xb + xq), 12) + k * FT;
+        const float4 a = make_float4(sb[wv][j * 16 + xq].re, sb[wv][j * 16 + xq].im, sb[wv][j * 16 + xq + 1].re,
+                                     sb[wv][j * 16 + xq + 1].im);
+        const float4 b = make_float4(sb[wv][j * 16 + xq + 2].re, sb[wv][j * 16 + xq + 2].im,
+                                     sb[wv][j * 16 + xq + 3].re, sb[wv][j * 16 + xq + 3].im);
+        reinterpret_cast<float4*>(o)[0] = a;
+        reinterpret_cast<float4*>(o)[1] = b;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // ------------------------------------------------------------------ restriction (K4)
 // One workgroup per aggregate (one thread per site):
 // out(y, s*nv + i) = sum_{x in y} sum_{k in s} conj(P_i[k](x)) in[k](x)
@@ -58,6 +202,13 @@ void launch_restrict_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<
                           hipStream_t st) {
   size_t sh = (size_t)(g.bvol / 64) * 2 * nv * sizeof(cplx<T>);
   const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
+  if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
+    if (nrhs >= 8 && nv <= 32 && g.bvol % 16 == 0) {
+      hipLaunchKernelGGL(k_restrict_mf, dim3(n8 * ((nrhs + TR_NR - 1) / TR_NR)), dim3(256), 0, st, g, P, nv, in, out,
+                         nrhs);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_restrict_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 
@@ -100,6 +251,13 @@ void launch_prolong_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<T
                          hipStream_t st) {
   size_t sh = (size_t)2 * nv * sizeof(cplx<T>);
   const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
+  if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
+    if (nrhs >= 8 && nv <= 32 && g.bvol % 16 == 0) {
+      hipLaunchKernelGGL(k_prolong_mf, dim3(n8 * ((nrhs + TR_NR - 1) / TR_NR)), dim3(256), 0, st, g, P, nv, in, out,
+                         nrhs);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_prolong_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 
@@ -762,7 +920,6 @@ __global__ void __launch_bounds__(256) k_galerkin_proj4(FineGeom g, const SP<S>*
 // owns chirality w / 2 and row tile w % 2 (vectors 16 (w % 2) ..), so the
 // waves need no reduction.  Tiles of 16 sites of P (raw bf16 pairs) and Z
 // in LDS, loaded as in k_galerkin_proj4.
-constexpr int GPM_TS = 16;
 
 __global__ void __launch_bounds__(256) k_galerkin_proj_mf(FineGeom g, const bf16pair* __restrict__ P, int nv,
                                                           GalerkinZ zl, const cplx<float>* __restrict__ Z,

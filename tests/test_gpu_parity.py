@@ -155,6 +155,22 @@ def test_prolongation_and_galerkin_mixed_bf16(c1, nv):
         errs.append(rel(D[:, 2 + 2 * m], Dc.B[m].reshape(-1, d, d)))
     say(f"  D_c blocks, worst rel. difference {max(errs):.2e}")
     assert max(errs) < 4e-3
+    # batched transfers (20 right-hand sides: the matrix-core kernels, one
+    # full group of 16 and a ragged one; 4: the vector-ALU kernels) against
+    # the oracle's FP64 P^dag and P with the library's rounded P.  Bar: the
+    # two-part bf16 split keeps each input to 4e-6.
+    for nrhs in (20, 4):
+        psi, psid = spinors(w.dims, 57 + nrhs, nrhs)
+        rc = torch.empty((nrhs, Vc, d), dtype=torch.complex128, device=DEV)
+        s.apply(tm.OP_RESTRICT, 0, psid, rc)
+        ref = torch.stack([Pr.restrict(field(psi[r])).reshape(Vc, d) for r in range(nrhs)])
+        err_r = rel(rc.cpu(), ref)
+        back = torch.empty_like(psid)
+        s.apply(tm.OP_PROLONG, 1, rc, back)
+        refp = torch.stack([Pr.prolong(rc.cpu()[r].reshape(*Pr.coarse_dims[::-1], d)) for r in range(nrhs)])
+        err_p = rel(field(back.cpu()), refp)
+        say(f"  {nrhs} RHS: P^dag {err_r:.2e}, P {err_p:.2e}")
+        assert err_r < 2e-5 and err_p < 2e-5
 
 
 def test_transfers_and_coarse_operator(c1, injected_c1):
