@@ -2,7 +2,10 @@
 // (Sec. 1.1), SAP on a coarse level, transfers between two coarse levels,
 // block Gram-Schmidt of coarse test vectors, and the Galerkin product
 // D_c' = P^dag D_c P for the next coarsening.
+#include <type_traits>
+
 #include "kernels.h"
+#include "mfma.h"
 
 template <typename S> using SP = typename Store<S>::pair;
 
@@ -445,11 +448,87 @@ __global__ void __launch_bounds__(256) k_restrict_coarse(CoarseGeom g, int d, CA
   }
 }
 
+// P^dag for 16 right-hand sides per workgroup on the matrix cores (FP32
+// vectors, bf16 P, N_v <= 32, d/2 a multiple of 4): per coarse aggregate
+// and chirality an (N_v x K) x (K x 16) product over K = sites x d/2,
+// P exact in bf16, the inputs split into two bf16 parts (kept to 2^-18 of
+// their size).  Wave w owns chirality w / 2 and vector tile w % 2; each lane
+// group takes four consecutive components of one site per K step (one
+// 16-byte load of P, two of the input).
+__global__ void __launch_bounds__(256) k_restrict_coarse_mf(CoarseGeom g, int d, CAgg a,
+                                                            const bf16pair* __restrict__ P, int nv,
+                                                            const cplx<float>* __restrict__ in,
+                                                            cplx<float>* __restrict__ out, long Vc, int nrhs) {
+  __shared__ long sites[256];
+  constexpr int NR = 16;
+  const int ng = (nrhs + NR - 1) / NR;
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int r0 = (rest % ng) * NR;
+  const long Y = (long)(rest / ng) * 8 + x8;
+  if (Y >= Vc) return;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  for (int sl = t; sl < a.na; sl += 256) {
+    int lc[4];
+    sites[sl] = cagg_site(g, a, Y, sl, lc);
+  }
+  __syncthreads();
+  const int hd = d / 2, no = 2 * nv;
+  const int sc = wv >> 1, mt = wv & 1, iv = 16 * mt + lr, r = r0 + lr;
+  const unsigned* pbase = reinterpret_cast<const unsigned*>(P) + (long)(iv < nv ? iv : 0) * g.V * d + sc * hd;
+  const cplx<float>* ibase = in + (long)(r < nrhs ? r : r0) * g.V * d + sc * hd;
+  const int K = a.na * hd;
+  mf_f4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int kk = k0 + 4 * lk;   // four consecutive components of one site (hd % 4 == 0)
+    uint4 pu = make_uint4(0u, 0u, 0u, 0u);
+    float4 z01 = make_float4(0.f, 0.f, 0.f, 0.f), z23 = z01;
+    if (kk < K) {
+      const int sl = kk / hd, k = kk - sl * hd;
+      const long o = sites[sl] * d + k;
+      if (iv < nv) pu = *reinterpret_cast<const uint4*>(pbase + o);
+      if (r < nrhs) {
+        z01 = reinterpret_cast<const float4*>(ibase + o)[0];
+        z23 = reinterpret_cast<const float4*>(ibase + o)[1];
+      }
+    }
+    const unsigned pw[4] = {pu.x, pu.y, pu.z, pu.w};
+    mf_s4 ar, ai;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ar[e] = (short)(pw[e] & 0xffffu);
+      ai[e] = (short)(pw[e] >> 16);
+    }
+    const cplx<float> zv[4] = {mk(z01.x, z01.y), mk(z01.z, z01.w), mk(z23.x, z23.y), mk(z23.z, z23.w)};
+    const MfSplit bb = mf_split(zv);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int ivo = 16 * mt + 4 * lk + v, rr = r0 + lr;
+    if (ivo < nv && rr < nrhs) out[((long)rr * Vc + Y) * no + sc * nv + ivo] = mk(accr[v], acci[v]);
+  }
+}
+
 template <typename T, typename S>
 void launch_restrict_coarse(const CoarseGeom& g, int d, const int agg[4], const SP<S>* P, int nv, const cplx<T>* in,
                             cplx<T>* out, int nrhs, hipStream_t st) {
   CAgg a = make_cagg(g, agg);
   long Vc = g.V / a.na;
+  if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
+    if (nrhs >= 8 && nv <= 32 && (d / 2) % 4 == 0 && a.na <= 256) {
+      const long n8 = (Vc + 7) / 8 * 8;
+      hipLaunchKernelGGL(k_restrict_coarse_mf, dim3((unsigned)(n8 * ((nrhs + 15) / 16))), dim3(256), 0, st, g, d, a, P,
+                         nv, in, out, Vc, nrhs);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_restrict_coarse<T, S>), dim3((unsigned)Vc, nrhs), dim3(256), 0, st, g, d, a, P, nv, in, out,
                      Vc);
 }

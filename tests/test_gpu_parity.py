@@ -471,3 +471,34 @@ def test_coarse_sap_batched_mixed(mixed_three_level_d48, nrhs):
         worst = max(worst, rel(out.cpu()[r], ref.reshape(Vc, d)))
     say(f"  worst rel. difference {worst:.2e}")
     assert worst < 1e-4
+
+
+@pytest.mark.parametrize("nrhs", [20, 4])
+def test_coarse_transfers_batched_mixed(mixed_three_level_d48, nrhs):
+    """Level 1 -> 2 restriction (20 RHS: the matrix-core kernel) and level
+    2 -> 1 prolongation against the oracle's FP64 transfers with the
+    library's own rounded level-1 P."""
+    s, cd1, cd2, sap1 = mixed_three_level_d48
+    Vc1, d1 = s.level_info(1)
+    Vc2, d2 = s.level_info(2)
+    nv1 = d2 // 2
+    say(f"batched level-1 transfers (d = {d1} -> {d2}), {nrhs} RHS, mixed bf16")
+    P1 = torch.empty((nv1, Vc1, d1), dtype=torch.complex128, device=DEV)
+    s.export(0, 1, P1)
+    lx, ly, lz, lt = cd1
+    V1 = P1.cpu().reshape(nv1, lt, lz, ly, lx, d1)
+    agg1 = tuple(a // b for a, b in zip(cd1, cd2))
+    Q = mg.to_blocks(V1, agg1, True).movedim(0, -1).contiguous()
+    Pr = mg.Prolongation(Q, agg1, cd1, d1)
+    v = mg.random_test_vectors(cd1, d1, nrhs, 7320)
+    vd = to_dev(v.reshape(nrhs, Vc1, d1).numpy())
+    rc = torch.empty((nrhs, Vc2, d2), dtype=torch.complex128, device=DEV)
+    s.apply(tm.OP_RESTRICT, 1, vd, rc)
+    ref = torch.stack([Pr.restrict(v[r]).reshape(Vc2, d2) for r in range(nrhs)])
+    err_r = rel(rc.cpu(), ref)
+    back = torch.empty_like(vd)
+    s.apply(tm.OP_PROLONG, 2, rc, back)
+    refp = torch.stack([Pr.prolong(rc.cpu()[r].reshape(*cd2[::-1], d2)).reshape(Vc1, d1) for r in range(nrhs)])
+    err_p = rel(back.cpu(), refp)
+    say(f"  P^dag {err_r:.2e}, P {err_p:.2e}")
+    assert err_r < 2e-5 and err_p < 2e-5
