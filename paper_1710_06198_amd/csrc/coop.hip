@@ -161,11 +161,14 @@ template <typename T, typename S, int D> constexpr bool mf_ok() {
   return std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value && D % 16 == 0;
 }
 
-// vst: [16][9D] staged inputs; on return (after a barrier) the partial
-// sums of wave w are at vst[q * 9D + (1 + w) D + i]
+// vst: [16][stride] staged inputs, block b's D values at slot[b] * D (slot
+// == nullptr: slot b); on return (after a barrier) the partial sums of wave
+// w are at vst[q * stride + (1 + w) D + i] (slots 1..4 must exist)
 template <int D>
-TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsigned mask) {
-  constexpr int MT = D / 16, KS = D / 16, K9 = 9 * D;
+TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsigned mask, int stride = 9 * D,
+                       const int* slot = nullptr) {
+  constexpr int MT = D / 16, KS = D / 16;
+  const int K9 = stride;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
   const unsigned* __restrict__ Du = reinterpret_cast<const unsigned*>(Dm);
   mf_f4 accr[MT], acci[MT];
@@ -204,7 +207,7 @@ TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsign
       const int j0 = 16 * ks + 4 * lk;
       cplx<float> v4[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v4[e] = vst[lr * K9 + b * D + j0 + e];
+      for (int e = 0; e < 4; ++e) v4[e] = vst[lr * K9 + (slot ? slot[b] : b) * D + j0 + e];
       const MfSplit bb = mf_split(v4);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -234,8 +237,8 @@ TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsign
   __syncthreads();
 }
 template <int D>
-TM_D cplx<float> site_mv_mfma_row(const cplx<float>* vst, int q, int i) {
-  const cplx<float>* p = vst + q * 9 * D + D + i;
+TM_D cplx<float> site_mv_mfma_row(const cplx<float>* vst, int q, int i, int stride = 9 * D) {
+  const cplx<float>* p = vst + q * stride + D + i;
   return (p[0] + p[D]) + (p[2 * D] + p[3 * D]);
 }
 
@@ -576,10 +579,13 @@ __global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* _
                                                     const double* __restrict__ part_in,
                                                     cplx<float>* __restrict__ rho_out, cplx<float>* __restrict__ q_out,
                                                     double* __restrict__ part_out, const double* __restrict__ mu_dev,
-                                                    int first) {
+                                                    int first, int nslot) {
+  // only the blocks inside the SAP block are staged: block b in slot
+  // slot9[b]; nslot (at least 5, for the partial sums) bounds the count
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<float>* vst = reinterpret_cast<cplx<float>*>(smem_raw);
   __shared__ cplx<float> alpha_s[MF_NR];
+  __shared__ int slot9[9], bslot[9];
   const CoarseGeom& g = a.g;
   const CBlk& cb = a.cb;
   const long VD = g.V * D;
@@ -596,10 +602,21 @@ __global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* _
   unsigned mask = 0u;
   for (int b = 0; b < 9; ++b)
     if (src9[b] >= 0) mask |= 1u << b;
-  for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
-    const int k = 2 * k2, q = k / (9 * D), kk = k - q * 9 * D, b = kk / D, j = kk - b * D, r = r0 + q;
+  if (t == 0) {
+    int ns = 0;
+    for (int b = 0; b < 9; ++b) {
+      slot9[b] = ((mask >> b) & 1u) ? ns : -1;
+      if ((mask >> b) & 1u) bslot[ns++] = b;
+    }
+    for (; ns < 9; ++ns) bslot[ns] = -1;
+  }
+  __syncthreads();
+  const int stride = nslot * D;
+  for (int k2 = t; k2 < MF_NR * stride / 2; k2 += 256) {   // two complex values per 16-byte access
+    const int k = 2 * k2, q = k / stride, kk = k - q * stride, sl2 = kk / D, j = kk - sl2 * D, r = r0 + q;
+    const int b = bslot[sl2];
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    const long src = src9[b];
+    const long src = b >= 0 ? src9[b] : -1;
     if (src >= 0 && r < a.nrhs) {
       v = *reinterpret_cast<const float4*>(rho_in + r * VD + src * D + j);
       if (!first) {
@@ -614,7 +631,7 @@ __global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* _
     *reinterpret_cast<float4*>(vst + k) = v;
   }
   __syncthreads();
-  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, mask);
+  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, mask, stride, slot9);
   // wave q: right-hand sides r0 + q, r0 + q + 4, ...; lanes over rows
   const int wq = t >> 6, lane = t & 63;
   for (int q = wq; q < MF_NR; q += 4) {
@@ -623,8 +640,8 @@ __global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* _
     float qq = 0, qre = 0, qim = 0;
     if (lane < D) {
       const float mu = (float)mu_dev[r];
-      const cplx<float> rho = vst[q * 9 * D + lane];
-      cplx<float> acc = site_mv_mfma_row<D>(vst, q, lane);
+      const cplx<float> rho = vst[q * stride + lane];
+      cplx<float> acc = site_mv_mfma_row<D>(vst, q, lane, stride);
       acc += (lane < D / 2 ? mu : -mu) * times_i(rho);
       const long o = r * VD + y * D + lane;
       q_out[o] = acc;
@@ -665,6 +682,12 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
   a.g = g;
   a.cb = cb;
   a.nrhs = nrhs;
+  // in-block neighbours a site can have: both along a direction whose block
+  // extent is at least 3 (or that wraps), one along an extent of 2
+  int nact = 1;
+  for (int m = 0; m < 4; ++m) nact += (cb.NB[m] == 1 || cb.B[m] >= 3) ? 2 : (cb.B[m] == 2 ? 1 : 0);
+  const int nslot = std::max(5, std::min(9, nact));
+  const size_t lds_mr = (size_t)MF_NR * nslot * D * sizeof(cplx<float>);
   const int ng = (nrhs + MF_NR - 1) / MF_NR;
   for (int sw = 0; sw < sweeps; ++sw)
     for (int col = 0; col < 2; ++col) {
@@ -674,8 +697,8 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
       hipLaunchKernelGGL((k_sap1_resid_mf<D>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
       for (int k = 0; k < mr; ++k) {
         const int in = (k + 1) & 1, out = k & 1;
-        hipLaunchKernelGGL((k_sap1_mr_mf<D>), dim3(units), dim3(256), lds, st, a, Dc, z, rho[in], q[in], part[in],
-                           rho[out], q[out], part[out], mu, k == 0 ? 1 : 0);
+        hipLaunchKernelGGL((k_sap1_mr_mf<D>), dim3(units), dim3(256), lds_mr, st, a, Dc, z, rho[in], q[in],
+                           part[in], rho[out], q[out], part[out], mu, k == 0 ? 1 : 0, nslot);
       }
       if (mr > 0) {
         const int in = (mr - 1) & 1;
