@@ -76,18 +76,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solver_params(tm, w, precision):
+def solver_params(tm, w, precision, graph=0):
     """The workload's hierarchy.  With three levels the intermediate FGMRES
     takes at most 6 steps and the coarsest GMRES at most 10: sweeps on the
     24^3 x 48 job (intermediate 3-15, coarsest 10-70 steps) moved the outer
     iteration count only between 14 and 26 while the coarse solves got
     several times cheaper (14 outer iterations at 10/50, 17 at 6/10).  Both
     precisions use the same hierarchy, so the FP64 comparison solver gets
-    the same saving."""
+    the same saving.  graph=1 replays the intermediate-level solve of each
+    fine cycle from a captured HIP graph (mixed precision only; the plain FP64
+    solver is the eager one)."""
     p = dict(nlevels=w.nlevels, agg=w.agg, nv=w.nv, setup_iters=w.setup_iters, init_smooth=w.init_smooth,
              sap_sweeps=w.sap_sweeps, mr_steps=w.mr_steps, restart=w.restart, precision=precision,
              storage=tm.STORE_BF16, coarsest_iters=10 if w.nlevels == 3 else 100,
-             l2_iters=6 if w.nlevels == 3 else 10)
+             l2_iters=6 if w.nlevels == 3 else 10, use_graph=graph if precision == tm.MIXED else 0)
     if w.nlevels == 3:
         p["sap_block1"] = w.sap_block[1]
     return tm.default_params(**p)
@@ -176,7 +178,7 @@ def bench_batched(args):
     for prec, name in ((tm.MIXED, "mixed"), (tm.FP64, "fp64")):
         if name == "fp64" and args.no_fp64:
             continue
-        p = solver_params(tm, w, prec)
+        p = solver_params(tm, w, prec, args.graph)
         p.restart = 12
         s = tm.Solver(w.dims, p)
         _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
@@ -227,7 +229,7 @@ def bench_force(args):
     for prec, name in ((tm.MIXED, "mixed"), (tm.FP64, "fp64")):
         if name == "fp64" and args.no_fp64:
             continue
-        s = tm.Solver(w.dims, solver_params(tm, w, prec))
+        s = tm.Solver(w.dims, solver_params(tm, w, prec, args.graph))
         _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
         phi = torch.empty_like(xi)
         s.apply(tm.OP_D64, 0, xi, phi, [w.mu])
@@ -262,6 +264,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--graph", type=int, choices=(0, 1), default=0,
+                    help="mixed precision: replay the intermediate-level solve from a HIP graph")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil and copy timing loops (for hardware-counter passes)")
     args = ap.parse_args()
@@ -292,7 +296,7 @@ def main():
         solver.setup(U, kappa, w.csw, w.mu)
         return solver.solve(b, x, tol=w.tol)
 
-    mixed = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED), stream=stream)
+    mixed = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED, args.graph), stream=stream)
     if args.kernels_only:
         mixed.setup(U, kappa, w.csw, w.mu)
         d_ms = mixed.time_kernel(tm.K_DSLASH32, 1, 10)
@@ -370,7 +374,7 @@ def main():
         "config": {"workload": f"{w.name}: {'x'.join(map(str, w.dims))} twisted-mass clover, "
                                f"{w.nlevels}-level DD-alpha-AMG, mixed precision, 1 RHS, setup+solve",
                    "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "m0": m0, "nv": list(w.nv),
-                   "tol": w.tol, "parallelism": "1 GPU"},
+                   "tol": w.tol, "hip_graph_level1_solve": bool(args.graph), "parallelism": "1 GPU"},
         "setup_s": setup_s,
         "solve_s": solve_s,
         "outer_iters": infos[-1]["outer_iters"],

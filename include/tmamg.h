@@ -80,6 +80,10 @@ typedef struct {
   int storage;          /* TMAMG_STORE_*: P and D_c storage in mixed precision */
   double inner_tol;     /* mixed: relative reduction per FP32 inner cycle */
   unsigned long long seed;  /* test-vector noise */
+  int use_graph;        /* 1: with three levels, the intermediate-level solve of
+                           every fine cycle is captured once per right-hand-side
+                           count as a HIP graph and replayed (same kernels, same
+                           order, identical results); 0: plain launches */
 } tmamg_params;
 
 typedef struct {

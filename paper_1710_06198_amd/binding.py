@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("storage", ctypes.c_int),
         ("inner_tol", ctypes.c_double),
         ("seed", ctypes.c_ulonglong),
+        ("use_graph", ctypes.c_int),
     ]
 
 

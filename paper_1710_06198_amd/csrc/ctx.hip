@@ -173,6 +173,7 @@ Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s) : lat(l),
   check(p.max_iter >= 1, "max_iter must be positive");
   check(p.mr_steps >= 0 && p.sap_sweeps[0] >= 0 && p.sap_sweeps[1] >= 0, "negative smoother counts");
   check(p.precision == TMAMG_FP64 || p.precision == TMAMG_MIXED, "precision");
+  check(p.use_graph == 0 || p.use_graph == 1, "use_graph must be 0 or 1");
   if (p.precision == TMAMG_MIXED)
     check(p.storage == TMAMG_STORE_FP32 || p.storage == TMAMG_STORE_BF16 || p.storage == TMAMG_STORE_FP16,
           "mixed precision stores P and D_c in fp32, bf16 or fp16");

@@ -154,8 +154,17 @@ struct Hier : HierBase {
   DevArr<int> cg_iws;
   int cap = 0;
   bool use_coop = true;
+  // captured intermediate-level solves (rc1 -> ec1), one per right-hand-side
+  // count and twisted-mass array; `calls` counts eager uses before capture
+  struct GraphEntry { int nrhs; const double* mu; int calls; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_st = nullptr;
+  bool capturing = false;
 
   explicit Hier(Ctx* c_);
+  ~Hier() override;
+  void drop_graphs();
+  bool coarse_solve_graph(int nrhs, const double* mu);
   void build_colours(const int nb[4], DevArr<int> out[2]);
   void ensure(int nrhs) override;
   std::string stats_line() override;

@@ -175,6 +175,62 @@ Hier<T, S>::Hier(Ctx* c_) : c(c_) {
 }
 
 template <typename T, typename S>
+Hier<T, S>::~Hier() {
+  drop_graphs();
+  if (cap_st) (void)hipStreamDestroy(cap_st);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::drop_graphs() {
+  for (GraphEntry& e : graphs)
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  graphs.clear();
+}
+
+// The intermediate-level solve of a fine cycle always reads rc1 and writes
+// ec1, and its launch schedule depends only on the hierarchy and the
+// right-hand-side count (fixed step counts, device-side convergence masks),
+// so it is captured as a HIP graph and replayed.  A key is captured on its
+// second use, so one-off calls never pay for the capture; the graphs hold
+// the hierarchy's buffer addresses and are dropped whenever those may move.
+// Returns false when the call must run eagerly.
+template <typename T, typename S>
+bool Hier<T, S>::coarse_solve_graph(int nrhs, const double* mu) {
+  size_t k = 0;
+  while (k < graphs.size() && !(graphs[k].nrhs == nrhs && graphs[k].mu == mu)) ++k;
+  if (k == graphs.size()) graphs.push_back({nrhs, mu, 0, nullptr});
+  if (!graphs[k].exec) {
+    if (++graphs[k].calls < 2) return false;
+    if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+    const hipStream_t saved = c->st;
+    hipGraph_t gr = nullptr;
+    c->st = cap_st;
+    capturing = true;
+    try {
+      HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
+      coarse_solve(1, rc1.p, ec1.p, nrhs, mu);
+      HIPCHK(hipStreamEndCapture(cap_st, &gr));
+    } catch (...) {
+      hipGraph_t partial = nullptr;
+      (void)hipStreamEndCapture(cap_st, &partial);
+      if (partial) (void)hipGraphDestroy(partial);
+      c->st = saved;
+      capturing = false;
+      throw;
+    }
+    c->st = saved;
+    capturing = false;
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIPCHK(e);
+    graphs[k].exec = ex;
+  }
+  HIPCHK(hipGraphLaunch(graphs[k].exec, c->st));
+  return true;
+}
+
+template <typename T, typename S>
 void Hier<T, S>::build_colours(const int nb[4], DevArr<int> out[2]) {
   std::vector<int> lists[2];
   for (int b3 = 0; b3 < nb[3]; ++b3)
@@ -198,6 +254,7 @@ void Hier<T, S>::ensure(int nrhs) {
   hipStream_t st = c->st;
   int need = std::max(nrhs, std::max(nv0, nv1));
   if (need <= cap) return;
+  drop_graphs();
   cap = need;
   red_partial.alloc(1024 * (size_t)cap);
   red_out.alloc(cap);
@@ -325,6 +382,9 @@ void Hier<T, S>::precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, cons
 template <typename T, typename S>
 void Hier<T, S>::coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu) {
   const tmamg_params& p = c->par;
+  if (level == 1 && nlev >= 3 && p.use_graph && !capturing && !c->timer.on && rhs == rc1.p && sol == ec1.p &&
+      coarse_solve_graph(nrhs, mu))
+    return;
   hipStream_t st = c->st;
   long n = level == 1 ? g1.V * d1 : g2.V * d2;
   launch_fill_zero(sol, (size_t)nrhs * n * sizeof(cplx<T>), st);
@@ -361,6 +421,7 @@ template <typename T, typename S>
 void Hier<T, S>::build(int l) {
   hipStream_t st = c->st;
   const tmamg_params& p = c->par;
+  drop_graphs();
   hipEvent_t e0 = c->timer.begin(st);
   build_inner(l);
   c->timer.end(PhaseTimer::SETUP_BUILD, e0, st);

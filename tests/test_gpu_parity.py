@@ -412,6 +412,48 @@ def test_coarsest_gmres_three_level():
     check_coarsest(s, 2, cdims, 1, [0.003], 24, 1e-3, 7200)
 
 
+# Graph mode: the intermediate-level solve of every fine cycle is captured
+# once per right-hand-side count and replayed.  The replayed kernels are the
+# eager ones in the same order with fixed-order reductions, so every solve
+# must match the eager solver bit for bit: three single-RHS solves in a row
+# (capture on the second use, replays after), a 3-RHS batch with signed
+# per-RHS mu (a second graph), then single RHS again, with eager test-hook
+# work and host synchronisation between the solves.
+def test_graph_captured_cycle_matches_eager():
+    dims = (8, 8, 16, 16)
+    say("graph-captured level-1 solve vs eager", dims)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1238)
+    op = WilsonClover(U, m0, 1.6)
+    base = dict(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(1, 1, 2, 2), setup_iters=1,
+                l2_iters=6, coarsest_iters=10, precision=tm.MIXED, storage=tm.STORE_BF16)
+    solvers = []
+    for g in (0, 1):
+        s = tm.Solver(dims, tm.default_params(use_graph=g, **base))
+        s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+        solvers.append(s)
+    cases = [(5101, 1, None), (5102, 1, None), (5103, 1, None), (5104, 3, [0.003, -0.003, 0.02]), (5105, 1, None)]
+    for seed, n, mus in cases:
+        b, bd = spinors(dims, seed, n)
+        xs, infos = [], []
+        for s in solvers:
+            x = torch.empty_like(bd)
+            info = s.solve(bd, x, mus, tol=1e-10)
+            assert info.status == 0
+            xs.append(x)
+            infos.append(info)
+            y = torch.empty_like(bd)
+            s.apply(tm.OP_D64, 0, x, y, mus)   # eager work between the solves
+            torch.cuda.synchronize()
+        say("seed", seed, "nrhs", n, "outer", infos[0].outer_iters, infos[1].outer_iters)
+        assert infos[0].outer_iters == infos[1].outer_iters
+        assert torch.equal(xs[0], xs[1])
+        mu_list = mus or [0.003] * n
+        for r in range(n):
+            res = norm(field(b[r]) - op.apply(field(xs[1].cpu()[r]), mu_list[r])) / norm(field(b[r]))
+            assert res <= 1e-10
+
+
 # The batched coarse operator and level-1 SAP on the matrix cores: 16
 # right-hand sides per workgroup, bf16 D_c, each FP32 vector entry split
 # into two bf16 parts (kept to 2^-18 of its size), FP32 accumulation.
