@@ -72,6 +72,33 @@ def batched_coarse(tm, solver, reps):
             "frac": round(tfs / MFMA_BF16_PEAK_TFS, 4), "sap1_sweep_16rhs_ms": round(sap_ms, 4)}
 
 
+def autotune(tm, solver, counts, args):
+    """Kernel variant tuning before the timed region: the library times
+    both variants of every tunable family at these right-hand-side counts on
+    the solver's own hierarchy and keeps the faster (process-wide table).
+    --tune-cache loads a table written earlier instead, or saves this one."""
+    import tempfile
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        n = tm.tune_load(args.tune_cache)
+        log(f"[bench] variant table: {n} entries from {args.tune_cache}")
+        path = args.tune_cache
+    else:
+        fd, path = tempfile.mkstemp(suffix=".json")
+        os.close(fd)
+        t0 = time.perf_counter()
+        solver.autotune(sorted(set(counts)), reps=3, json_path=path)
+        log(f"[bench] autotune {sorted(set(counts))} in {time.perf_counter() - t0:.1f} s")
+        if args.tune_cache:
+            tm.tune_save(args.tune_cache)
+    with open(path) as f:
+        entries = json.load(f)["entries"]
+    if not args.tune_cache:
+        os.remove(path)
+    for e in entries:
+        log(f"[bench]   {e['family']} {e['shape']} -> {e['variant']} {e['ms']}")
+    return entries
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -181,6 +208,9 @@ def bench_batched(args):
         p = solver_params(tm, w, prec, args.graph)
         p.restart = 12
         s = tm.Solver(w.dims, p)
+        if name == "mixed" and args.tune:
+            s.setup(U, kappa, w.csw, w.mu)
+            res["autotuned_variants"] = autotune(tm, s, [1, npt, nsh] + list(w.nv), args)
         _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
         xp = torch.empty_like(bp)
         ip, t_pt = _timed(lambda: s.solve(bp, xp, tol=w.tol))
@@ -194,6 +224,7 @@ def bench_batched(args):
         s.close()
         del xp, xs
         torch.cuda.empty_cache()
+    tuned = res.pop("autotuned_variants", None)
     m = res["mixed"]
     out = {"metric": "batched solve time (s) @1e-10 rel. resid: 12 point sources + 8 shifted systems",
            "value": m["total_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -203,7 +234,7 @@ def bench_batched(args):
                       "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "shifts": sig},
            "mixed": m, "fp64_amg": res.get("fp64"),
            "speedup_vs_fp64": (res["fp64"]["total_s"] / m["total_s"]) if "fp64" in res else None,
-           "per_rhs_s": m["total_s"] / (npt + nsh)}
+           "per_rhs_s": m["total_s"] / (npt + nsh), "autotuned_variants": tuned}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -230,6 +261,9 @@ def bench_force(args):
         if name == "fp64" and args.no_fp64:
             continue
         s = tm.Solver(w.dims, solver_params(tm, w, prec, args.graph))
+        if name == "mixed" and args.tune:
+            s.setup(U, kappa, w.csw, w.mu)
+            res["autotuned_variants"] = autotune(tm, s, [1] + list(w.nv), args)
         _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
         phi = torch.empty_like(xi)
         s.apply(tm.OP_D64, 0, xi, phi, [w.mu])
@@ -242,6 +276,7 @@ def bench_force(args):
                      "F_norm": float(torch.linalg.vector_norm(F))}
         log(f"[bench]   {name}: {res[name]}")
         s.close()
+    tuned = res.pop("autotuned_variants", None)
     m = res["mixed"]
     out = {"metric": "force time (s): S_f and dS_f/dU with solves to 1e-12",
            "value": m["setup_s"] + m["force_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
@@ -251,7 +286,7 @@ def bench_force(args):
                       "mu": w.mu, "csw": w.csw},
            "mixed": m, "fp64_amg": res.get("fp64"),
            "speedup_vs_fp64": ((res["fp64"]["setup_s"] + res["fp64"]["force_s"]) / (m["setup_s"] + m["force_s"]))
-           if "fp64" in res else None}
+           if "fp64" in res else None, "autotuned_variants": tuned}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -266,6 +301,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--graph", type=int, choices=(0, 1), default=0,
                     help="mixed precision: replay the intermediate-level solve from a HIP graph")
+    ap.add_argument("--tune", type=int, choices=(0, 1), default=1,
+                    help="autotune the kernel variants on the workload's hierarchy before timing")
+    ap.add_argument("--tune-cache", default=None, help="variant table JSON to load if present, else to write")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stencil and copy timing loops (for hardware-counter passes)")
     args = ap.parse_args()
@@ -306,6 +344,10 @@ def main():
               flush=True)
         mixed.close()
         return 0
+    tuned = None
+    if args.tune:
+        mixed.setup(U, kappa, w.csw, w.mu)
+        tuned = autotune(tm, mixed, [1] + list(w.nv), args)
     for i in range(args.warmup):
         log(f"[bench] warmup {i}")
         info = job(mixed)
@@ -387,6 +429,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_dslash<float> (fine stencil)", "bytes_per_site": bytes_site, "sites": V},
         "mfma_batched_coarse": mfma,
+        "autotuned_variants": tuned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

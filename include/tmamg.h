@@ -187,6 +187,47 @@ enum {
 };
 tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms);
 
+/* Kernel variant tuning (measurement and plumbing; the paper has nothing to
+ * say about it).  Some steps have two correct kernels for one shape; the
+ * launcher picks one by a built-in rule unless the process-wide variant
+ * table holds an entry for its family and shape key (a, b, nrhs):
+ *   TMAMG_TUNE_COARSE_APPLY  a = dof per coarse site, b = coarse sites;
+ *                            0 vector ALU, 1 matrix cores (16 RHS tiles)
+ *   TMAMG_TUNE_SAP1          level-1 SAP, same key and variants
+ *   TMAMG_TUNE_RESTRICT0,
+ *   TMAMG_TUNE_PROLONG0      a = N_v, b = fine sites; 0 vector ALU, 1 matrix cores
+ *   TMAMG_TUNE_SAP0          fine SAP, a = block sites, b = fine sites;
+ *                            register budget for 0 one / 1 three workgroups per CU
+ * A variant a launcher cannot run for its precision, storage or shape is
+ * ignored (the rule applies).  Every variant computes the same operation;
+ * results differ only by rounding (SAP0 variants not at all).  The table
+ * is shared by all contexts of the process and is not locked against
+ * concurrent tuning from several threads. */
+enum {
+  TMAMG_TUNE_COARSE_APPLY = 0,
+  TMAMG_TUNE_SAP1 = 1,
+  TMAMG_TUNE_RESTRICT0 = 2,
+  TMAMG_TUNE_PROLONG0 = 3,
+  TMAMG_TUNE_SAP0 = 4
+};
+/* Autotuner: for every right-hand-side count nrhs_list[0..n) (host, each
+ * 1..64) and every family with two variants for this context's hierarchy,
+ * times each variant over `reps` launches (HIP events, as
+ * tmamg_time_kernel) and stores the faster in the table.  json_path: if
+ * not NULL, the whole table is written there as JSON (entries with the
+ * measured milliseconds of each variant).  Needs a completed setup. */
+tmamg_status tmamg_autotune(tmamg_ctx* ctx, const int* nrhs_list, int n, int reps, const char* json_path);
+/* Add the entries of a file written by tmamg_autotune or tmamg_tune_save
+ * (same keys are replaced); *n_entries (may be NULL) = entries read.
+ * TMAMG_EINVAL if the file is unreadable or malformed (nothing is added). */
+tmamg_status tmamg_tune_load(const char* json_path, int* n_entries);
+tmamg_status tmamg_tune_save(const char* json_path);
+/* Set one entry (variant -1 removes it); read one (-1: none). */
+tmamg_status tmamg_tune_set(int family, long a, long b, long nrhs, int variant);
+int tmamg_tune_get(int family, long a, long b, long nrhs);
+int tmamg_tune_entries(void);
+void tmamg_tune_clear(void);
+
 /* Sizes of level `level`: sites and dof per site (fine: 12). */
 tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int* dof);
 

@@ -22,9 +22,11 @@ EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",
     "tmamg_solve_shifted", "tmamg_force", "tmamg_force_from_fields", "tmamg_apply",
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
-    "tmamg_time_kernel", "tmamg_last_error",
+    "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
+    "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY = range(9)
+TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
 
 
 class Lattice(ctypes.Structure):
@@ -98,8 +100,17 @@ def load(path: str = LIB_PATH):
     lib.tmamg_destroy.argtypes = [vp]
     lib.tmamg_destroy.restype = None
     lib.tmamg_last_error.restype = ctypes.c_char_p
+    cs, lg = ctypes.c_char_p, ctypes.c_long
+    lib.tmamg_autotune.argtypes = [vp, P(i), i, i, cs]
+    lib.tmamg_tune_load.argtypes = [cs, P(i)]
+    lib.tmamg_tune_save.argtypes = [cs]
+    lib.tmamg_tune_set.argtypes = [i, lg, lg, lg, i]
+    lib.tmamg_tune_get.argtypes = [i, lg, lg, lg]
+    lib.tmamg_tune_entries.argtypes = []
+    lib.tmamg_tune_clear.argtypes = []
+    lib.tmamg_tune_clear.restype = None
     for nm in EXPORTS:
-        if nm not in ("tmamg_destroy", "tmamg_last_error"):
+        if nm not in ("tmamg_destroy", "tmamg_last_error", "tmamg_tune_clear"):
             getattr(lib, nm).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -220,7 +231,41 @@ class Solver:
         _check(self.lib.tmamg_time_kernel(self.h, int(kernel), int(nrhs), int(reps), ctypes.byref(ms)))
         return ms.value
 
+    def autotune(self, nrhs_list, reps=5, json_path=None):
+        """Time both variants of every tunable kernel family at these
+        right-hand-side counts and keep the faster in the variant table."""
+        arr = (ctypes.c_int * len(nrhs_list))(*[int(n) for n in nrhs_list])
+        _check(self.lib.tmamg_autotune(self.h, arr, len(nrhs_list), int(reps),
+                                       None if json_path is None else os.fsencode(json_path)))
+
     def level_info(self, level):
         s, d = ctypes.c_long(), ctypes.c_int()
         _check(self.lib.tmamg_level_info(self.h, int(level), ctypes.byref(s), ctypes.byref(d)))
         return s.value, d.value
+
+
+# ---- process-wide kernel variant table (see tmamg_tune_* in include/tmamg.h)
+def tune_load(path) -> int:
+    n = ctypes.c_int()
+    _check(load().tmamg_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_save(path):
+    _check(load().tmamg_tune_save(os.fsencode(path)))
+
+
+def tune_set(family, a, b, nrhs, variant):
+    _check(load().tmamg_tune_set(int(family), int(a), int(b), int(nrhs), int(variant)))
+
+
+def tune_get(family, a, b, nrhs) -> int:
+    return load().tmamg_tune_get(int(family), int(a), int(b), int(nrhs))
+
+
+def tune_entries() -> int:
+    return load().tmamg_tune_entries()
+
+
+def tune_clear():
+    load().tmamg_tune_clear()

@@ -329,11 +329,14 @@ template <typename T, typename S, int D>
 static void coarse_apply_site(const CoarseGeom& g, const SP<S>* Dc, const cplx<T>* in, cplx<T>* out, int nrhs,
                               const double* mu_dev, hipStream_t st) {
   if constexpr (mf_ok<T, S, D>()) {
-    if (nrhs >= 8) {
+    const int tv = tune_get(TUNE_COARSE_APPLY, D, g.V, nrhs);
+    if (tv >= 0 ? tv == 1 : nrhs >= 8) {
       coarse_apply_mf<D>(g, Dc, in, out, nrhs, mu_dev, st);
+      tune_used(TUNE_COARSE_APPLY, 1);
       return;
     }
   }
+  tune_used(TUNE_COARSE_APPLY, 0);
   if (nrhs >= 4)
     hipLaunchKernelGGL((k_coarse_apply_site<T, S, D, 4>), dim3((unsigned)g.V, (nrhs + 3) / 4), dim3(256), 0, st, g,
                        Dc, in, out, nrhs, mu_dev);
@@ -740,11 +743,14 @@ static bool sap_mf(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const c
                    const double* mu, const int* const bl[2], const int nb[2], int sweeps, int mr,
                    cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
   if constexpr (mf_ok<T, S, D>()) {
-    if (nrhs >= 8) {
+    const int tv = tune_get(TUNE_SAP1, D, g.V, nrhs);
+    if (tv >= 0 ? tv == 1 : nrhs >= 8) {
       sap_fused_mf<D>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, rho, q, part, st);
+      tune_used(TUNE_SAP1, 1);
       return true;
     }
   }
+  tune_used(TUNE_SAP1, 0);
   return false;
 }
 
@@ -768,8 +774,10 @@ bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const
   // one right-hand side per workgroup, or four (FP64: two) sharing each D_c load
   // eight or more right-hand sides with a bf16 D_c: 16 per workgroup on the matrix cores
 #define SAP_CASE(DD)                                                                                   \
-  if (nrhs == 1) sap_fused<T, S, DD, 1>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st); \
-  else if (!sap_mf<T, S, DD>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st))            \
+  if (nrhs == 1 && !(mf_ok<T, S, DD>() && tune_get(TUNE_SAP1, DD, g.V, 1) == 1)) {                  \
+    sap_fused<T, S, DD, 1>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st);        \
+    tune_used(TUNE_SAP1, 0);                                                                         \
+  } else if (!sap_mf<T, S, DD>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st))            \
     sap_fused<T, S, DD, sizeof(T) == 4 ? 4 : 2>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q,     \
                                                   part, st);
   switch (d) {

@@ -109,7 +109,7 @@ double Hier<T, S>::time_kernel(int kernel, int nrhs, int reps) {
   DevArr<cplx<T>> a, b;
   DevArr<double> mu;
   mu.alloc(nrhs);
-  hipLaunchKernelGGL(k_fill_double, dim3(1), dim3(64), 0, st, mu.p, c->mu, nrhs);
+  hipLaunchKernelGGL(k_fill_double, dim3((nrhs + 63) / 64), dim3(64), 0, st, mu.p, c->mu, nrhs);
   switch (kernel) {
     case TMAMG_K_SAP0: {
       a.alloc((size_t)nrhs * n0);
@@ -643,22 +643,28 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
 double Ctx::time_kernel(int kernel, int nrhs, int reps) {
   check(nrhs >= 1 && reps >= 1, "nrhs and reps must be positive");
   if (!have_links) throw TmError{TMAMG_ESTATE, "timing before setup"};
-  ensure(nrhs);
-  upload_mu(nrhs, nullptr);
+  // the stencil timings use buffers of their own: the solve workspace
+  // (sized for nrhs with its Krylov bases) is not grown for a measurement
   const long n0 = 12 * fg.V;
-  if (kernel == TMAMG_K_DSLASH64) {
-    launch_random<double>(b64.p, (long)nrhs * n0, 21, st);
-    FineOp<double> o = op64();
-    return time_launches(st, reps, [&]() { launch_dslash<double>(o, b64.p, t64.p, nrhs, mu_dev.p, st); });
-  }
-  if (kernel == TMAMG_K_DSLASH32) {
+  if (kernel == TMAMG_K_DSLASH64 || kernel == TMAMG_K_DSLASH32) {
+    DevArr<double> mu_t;
+    mu_t.alloc(nrhs);
+    hipLaunchKernelGGL(k_fill_double, dim3((nrhs + 63) / 64), dim3(64), 0, st, mu_t.p, mu, nrhs);
+    if (kernel == TMAMG_K_DSLASH64) {
+      DevArr<cplx<double>> a, b;
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * n0);
+      launch_random<double>(a.p, (long)nrhs * n0, 21, st);
+      FineOp<double> o = op64();
+      return time_launches(st, reps, [&]() { launch_dslash<double>(o, a.p, b.p, nrhs, mu_t.p, st); });
+    }
     if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
     DevArr<cplx<float>> a, b;
     a.alloc((size_t)nrhs * n0);
     b.alloc((size_t)nrhs * n0);
     launch_random<float>(a.p, (long)nrhs * n0, 22, st);
     FineOp<float> o = op32();
-    return time_launches(st, reps, [&]() { launch_dslash<float>(o, a.p, b.p, nrhs, mu_dev.p, st); });
+    return time_launches(st, reps, [&]() { launch_dslash<float>(o, a.p, b.p, nrhs, mu_t.p, st); });
   }
   if (kernel == TMAMG_K_COPY) {
     const size_t bytes = (size_t)512 << 20;
@@ -670,6 +676,50 @@ double Ctx::time_kernel(int kernel, int nrhs, int reps) {
   }
   if (!have_setup) throw TmError{TMAMG_ESTATE, "timing before setup"};
   return hier->time_kernel(kernel, nrhs, reps);
+}
+
+// Autotuner: for each family with more than one kernel for the
+// hierarchy's shapes, force each variant in turn, time it with HIP events
+// on the hierarchy's own operators (the same launches as time_kernel), and
+// keep the fastest in the variant table with every variant's time.  A
+// variant the launcher did not run (not available for this precision,
+// storage or shape) is not a candidate; a shape with no candidate gets no
+// entry.
+template <typename T, typename S>
+void Hier<T, S>::autotune(int nrhs, int reps) {
+  struct Job { int fam, kernel; long a, b; };
+  std::vector<Job> jobs;
+  jobs.push_back({TUNE_SAP0, TMAMG_K_SAP0, c->fg.bvol, c->fg.V});
+  if (nlev >= 2) {
+    jobs.push_back({TUNE_RESTRICT0, TMAMG_K_RESTRICT0, nv0, c->fg.V});
+    jobs.push_back({TUNE_PROLONG0, TMAMG_K_PROLONG0, nv0, c->fg.V});
+    jobs.push_back({TUNE_COARSE_APPLY, TMAMG_K_DC1, d1, g1.V});
+  }
+  if (nlev >= 3) {
+    jobs.push_back({TUNE_COARSE_APPLY, TMAMG_K_DC2, d2, g2.V});
+    jobs.push_back({TUNE_SAP1, TMAMG_K_SAP1, d1, g1.V});
+  }
+  for (const Job& j : jobs) {
+    double ms[2] = {-1.0, -1.0};
+    int best = -1;
+    for (int v = 0; v < 2; ++v) {
+      tune_put(j.fam, j.a, j.b, nrhs, v, nullptr, 0);
+      tune_used(j.fam, -1);
+      const double t = time_kernel(j.kernel, nrhs, reps);
+      if (tune_last_used(j.fam) != v) continue;
+      ms[v] = t;
+      if (best < 0 || t < ms[best]) best = v;
+    }
+    tune_put(j.fam, j.a, j.b, nrhs, best, ms, 2);
+  }
+}
+
+void Ctx::autotune(const int* nrhs_list, int n, int reps) {
+  check(nrhs_list != nullptr && n >= 1 && reps >= 1, "autotune needs right-hand-side counts and reps >= 1");
+  for (int k = 0; k < n; ++k) check(nrhs_list[k] >= 1 && nrhs_list[k] <= 64, "right-hand-side counts must be 1..64");
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "autotune before setup"};
+  for (int k = 0; k < n; ++k) hier->autotune(nrhs_list[k], reps);
+  HIPCHK(hipStreamSynchronize(st));
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -843,6 +893,54 @@ tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, d
     return TMAMG_OK;
   });
 }
+
+tmamg_status tmamg_autotune(tmamg_ctx* ctx, const int* nrhs_list, int n, int reps, const char* json_path) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->autotune(nrhs_list, n, reps);
+    if (json_path) {
+      int dev = 0;
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipGetDeviceProperties(&prop, dev));
+      check(tune_save(json_path, prop.gcnArchName), "cannot write the tuning file");
+    }
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_tune_load(const char* json_path, int* n_entries) {
+  return guarded([&]() {
+    check(json_path != nullptr, "null path");
+    const int n = tune_load(json_path);
+    check(n >= 0, "unreadable or malformed tuning file");
+    if (n_entries) *n_entries = n;
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_tune_save(const char* json_path) {
+  return guarded([&]() {
+    check(json_path != nullptr, "null path");
+    check(tune_save(json_path, ""), "cannot write the tuning file");
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_tune_set(int family, long a, long b, long nrhs, int variant) {
+  return guarded([&]() {
+    check(family >= 0 && family < TUNE_NFAM, "unknown kernel family");
+    check(variant >= -1 && variant < 2, "variant must be -1, 0 or 1");
+    tune_put(family, a, b, nrhs, variant, nullptr, 0);
+    return TMAMG_OK;
+  });
+}
+
+int tmamg_tune_get(int family, long a, long b, long nrhs) { return tune_get(family, a, b, nrhs); }
+
+int tmamg_tune_entries(void) { return tune_entries(); }
+
+void tmamg_tune_clear(void) { tune_clear(); }
 
 void tmamg_destroy(tmamg_ctx* ctx) {
   try {

@@ -203,12 +203,15 @@ void launch_restrict_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<
   size_t sh = (size_t)(g.bvol / 64) * 2 * nv * sizeof(cplx<T>);
   const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
   if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
-    if (nrhs >= 8 && nv <= 32 && g.bvol % 16 == 0) {
+    const int tv = tune_get(TUNE_RESTRICT0, nv, g.V, nrhs);
+    if ((tv >= 0 ? tv == 1 : nrhs >= 8) && nv <= 32 && g.bvol % 16 == 0) {
       hipLaunchKernelGGL(k_restrict_mf, dim3(n8 * ((nrhs + TR_NR - 1) / TR_NR)), dim3(256), 0, st, g, P, nv, in, out,
                          nrhs);
+      tune_used(TUNE_RESTRICT0, 1);
       return;
     }
   }
+  tune_used(TUNE_RESTRICT0, 0);
   hipLaunchKernelGGL((k_restrict_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 
@@ -252,12 +255,15 @@ void launch_prolong_fine(const FineGeom& g, const SP<S>* P, int nv, const cplx<T
   size_t sh = (size_t)2 * nv * sizeof(cplx<T>);
   const unsigned n8 = (unsigned)((g.nblocks + 7) / 8 * 8);
   if constexpr (std::is_same<T, float>::value && std::is_same<S, __hip_bfloat16>::value) {
-    if (nrhs >= 8 && nv <= 32 && g.bvol % 16 == 0) {
+    const int tv = tune_get(TUNE_PROLONG0, nv, g.V, nrhs);
+    if ((tv >= 0 ? tv == 1 : nrhs >= 8) && nv <= 32 && g.bvol % 16 == 0) {
       hipLaunchKernelGGL(k_prolong_mf, dim3(n8 * ((nrhs + TR_NR - 1) / TR_NR)), dim3(256), 0, st, g, P, nv, in, out,
                          nrhs);
+      tune_used(TUNE_PROLONG0, 1);
       return;
     }
   }
+  tune_used(TUNE_PROLONG0, 0);
   hipLaunchKernelGGL((k_prolong_fine<T, S>), dim3(n8 * nrhs), dim3(g.bvol), sh, st, g, P, nv, in, out, nrhs);
 }
 

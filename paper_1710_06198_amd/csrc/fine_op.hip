@@ -503,12 +503,15 @@ void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nr
   size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
   const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
   if constexpr (sizeof(T) == 4) {
-    if (nrhs > 1) {
+    const int tv = tune_get(TUNE_SAP0, op.g.bvol, op.g.V, nrhs);
+    if (tv >= 0 ? tv == 1 : nrhs > 1) {
       hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
                          block_list, nblk, nrhs, mr_steps);
+      tune_used(TUNE_SAP0, 1);
       return;
     }
   }
+  tune_used(TUNE_SAP0, 0);
   hipLaunchKernelGGL((k_sap_fine<T, 1>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list,
                      nblk, nrhs, mr_steps);
 }

@@ -125,6 +125,7 @@ struct HierBase {
   virtual void export_P(int level, cplx<double>* out) = 0;
   virtual void export_Dc(int level, cplx<double>* out) = 0;
   virtual double time_kernel(int kernel, int nrhs, int reps) = 0;
+  virtual void autotune(int nrhs, int reps) = 0;
   // counters of the coarse solves since the last call, for the timing line
   virtual std::string stats_line() { return ""; }
   long stats_l2 = 0, stats_coarsest = 0;
@@ -188,6 +189,7 @@ struct Hier : HierBase {
   void export_P(int level, cplx<double>* out) override;
   void export_Dc(int level, cplx<double>* out) override;
   double time_kernel(int kernel, int nrhs, int reps) override;
+  void autotune(int nrhs, int reps) override;
 };
 
 struct Ctx {
@@ -233,6 +235,7 @@ struct Ctx {
   void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
   void upload_mu(int nrhs, const double* mu_host);
   double time_kernel(int kernel, int nrhs, int reps);
+  void autotune(const int* nrhs_list, int n, int reps);
 };
 
 // mean milliseconds per call of f over reps calls, HIP events on st

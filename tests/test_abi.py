@@ -60,7 +60,7 @@ int main(void) {
   F(tmamg_params, init_smooth) F(tmamg_params, sap_block1) F(tmamg_params, sap_sweeps) F(tmamg_params, mr_steps)
   F(tmamg_params, l2_iters) F(tmamg_params, l2_tol) F(tmamg_params, coarsest_iters) F(tmamg_params, coarsest_tol)
   F(tmamg_params, restart) F(tmamg_params, max_iter) F(tmamg_params, precision) F(tmamg_params, storage)
-  F(tmamg_params, inner_tol) F(tmamg_params, seed)
+  F(tmamg_params, inner_tol) F(tmamg_params, seed) F(tmamg_params, use_graph)
   F(tmamg_info, status) F(tmamg_info, outer_iters) F(tmamg_info, cycles) F(tmamg_info, true_rel_resid)
   F(tmamg_info, t_setup_s) F(tmamg_info, t_solve_s)
   printf("enum %d %d %d %d %d %d %d\n", TMAMG_OK, TMAMG_NOT_CONVERGED, TMAMG_EINVAL, TMAMG_ENOMEM, TMAMG_EHIP,
@@ -69,6 +69,8 @@ int main(void) {
          TMAMG_STORE_BF16, TMAMG_STORE_FP16);
   printf("ops %d %d %d %d %d %d %d %d\n", TMAMG_OP_D64, TMAMG_OP_D32, TMAMG_OP_PROLONG, TMAMG_OP_RESTRICT,
          TMAMG_OP_DC, TMAMG_OP_SAP, TMAMG_OP_PREC, TMAMG_OP_COARSEST);
+  printf("tune %d %d %d %d %d\n", TMAMG_TUNE_COARSE_APPLY, TMAMG_TUNE_SAP1, TMAMG_TUNE_RESTRICT0,
+         TMAMG_TUNE_PROLONG0, TMAMG_TUNE_SAP0);
   return 0;
 }
 """
@@ -96,6 +98,9 @@ def test_struct_layout_matches_c_compiler(tm, tmp_path):
         elif parts[0] == "ops":
             assert [int(v) for v in parts[1:]] == [b.OP_D64, b.OP_D32, b.OP_PROLONG, b.OP_RESTRICT, b.OP_DC,
                                                    b.OP_SAP, b.OP_PREC, b.OP_COARSEST]
+        elif parts[0] == "tune":
+            assert [int(v) for v in parts[1:]] == [b.TUNE_COARSE_APPLY, b.TUNE_SAP1, b.TUNE_RESTRICT0,
+                                                   b.TUNE_PROLONG0, b.TUNE_SAP0]
 
 
 def test_default_params(tm):
@@ -154,3 +159,51 @@ def test_missing_library_fails_loudly(tm):
             b.load(os.path.join(ROOT, "no_such_dir", "libtmamg.so"))
     finally:
         b._lib = saved
+
+
+def test_variant_table_round_trip(tm, tmp_path):
+    """The kernel variant table is host logic: set, read, remove, and its
+    JSON file written and read back; malformed files and bad arguments are
+    rejected without changing the table."""
+    tm.tune_clear()
+    try:
+        assert tm.tune_entries() == 0
+        assert tm.tune_get(tm.TUNE_COARSE_APPLY, 48, 2592, 16) == -1
+        tm.tune_set(tm.TUNE_COARSE_APPLY, 48, 2592, 16, 1)
+        tm.tune_set(tm.TUNE_SAP1, 48, 2592, 1, 0)
+        tm.tune_set(tm.TUNE_SAP0, 256, 663552, 24, 1)
+        tm.tune_set(tm.TUNE_RESTRICT0, 24, 663552, 24, 1)
+        tm.tune_set(tm.TUNE_PROLONG0, 24, 663552, 1, 0)
+        assert tm.tune_entries() == 5
+        assert tm.tune_get(tm.TUNE_COARSE_APPLY, 48, 2592, 16) == 1
+        assert tm.tune_get(tm.TUNE_COARSE_APPLY, 48, 2592, 15) == -1
+        assert tm.tune_get(tm.TUNE_SAP1, 48, 2592, 1) == 0
+        path = tmp_path / "tune.json"
+        tm.tune_save(str(path))
+        text = path.read_text()
+        assert '"tmamg-tune-1"' in text and text.count('"family"') == 5
+        tm.tune_clear()
+        assert tm.tune_entries() == 0
+        assert tm.tune_load(str(path)) == 5
+        assert tm.tune_get(tm.TUNE_SAP0, 256, 663552, 24) == 1
+        assert tm.tune_get(tm.TUNE_RESTRICT0, 24, 663552, 24) == 1
+        assert tm.tune_get(tm.TUNE_PROLONG0, 24, 663552, 1) == 0
+        tm.tune_set(tm.TUNE_SAP0, 256, 663552, 24, -1)   # removes the entry
+        assert tm.tune_get(tm.TUNE_SAP0, 256, 663552, 24) == -1 and tm.tune_entries() == 4
+        bad = tmp_path / "bad.json"
+        bad.write_text(text.replace('"sap1"', '"no_such_family"'))
+        with pytest.raises(tm.TmamgError, match="malformed"):
+            tm.tune_load(str(bad))
+        bad.write_text(text.replace("[48, 2592, 16]", "[48, 2592]"))
+        with pytest.raises(tm.TmamgError, match="malformed"):
+            tm.tune_load(str(bad))
+        with pytest.raises(tm.TmamgError, match="malformed"):
+            tm.tune_load(str(tmp_path / "missing.json"))
+        assert tm.tune_entries() == 4
+        with pytest.raises(tm.TmamgError, match="family"):
+            tm.tune_set(7, 1, 1, 1, 0)
+        with pytest.raises(tm.TmamgError, match="variant"):
+            tm.tune_set(tm.TUNE_SAP1, 1, 1, 1, 2)
+        assert tm.binding.load().tmamg_autotune(None, None, 0, 1, None) == -1
+    finally:
+        tm.tune_clear()

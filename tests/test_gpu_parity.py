@@ -156,20 +156,29 @@ def test_prolongation_and_galerkin_mixed_bf16(c1, nv):
     say(f"  D_c blocks, worst rel. difference {max(errs):.2e}")
     assert max(errs) < 4e-3
     # batched transfers (20 right-hand sides: the matrix-core kernels, one
-    # full group of 16 and a ragged one; 4: the vector-ALU kernels) against
-    # the oracle's FP64 P^dag and P with the library's rounded P.  Bar: the
-    # two-part bf16 split keeps each input to 4e-6.
-    for nrhs in (20, 4):
+    # full group of 16 and a ragged one; 4: the vector-ALU kernels; then
+    # each family forced to the other variant through the variant table:
+    # 20 on the vector ALU, 1 on the matrix cores) against the oracle's
+    # FP64 P^dag and P with the library's rounded P.  Bar: the two-part
+    # bf16 split keeps each input to 4e-6.
+    V = math.prod(w.dims)
+    for nrhs, forced in ((20, None), (4, None), (20, 0), (1, 1)):
         psi, psid = spinors(w.dims, 57 + nrhs, nrhs)
-        rc = torch.empty((nrhs, Vc, d), dtype=torch.complex128, device=DEV)
-        s.apply(tm.OP_RESTRICT, 0, psid, rc)
+        try:
+            if forced is not None:
+                tm.tune_set(tm.TUNE_RESTRICT0, nv, V, nrhs, forced)
+                tm.tune_set(tm.TUNE_PROLONG0, nv, V, nrhs, forced)
+            rc = torch.empty((nrhs, Vc, d), dtype=torch.complex128, device=DEV)
+            s.apply(tm.OP_RESTRICT, 0, psid, rc)
+            back = torch.empty_like(psid)
+            s.apply(tm.OP_PROLONG, 1, rc, back)
+        finally:
+            tm.tune_clear()
         ref = torch.stack([Pr.restrict(field(psi[r])).reshape(Vc, d) for r in range(nrhs)])
         err_r = rel(rc.cpu(), ref)
-        back = torch.empty_like(psid)
-        s.apply(tm.OP_PROLONG, 1, rc, back)
         refp = torch.stack([Pr.prolong(rc.cpu()[r].reshape(*Pr.coarse_dims[::-1], d)) for r in range(nrhs)])
         err_p = rel(field(back.cpu()), refp)
-        say(f"  {nrhs} RHS: P^dag {err_r:.2e}, P {err_p:.2e}")
+        say(f"  {nrhs} RHS (variant {forced}): P^dag {err_r:.2e}, P {err_p:.2e}")
         assert err_r < 2e-5 and err_p < 2e-5
 
 
@@ -478,17 +487,25 @@ def mixed_three_level_d48():
     return s, cd1, cd2, sap1
 
 
-@pytest.mark.parametrize("level,nrhs", [(1, 20), (2, 20), (1, 4), (2, 4)])
-def test_coarse_operator_batched_mixed(mixed_three_level_d48, level, nrhs):
+# variant None: the launcher's own rule; 0 / 1 forced through the variant
+# table (vector ALU with 20 right-hand sides, matrix cores with one).
+@pytest.mark.parametrize("level,nrhs,variant", [(1, 20, None), (2, 20, None), (1, 4, None), (2, 4, None),
+                                                (1, 20, 0), (2, 20, 0), (1, 1, 1), (2, 1, 1)])
+def test_coarse_operator_batched_mixed(mixed_three_level_d48, level, nrhs, variant):
     s, cd1, cd2, sap1 = mixed_three_level_d48
     cdims = cd1 if level == 1 else cd2
     Dc, Vc, d = coarse_op_from_export(s, level, cdims)
-    say(f"batched D_c, level {level} (d = {d}), {nrhs} RHS, mixed bf16")
+    say(f"batched D_c, level {level} (d = {d}), {nrhs} RHS, variant {variant}, mixed bf16")
     mus = [0.003 * (1 + r) * (-1) ** r for r in range(nrhs)]
     v = mg.random_test_vectors(cdims, d, nrhs, 7300 + level)
     vd = to_dev(v.reshape(nrhs, Vc, d).numpy())
     out = torch.empty_like(vd)
-    s.apply(tm.OP_DC, level, vd, out, mus)
+    try:
+        if variant is not None:
+            tm.tune_set(tm.TUNE_COARSE_APPLY, d, Vc, nrhs, variant)
+        s.apply(tm.OP_DC, level, vd, out, mus)
+    finally:
+        tm.tune_clear()
     worst = 0.0
     for r in range(nrhs):
         ref = Dc.apply(v[r], mus[r])
@@ -497,16 +514,21 @@ def test_coarse_operator_batched_mixed(mixed_three_level_d48, level, nrhs):
     assert worst < 2e-5
 
 
-@pytest.mark.parametrize("nrhs", [20, 4])
-def test_coarse_sap_batched_mixed(mixed_three_level_d48, nrhs):
+@pytest.mark.parametrize("nrhs,variant", [(20, None), (4, None), (20, 0), (1, 1)])
+def test_coarse_sap_batched_mixed(mixed_three_level_d48, nrhs, variant):
     s, cd1, cd2, sap1 = mixed_three_level_d48
     Dc, Vc, d = coarse_op_from_export(s, 1, cd1)
-    say(f"batched level-1 SAP (d = {d}), {nrhs} RHS, mixed bf16")
+    say(f"batched level-1 SAP (d = {d}), {nrhs} RHS, variant {variant}, mixed bf16")
     mus = [0.003 * (1 + r) * (-1) ** r for r in range(nrhs)]
     v = mg.random_test_vectors(cd1, d, nrhs, 7310)
     vd = to_dev(v.reshape(nrhs, Vc, d).numpy())
     out = torch.empty_like(vd)
-    s.apply(tm.OP_SAP, 1, vd, out, mus)
+    try:
+        if variant is not None:
+            tm.tune_set(tm.TUNE_SAP1, d, Vc, nrhs, variant)
+        s.apply(tm.OP_SAP, 1, vd, out, mus)
+    finally:
+        tm.tune_clear()
     worst = 0.0
     for r in range(nrhs):
         ref = mg.sap(Dc, v[r], torch.zeros_like(v[r]), mus[r], sap1, 2, 4)
@@ -544,3 +566,37 @@ def test_coarse_transfers_batched_mixed(mixed_three_level_d48, nrhs):
     err_p = rel(back.cpu(), refp)
     say(f"  P^dag {err_r:.2e}, P {err_p:.2e}")
     assert err_r < 2e-5 and err_p < 2e-5
+
+
+def test_autotune_table_and_tuned_solve(mixed_three_level_d48, tmp_path):
+    """The autotuner times both variants of every family for 1 and 20
+    right-hand sides on this hierarchy, keeps the faster and writes the
+    table as JSON; a solve with the tuned table still meets 1e-10 against
+    the oracle's operator."""
+    import json
+    s, cd1, cd2, sap1 = mixed_three_level_d48
+    path = tmp_path / "tune.json"
+    tm.tune_clear()
+    try:
+        s.autotune([1, 20], reps=2, json_path=str(path))
+        doc = json.loads(path.read_text())
+        say("tuned", json.dumps(doc["entries"]))
+        assert doc["format"] == "tmamg-tune-1"
+        fams = {e["family"] for e in doc["entries"]}
+        assert {"coarse_apply", "sap1", "restrict0", "prolong0", "sap0"} <= fams
+        names = ["coarse_apply", "sap1", "restrict0", "prolong0", "sap0"]
+        for e in doc["entries"]:
+            times = {v: t for v, t in e["ms"]}
+            assert e["variant"] in times and times[e["variant"]] == min(times.values())
+            assert tm.tune_get(names.index(e["family"]), *e["shape"]) == e["variant"]
+        dims = (8, 8, 16, 16)
+        m0 = load_m0()["c4"]
+        U, _ = links(dims, 0.3, 1237)
+        op = WilsonClover(U, m0, 1.6)
+        b, bd = spinors(dims, 5201, 1)
+        x = torch.empty_like(bd)
+        info = s.solve(bd, x, tol=1e-10)
+        assert info.status == 0
+        assert norm(field(b[0]) - op.apply(field(x.cpu()[0]), 0.003)) / norm(field(b[0])) <= 1e-10
+    finally:
+        tm.tune_clear()
