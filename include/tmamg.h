@@ -143,6 +143,16 @@ tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, do
  * without solves: F from the hopping and clover derivatives. */
 tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F);
 
+/* Link gradient of S_f for automatic differentiation (Sec. 1.2 force, as
+ * a gradient): G_mu(x) = 2 scale F_mu(x) U_mu(x), with F a force from
+ * tmamg_force at the context's current links U.  For every perturbation
+ * U -> exp(X) U with X traceless anti-Hermitian, the first-order change of
+ * scale * S_f is Re sum conj(G) (X U): G is the complex gradient
+ * dS/dRe U + i dS/dIm U (PyTorch's convention) on the directions tangent
+ * to SU(3); its component normal to SU(3) is not computed.  F, G: device
+ * [4][T][Z][Y][X][3][3] complex128 (may not alias); scale: host. */
+tmamg_status tmamg_force_link_gradient(tmamg_ctx* ctx, const void* F, void* G, double scale);
+
 /* Operator hook for tests.  op: one of TMAMG_OP_*; level: 0 fine, 1, 2.
  * in/out: device, canonical fields of that level, nrhs of them; mu_rhs host
  * [nrhs] or NULL (setup mu). */

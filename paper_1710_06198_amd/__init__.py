@@ -10,3 +10,4 @@ from .binding import (Solver, Params, Info, default_params, load, TmamgError,  #
                       K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY,
                       TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0,
                       tune_load, tune_save, tune_set, tune_get, tune_entries, tune_clear)
+from .autograd import FermionAction, fermion_action  # noqa: F401,E402

@@ -23,7 +23,7 @@ EXPORTS = [
     "tmamg_solve_shifted", "tmamg_force", "tmamg_force_from_fields", "tmamg_apply",
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
-    "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear",
+    "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY = range(9)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.tmamg_solve_shifted.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_force.argtypes = [vp, vp, vp, P(d), d, P(Info)]
     lib.tmamg_force_from_fields.argtypes = [vp, vp, vp, vp]
+    lib.tmamg_force_link_gradient.argtypes = [vp, vp, vp, d]
     lib.tmamg_apply.argtypes = [vp, i, i, vp, vp, i, P(d)]
     lib.tmamg_debug_set_test_vectors.argtypes = [vp, i, vp]
     lib.tmamg_debug_export.argtypes = [vp, i, i, vp]
@@ -187,11 +188,17 @@ class Solver:
         except Exception:
             pass
 
+    # links_version counts the link fields loaded (setup or setup_update),
+    # so a gradient can check that the links are still those of its action
+    links_version = 0
+
     def setup(self, U, kappa, csw, mu):
         _check(self.lib.tmamg_setup(self.h, _ptr(U), float(kappa), float(csw), float(mu)))
+        self.links_version += 1
 
     def setup_update(self, U, iters=1):
         _check(self.lib.tmamg_setup_update(self.h, _ptr(U), int(iters)))
+        self.links_version += 1
 
     def solve(self, b, x, mu_rhs=None, tol=1e-10):
         info = Info()
@@ -215,6 +222,9 @@ class Solver:
 
     def force_from_fields(self, X, Y, F):
         _check(self.lib.tmamg_force_from_fields(self.h, _ptr(X), _ptr(Y), _ptr(F)))
+
+    def force_link_gradient(self, F, G, scale=1.0):
+        _check(self.lib.tmamg_force_link_gradient(self.h, _ptr(F), _ptr(G), float(scale)))
 
     def apply(self, op, level, inp, out, mu_rhs=None):
         _check(self.lib.tmamg_apply(self.h, int(op), int(level), _ptr(inp), _ptr(out), inp.shape[0],

@@ -570,6 +570,15 @@ tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, dou
   return s;
 }
 
+void Ctx::force_link_gradient(const cplx<double>* F, cplx<double>* G, double scale) {
+  if (!have_links) throw TmError{TMAMG_ESTATE, "link gradient before setup"};
+  check(F && G, "null pointer");
+  check(std::isfinite(scale), "scale must be finite");
+  launch_link_gradient(op64(), lat.t_antiperiodic, F, G, scale, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+}
+
 void Ctx::force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F) {
   if (!have_links) throw TmError{TMAMG_ESTATE, "force before setup"};
   check(X && Y && F, "null pointer");
@@ -814,6 +823,14 @@ tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, do
   return guarded([&]() {
     check(ctx != nullptr, "null context");
     return C(ctx)->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info);
+  });
+}
+
+tmamg_status tmamg_force_link_gradient(tmamg_ctx* ctx, const void* F, void* G, double scale) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    C(ctx)->force_link_gradient(static_cast<const cplx<double>*>(F), static_cast<cplx<double>*>(G), scale);
+    return TMAMG_OK;
   });
 }
 

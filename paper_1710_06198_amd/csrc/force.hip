@@ -253,3 +253,39 @@ void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, c
                      clover ? Xi.p : nullptr, clover ? 1 : 0, F_canon);
   HIPCHK(hipStreamSynchronize(st));
 }
+
+// Link gradient for automatic differentiation: G_mu(x) = 2 scale F_mu(x) U_mu(x)
+// with the caller's links U (internal links carry the time-boundary sign,
+// undone here), canonical layout in and out.  For U -> exp(X) U with X in
+// su(3), Re sum conj(G) (X U) = -2 scale tr(F X) = scale dS/dt: G is the
+// complex gradient dS/dRe U + i dS/dIm U on the directions tangent to SU(3).
+__global__ void k_link_gradient(FineGeom g, const cplx<double>* __restrict__ links, int antiperiodic,
+                                const cplx<double>* __restrict__ F, cplx<double>* __restrict__ G, double scale) {
+  const long cs = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (cs >= g.V) return;
+  const int mu = blockIdx.y;
+  int c[4];
+  long r = cs;
+  c[0] = (int)(r % g.L[0]); r /= g.L[0];
+  c[1] = (int)(r % g.L[1]); r /= g.L[1];
+  c[2] = (int)(r % g.L[2]);
+  c[3] = (int)(r / g.L[2]);
+  const double sign = (antiperiodic && mu == 3 && c[3] == g.L[3] - 1) ? -1.0 : 1.0;
+  const M3<double> U = load_link(links, mu, fine_index(g, c), g.V);
+  const cplx<double>* f = F + ((long)mu * g.V + cs) * 9;
+  cplx<double>* o = G + ((long)mu * g.V + cs) * 9;
+  const double k = 2.0 * sign * scale;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cplx<double> acc = f[i * 3] * U.e[0][j];
+      cfma(acc, f[i * 3 + 1], U.e[1][j]);
+      cfma(acc, f[i * 3 + 2], U.e[2][j]);
+      o[i * 3 + j] = k * acc;
+    }
+}
+
+void launch_link_gradient(const FineOp<double>& op, int antiperiodic, const cplx<double>* F_canon,
+                          cplx<double>* G_canon, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_link_gradient, dim3((unsigned)((op.g.V + 127) / 128), 4), dim3(128), 0, st, op.g, op.links,
+                     antiperiodic, F_canon, G_canon, scale);
+}

@@ -232,6 +232,7 @@ struct Ctx {
                              tmamg_info* info);
   tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info);
   void force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F);
+  void force_link_gradient(const cplx<double>* F, cplx<double>* G, double scale);
   void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
   void upload_mu(int nrhs, const double* mu_host);
   double time_kernel(int kernel, int nrhs, int reps);
@@ -259,3 +260,5 @@ double time_launches(hipStream_t st, int reps, F&& f) {
 // force kernels (K13-K15)
 void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, const cplx<double>* Y,
                   cplx<double>* F_canon, hipStream_t st);
+void launch_link_gradient(const FineOp<double>& op, int antiperiodic, const cplx<double>* F_canon,
+                          cplx<double>* G_canon, double scale, hipStream_t st);

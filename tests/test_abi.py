@@ -207,3 +207,51 @@ def test_variant_table_round_trip(tm, tmp_path):
         assert tm.binding.load().tmamg_autotune(None, None, 0, 1, None) == -1
     finally:
         tm.tune_clear()
+
+
+def test_autograd_function_wiring(tm):
+    """FermionAction's host logic with a stand-in solver on the CPU: the first
+    call sets up, later calls update the setup, the gradient is the library's
+    link gradient scaled by the incoming gradient, and a gradient after the
+    links changed is refused."""
+    import torch
+
+    class Info:
+        status = 0
+
+        def as_dict(self):
+            return {}
+
+    class Standin:
+        links_version = 0
+
+        def __init__(self):
+            self.calls = []
+
+        def setup(self, U, kappa, csw, mu):
+            self.calls.append("setup")
+            self.links_version += 1
+
+        def setup_update(self, U, iters):
+            self.calls.append(("update", iters))
+            self.links_version += 1
+
+        def force(self, phi, F, tol):
+            F.fill_(0.25j)
+            return 3.5, Info()
+
+        def force_link_gradient(self, F, G, scale):
+            G.copy_(2 * scale * F)
+
+    s = Standin()
+    U = torch.zeros((4, 2, 2, 2, 2, 3, 3), dtype=torch.complex128, requires_grad=True)
+    phi = torch.zeros((1, 2, 2, 2, 2, 4, 3), dtype=torch.complex128)
+    S = tm.fermion_action(U, phi, s, 0.13, 1.0, 0.01)
+    assert float(S.detach()) == 3.5 and s.calls == ["setup"]
+    (3 * S).backward()
+    assert torch.allclose(U.grad, torch.full_like(U.grad, 1.5j))
+    S2 = tm.fermion_action(U, phi, s, 0.13, 1.0, 0.01, 1e-12, 2)
+    assert s.calls == ["setup", ("update", 2)]
+    s.setup(None, 0, 0, 0)   # links move before the gradient is taken
+    with pytest.raises(RuntimeError, match="links changed"):
+        S2.backward()
