@@ -325,7 +325,8 @@ def main():
     kappa = 1.0 / (2 * m0 + 8)
     dev = torch.device("cuda:0")
     log(f"[bench] workload {w.name} dims {w.dims}: generating inputs")
-    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    U_np = gauge_links(w.dims, w.eps, w.seeds["links"])
+    U = torch.as_tensor(U_np).to(dev)
     b = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"], n=1)).to(dev)
     x = torch.empty_like(b)
     stream = torch.cuda.Stream(device=dev)
@@ -380,6 +381,26 @@ def main():
     kern["dslash_fp32"] = round(st_ms, 4)
     mfma = batched_coarse(tm, mixed, 20)
 
+    # setup reuse along a trajectory: the links take one random-walk step
+    # (a stand-in for a molecular-dynamics update), the setup is updated with
+    # one iteration on the kept test vectors, then the solve
+    from lattice_inputs import md_step_links
+    U1 = torch.as_tensor(md_step_links(U_np, 0.05, w.seeds["links"] + 1)).to(dev)
+
+    def update_job(solver):
+        solver.setup(U, kappa, w.csw, w.mu)
+        torch.cuda.synchronize()
+        u0 = time.perf_counter()
+        solver.setup_update(U1, 1)
+        torch.cuda.synchronize()
+        u1 = time.perf_counter()
+        inf = solver.solve(b, x, tol=w.tol).as_dict()
+        return {"update_s": u1 - u0, "solve_s": inf["t_solve_s"], "total_s": u1 - u0 + inf["t_solve_s"],
+                "outer_iters": inf["outer_iters"], "true_rel_resid": inf["true_rel_resid"]}
+
+    upd = {"step": "U -> exp(0.05 i g.lambda/2) U, then 1 setup iteration", "mixed": update_job(mixed)}
+    log(f"[bench] setup update: {upd['mixed']}")
+
     fp64 = None
     if not args.no_fp64:
         log("[bench] plain FP64 DD-alpha-AMG")
@@ -392,6 +413,9 @@ def main():
         fp64 = {"total_s": f1 - f0, "setup_s": fi["t_setup_s"], "solve_s": fi["t_solve_s"],
                 "outer_iters": fi["outer_iters"], "true_rel_resid": fi["true_rel_resid"]}
         log(f"[bench]   {fp64}")
+        upd["fp64"] = update_job(plain)
+        upd["speedup_vs_fp64"] = upd["fp64"]["total_s"] / upd["mixed"]["total_s"]
+        log(f"[bench] setup update FP64: {upd['fp64']}")
         plain.close()
 
     cpu = None
@@ -430,6 +454,7 @@ def main():
                      "kernel": "k_dslash<float> (fine stencil)", "bytes_per_site": bytes_site, "sites": V},
         "mfma_batched_coarse": mfma,
         "autotuned_variants": tuned,
+        "setup_update_step": upd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

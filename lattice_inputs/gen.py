@@ -27,6 +27,7 @@ __all__ = [
     "su3_algebra_coeffs",
     "su3_from_coeffs",
     "random_gauge_transform",
+    "md_step_links",
     "unit_links",
 ]
 
@@ -139,6 +140,14 @@ def su3_algebra_coeffs(dims, seed: int) -> np.ndarray:
     lx, ly, lz, lt = dims
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal((4, lt, lz, ly, lx, 8))
+
+
+def md_step_links(U: np.ndarray, step: float, seed: int) -> np.ndarray:
+    """One step of a random walk on the links, a stand-in for a molecular
+    dynamics update: U'_mu(x) = exp(i step sum_a g_a lambda_a / 2) U_mu(x),
+    g_a ~ N(0,1) i.i.d. per link.  U: complex128 [4][T][Z][Y][X][3][3]."""
+    g = np.random.Generator(np.random.PCG64(seed)).standard_normal(U.shape[:-2] + (8,))
+    return _reunitarise(np.matmul(su3_from_coeffs(g, step), U))
 
 
 def random_gauge_transform(dims, seed: int, scale: float = 1.0) -> np.ndarray:

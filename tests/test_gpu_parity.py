@@ -600,3 +600,39 @@ def test_autotune_table_and_tuned_solve(mixed_three_level_d48, tmp_path):
         assert norm(field(b[0]) - op.apply(field(x.cpu()[0]), 0.003)) / norm(field(b[0])) <= 1e-10
     finally:
         tm.tune_clear()
+
+
+def test_setup_update_along_link_random_walk():
+    """Setup reuse along slowly changing links (the paper updates the setup
+    with one iteration per inversion along the trajectory): after a full
+    setup at U_0, three random-walk steps U_k = exp(0.05 i g.lambda/2) U_{k-1},
+    each followed by one setup iteration on the kept test vectors and a
+    solve.  Every solve meets 1e-10 in the oracle's operator at U_k, and the
+    updated hierarchy needs about as many outer iterations as a fresh full
+    setup at the same links."""
+    from lattice_inputs import md_step_links
+    dims = (8, 8, 16, 16)
+    say("setup update along a random walk", dims)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1239)
+    p = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(1, 1, 2, 2),
+                          setup_iters=2, l2_iters=6, coarsest_iters=10, precision=tm.MIXED,
+                          storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+    b, bd = spinors(dims, 5301, 1)
+    for k in range(1, 4):
+        U = md_step_links(U, 0.05, 5310 + k)
+        s.setup_update(to_dev(U), 1)
+        x = torch.empty_like(bd)
+        info = s.solve(bd, x, tol=1e-10)
+        op = WilsonClover(torch.as_tensor(U), m0, 1.6)
+        res = norm(field(b[0]) - op.apply(field(x.cpu()[0]), 0.003)) / norm(field(b[0]))
+        say(f"  step {k}: outer {info.outer_iters}, residual {res:.2e}")
+        assert info.status == 0 and res <= 1e-10
+    fresh = tm.Solver(dims, p)
+    fresh.setup(to_dev(U), kappa_of(m0), 1.6, 0.003)
+    x = torch.empty_like(bd)
+    info_f = fresh.solve(bd, x, tol=1e-10)
+    say(f"  fresh setup at the last links: outer {info_f.outer_iters}")
+    assert info.outer_iters <= 1.5 * info_f.outer_iters + 2

@@ -58,6 +58,23 @@ def test_links_are_su3():
     assert np.abs(np.linalg.det(U) - 1).max() < 1e-14
 
 
+def test_md_step_links_stay_su3_and_move_by_the_step():
+    """The random-walk stand-in for MD updates keeps the links in SU(3) and
+    moves each by about step * |g| (the generator norm), so halving the
+    step halves the mean distance."""
+    from lattice_inputs import md_step_links
+    U = gauge_links((4, 4, 4, 4), 0.3, 8)
+    for step in (0.05, 0.025):
+        V = md_step_links(U, step, 9)
+        vv = np.einsum("...ij,...kj->...ik", V, V.conj())
+        assert np.abs(vv - np.eye(3)).max() < 1e-14
+        assert np.abs(np.linalg.det(V) - 1).max() < 1e-14
+    d1 = np.linalg.norm(md_step_links(U, 0.05, 9) - U, axis=(-2, -1)).mean()
+    d2 = np.linalg.norm(md_step_links(U, 0.025, 9) - U, axis=(-2, -1)).mean()
+    assert abs(d1 / d2 - 2) < 0.01
+    assert 0.01 < d1 < 0.2
+
+
 # ----------------------------------------------------------------- free field
 def _symbol_np(p, m0, mu):
     """Momentum-space D at U = 1, derived independently: a plane wave
