@@ -75,3 +75,78 @@ def test_solve_full_size_bench_configuration(c2_full):
     say(f"  true relative residual (oracle operator, FP64) {res:.2e}")
     assert info.status == 0
     assert res <= 1e-10
+
+
+def random_su3_directions(shape, seed):
+    """Traceless anti-Hermitian 3x3 per link: a direction of U -> exp(tX) U."""
+    g = torch.Generator().manual_seed(seed)
+    A = torch.complex(torch.randn(shape + (3, 3), generator=g, dtype=torch.float64),
+                      torch.randn(shape + (3, 3), generator=g, dtype=torch.float64))
+    X = 0.5 * (A - A.transpose(-1, -2).conj())
+    tr = torch.diagonal(X, dim1=-2, dim2=-1).sum(-1) / 3
+    return X - tr[..., None, None] * torch.eye(3, dtype=X.dtype)
+
+
+def test_force_full_size_bench_configuration():
+    """The 16^3 x 32 differentiation workload at full size with the bench's
+    hierarchy: S_f(phi = D xi) = |xi|^2 exactly; the library's force against
+    the oracle's force formula on X = (D D^dag)^-1 phi (from the library's
+    shifted solve, its residual checked with the oracle's operator) and
+    Y = D^dag X (oracle), to the 1e-8 force target; and the force's
+    directional derivative -2 sum tr(F w) against central finite differences
+    (step 1e-5) of the library's S_f along 16 random su(3) directions.  FD
+    bar: S_f is computed to about 1e-14 relative (solves to 1e-12), i.e.
+    2e-8 absolute at |xi|^2 = 1.6e6, which the step turns into 1e-3 in the
+    difference quotient; the bar is 1e-6 relative plus 1e-2 absolute."""
+    import bench
+    from oracle import force as oforce
+    w = workload("c4")
+    m0 = load_m0()[w.name]
+    say("c4 full size: inputs", w.dims)
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"]))
+    Ud = to_dev(U)
+    xi = gaussian_spinor(w.dims, w.seeds["xi"], n=1)
+    xid = to_dev(xi)
+    p = bench.solver_params(tm, w, tm.MIXED)
+    s = tm.Solver(w.dims, p)
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    phid = torch.empty_like(xid)
+    s.apply(tm.OP_D64, 0, xid, phid, [w.mu])
+    F = torch.empty_like(Ud)
+    S, info = s.force(phid, F, tol=1e-12)
+    xi2 = float((torch.as_tensor(xi).abs() ** 2).sum())
+    say(f"  S {S:.15e} |xi|^2 {xi2:.15e} ({info.outer_iters} outer iterations)")
+    assert info.status == 0 and abs(S - xi2) / xi2 < 1e-10
+
+    op = WilsonClover(U, m0, w.csw)
+    xs = torch.empty_like(phid)
+    s.solve_shifted(phid, xs, [0.0], tol=1e-12)
+    X = field(xs.cpu()[0])
+    phi = field(phid.cpu()[0])
+    Y = op.apply_dag(X, w.mu)
+    res = norm(phi - op.apply(Y, w.mu)) / norm(phi)
+    F_ref = oforce.force_from_fields(U, m0, w.csw, X, Y)
+    err = rel(F.cpu(), F_ref)
+    say(f"  X residual (oracle operator) {res:.2e}; force vs oracle formula {err:.2e}")
+    assert res <= 1e-10 and err < 1e-8
+
+    s_fd = tm.Solver(w.dims, p)
+    s_fd.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    Fc = F.cpu()
+    h = 1e-5
+    worst = 0.0
+    for k in range(16):
+        om = random_su3_directions(tuple(U.shape[:-2]), 2000 + k)
+        d_f = oforce.directional_derivative(Fc, om)
+        Sx = []
+        for t in (h, -h):
+            s_fd.setup_update(to_dev(torch.matmul(torch.matrix_exp(t * om), U)), 1)
+            Ft = torch.empty_like(Ud)
+            St, it = s_fd.force(phid, Ft, tol=1e-12)
+            assert it.status == 0
+            Sx.append(St)
+        d_fd = (Sx[0] - Sx[1]) / (2 * h)
+        worst = max(worst, abs(d_f - d_fd) / abs(d_fd))
+        say(f"  direction {k}: force {d_f:.9e} finite difference {d_fd:.9e}")
+        assert abs(d_f - d_fd) <= 1e-6 * abs(d_fd) + 1e-2
+    say(f"  worst relative difference {worst:.2e}")
