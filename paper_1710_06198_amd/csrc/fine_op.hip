@@ -241,12 +241,55 @@ TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsig
 // U_mu(y)^dag (1 + g_mu) psi(y) as a half spinor with the link it already
 // loaded for its forward hop and leaves it in LDS for y + mu, so every
 // link of the block is read once.  Only hops across the block surface read
-// the neighbouring block's spinor (and, backwards, its link) from memory.
+// the neighbouring block's spinor (and, backwards, its link) from memory;
+// in FP32 those of the x and y faces are read at the start of the block,
+// next to the neighbouring blocks' own loads (all four directions would
+// need LDS for three more faces and cost a workgroup per CU).
 // Workgroups are mapped so that each XCD sweeps a contiguous range of
 // blocks, keeping neighbouring blocks' faces in the same L2.
+// Index of a site of the block on the face normal to MU: its local index
+// with the MU coordinate removed.
+template <int MU>
+TM_D int face_index(const FineGeom& g, int loc) {
+  const int ls = g.lstride[MU];
+  return loc % ls + (loc / (ls * g.B[MU])) * ls;
+}
+
+// Surface hops of direction MU loaded at the start of the block: a site on
+// the forward face keeps (1 - g_mu) psi(x + mu) projected, a site on the
+// backward face U_mu(x - mu)^dag (1 + g_mu) psi(x - mu), as half spinors in
+// LDS (ff, fb: [6][face sites]).  Neighbouring blocks on the same XCD start
+// within a few microseconds of each other and load these spinors at their
+// own start too, so the two reads of each line meet in L2.
+template <int MU, typename T>
+TM_D void load_faces(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, int loc, const int c[4],
+                     cplx<T>* ff, cplx<T>* fb) {
+  const FineGeom& g = op.g;
+  if (g.NB[MU] == 1) return;
+  const int B = g.B[MU], lc = c[MU] % B, fsz = g.bvol / B, fi = face_index<MU>(g, loc);
+  if (lc == B - 1) {
+    cplx<T> pn[12], h[6];
+    load_spinor(in, (unsigned)fine_neighbour(g, s, c, MU, +1), g.V, pn);
+    project<MU, -1>(pn, h);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ff[k * fsz + fi] = h[k];
+  } else if (lc == 0) {
+    cplx<T> pn[12], h[6], w[6];
+    const unsigned sb = (unsigned)fine_neighbour(g, s, c, MU, -1);
+    load_spinor(in, sb, g.V, pn);
+    const M3<T> ub = load_link_u<MU>(op.links, sb, g.V);
+    project<MU, +1>(pn, h);
+    su3_dmv(ub, h, w);
+    su3_dmv(ub, h + 3, w + 3);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) fb[k * fsz + fi] = w[k];
+  }
+}
+
 template <int MU, bool STREAM, typename T>
 TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* psl, cplx<T>* hb, unsigned s,
-                    int loc, const int c[4], const cplx<T>* psi, cplx<T>* acc) {
+                    int loc, const int c[4], const cplx<T>* psi, cplx<T>* acc, const cplx<T>* ff = nullptr,
+                    const cplx<T>* fb = nullptr) {
   const FineGeom& g = op.g;
   const long V = g.V;
   const int bv = g.bvol, ls = g.lstride[MU], B = g.B[MU];
@@ -268,19 +311,30 @@ TM_D void stage_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, const c
     if (nl >= 0) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) pn[k] = psl[k * bv + nl];
+      hop_fwd<MU>(u, pn, acc);
+    } else if (ff) {
+      const int fsz = bv / B, fi = face_index<MU>(g, loc);
+      cplx<T> h[6], w[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[k] = ff[k * fsz + fi];
+      su3_mv(u, h, w);
+      su3_mv(u, h + 3, w + 3);
+      reconstruct<MU, -1>(w, acc);
     } else {
       load_spinor(in, (unsigned)fine_neighbour(g, s, c, MU, +1), V, pn);
+      hop_fwd<MU>(u, pn, acc);
     }
-    hop_fwd<MU>(u, pn, acc);
   }
   compiler_fence(acc);
   __syncthreads();
   {
     const int nl = lc > 0 ? loc - ls : (whole ? loc + (B - 1) * ls : -1);
-    if (nl >= 0) {
+    if (nl >= 0 || fb) {
+      const cplx<T>* src = nl >= 0 ? hb + nl : fb + face_index<MU>(g, loc);
+      const int str = nl >= 0 ? bv : bv / B;
       cplx<T> w[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = hb[k * bv + nl];
+      for (int k = 0; k < 6; ++k) w[k] = src[k * str];
       reconstruct<MU, +1>(w, acc);
     } else {
       cplx<T> pn[12];
@@ -303,11 +357,24 @@ TM_D void dslash_block_rhs(const FineOp<T>& op, const cplx<T>* __restrict__ inr,
   load_spinor(inr, s, V, psi);
 #pragma unroll
   for (int k = 0; k < 12; ++k) psl[k * bv + loc] = psi[k];
+  // FP32: the x and y surface hops are loaded up front (LDS after hb)
+  constexpr bool EARLY = sizeof(T) == 4;
+  cplx<T>* ff0 = hb + 6 * bv;
+  cplx<T>* fb0 = ff0 + 6 * (bv / op.g.B[0]);
+  cplx<T>* ff1 = fb0 + 6 * (bv / op.g.B[0]);
+  cplx<T>* fb1 = ff1 + 6 * (bv / op.g.B[1]);
+  if constexpr (EARLY) {
+    load_faces<0>(op, inr, s, loc, c, ff0, fb0);
+    load_faces<1>(op, inr, s, loc, c, ff1, fb1);
+  }
   site_diag<T, STREAM>(op, s, mu, psi, acc);
   compiler_fence(acc);
   __syncthreads();
-  stage_dir<0, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
-  stage_dir<1, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  const bool w0 = op.g.NB[0] == 1, w1 = op.g.NB[1] == 1;
+  stage_dir<0, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc, EARLY && !w0 ? ff0 : nullptr,
+                       EARLY && !w0 ? fb0 : nullptr);
+  stage_dir<1, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc, EARLY && !w1 ? ff1 : nullptr,
+                       EARLY && !w1 ? fb1 : nullptr);
   stage_dir<2, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
   stage_dir<3, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
   cplx<T>* o = outr + tsite(s, 12);
@@ -350,7 +417,8 @@ template <typename T>
 void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu_dev,
                    hipStream_t st) {
   const int per = (op.g.nblocks + 7) / 8;
-  const size_t lds = 18 * (size_t)op.g.bvol * sizeof(cplx<T>);
+  size_t lds = 18 * (size_t)op.g.bvol * sizeof(cplx<T>);
+  if (sizeof(T) == 4) lds += 12 * (size_t)(op.g.bvol / op.g.B[0] + op.g.bvol / op.g.B[1]) * sizeof(cplx<T>);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_dslash<T, false>), dim3((unsigned)(8 * per)), dim3(op.g.bvol), lds, st, op, in, out, mu_dev,
                        nrhs);
