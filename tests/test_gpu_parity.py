@@ -636,3 +636,75 @@ def test_setup_update_along_link_random_walk():
     info_f = fresh.solve(bd, x, tol=1e-10)
     say(f"  fresh setup at the last links: outer {info_f.outer_iters}")
     assert info.outer_iters <= 1.5 * info_f.outer_iters + 2
+
+
+# ------------------------------------------------------------------ degenerate and failure cases
+def test_free_field_solve_matches_closed_form():
+    """Unit links (the clover term vanishes, D is diagonal in momentum space):
+    the multigrid solve at mu = 0 and at mu = 0.05 against the oracle's FFT
+    closed form, on 8^4 whose 4^4 aggregates give a 2^4 coarse lattice where
+    the +mu and -mu neighbours of a coarse site coincide.  Bar: residual
+    1e-10 times the condition number of the free operator at m0 = 0.1
+    (|lambda| from 0.1 to 8.1) gives 1e-8."""
+    from lattice_inputs import unit_links
+    from oracle.dirac import free_field_solve
+    dims = (8, 8, 8, 8)
+    m0 = 0.1
+    U = unit_links(dims)
+    p = tm.default_params(nlevels=2, nv=(12, 0), precision=tm.MIXED, storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    s.setup(to_dev(U), kappa_of(m0), 1.7, 0.05)
+    b, bd = spinors(dims, 5401, 2)
+    x = torch.empty_like(bd)
+    mus = [0.0, 0.05]
+    info = s.solve(bd, x, mus, tol=1e-10)
+    assert info.status == 0
+    for r in range(2):
+        ref = free_field_solve(field(b[r]), m0, mus[r])
+        err = rel(field(x.cpu()[r]), ref)
+        say(f"  free field, mu = {mus[r]}: {err:.2e}")
+        assert err < 1e-8
+
+
+def test_zero_and_mixed_right_hand_sides(c1):
+    """A zero right-hand side is solved by x = 0 at once; in a batch with a
+    nonzero one it stays exactly zero while the other converges."""
+    w, m0, U, Ud, op = c1
+    s = make_solver(w, precision=tm.MIXED, storage=tm.STORE_BF16)
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    b, bd = spinors(w.dims, 5402, 2)
+    bd[0].zero_()
+    x = torch.full_like(bd, 7.0)
+    info = s.solve(bd, x, tol=1e-10)
+    assert info.status == 0
+    assert torch.count_nonzero(x[0]) == 0
+    assert norm(field(b[1]) - op.apply(field(x.cpu()[1]), w.mu)) / norm(field(b[1])) <= 1e-10
+    z = torch.zeros_like(bd[:1])
+    x1 = torch.full_like(z, 3.0)
+    info = s.solve(z, x1, tol=1e-10)
+    assert info.status == 0 and info.outer_iters == 0 and torch.count_nonzero(x1) == 0
+
+
+def test_failure_paths_report_status(c1):
+    """Non-unitary links and NaN right-hand sides are refused with
+    TMAMG_ENUMERIC before any iteration; a solve before setup is a state
+    error; the context stays usable afterwards."""
+    w, m0, U, Ud, op = c1
+    s = make_solver(w, precision=tm.MIXED, storage=tm.STORE_BF16)
+    b, bd = spinors(w.dims, 5403, 1)
+    x = torch.empty_like(bd)
+    with pytest.raises(tm.TmamgError) as e:
+        s.solve(bd, x)
+    assert e.value.status == tm.binding.ESTATE
+    with pytest.raises(tm.TmamgError) as e:
+        s.setup(Ud * 1.01, kappa_of(m0), w.csw, w.mu)
+    assert e.value.status == tm.binding.ENUMERIC
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    bad = bd.clone()
+    bad[0, 1, 2, 3, 4, 0, 0] = float("nan")
+    with pytest.raises(tm.TmamgError) as e:
+        s.solve(bad, x)
+    assert e.value.status == tm.binding.ENUMERIC
+    info = s.solve(bd, x, tol=1e-10)
+    assert info.status == 0
+    assert norm(field(b[0]) - op.apply(field(x.cpu()[0]), w.mu)) / norm(field(b[0])) <= 1e-10
