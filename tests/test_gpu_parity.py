@@ -216,6 +216,30 @@ def test_sap_fixed_steps(c1, injected_c1):
         assert rel(field(out.cpu()[r]), ref) < 1e-11
 
 
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_sap_fixed_steps_fp32(c1, nrhs):
+    """The FP32 fine SAP (k sweeps of 4 MR steps per block) against the
+    oracle's FP64 SAP, one right-hand side (one workgroup per block) and a
+    batch of three with signed per-RHS mu (the batched kernel).  Bar: FP32
+    rounding through 16 block solves of a few hundred FP32 operations each
+    per site, about 1e-6; 1e-5."""
+    w, m0, U, Ud, op = c1
+    say("SAP parity c1, FP32,", nrhs, "RHS")
+    s = make_solver(w, precision=tm.MIXED, storage=tm.STORE_BF16, setup_iters=0, init_smooth=0)
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    mus = [w.mu, -0.1, 0.03][:nrhs]
+    psi, psid = spinors(w.dims, 68 + nrhs, nrhs)
+    out = torch.empty_like(psid)
+    s.apply(tm.OP_SAP, 0, psid, out, mus)
+    worst = 0.0
+    for r, mu in enumerate(mus):
+        eta = field(psi[r])
+        ref = mg.sap(op, eta, torch.zeros_like(eta), mu, w.sap_block[0], w.sap_sweeps[0], w.mr_steps)
+        worst = max(worst, rel(field(out.cpu()[r]), ref))
+    say(f"  worst rel. difference {worst:.2e}")
+    assert worst < 1e-5
+
+
 def test_multigrid_cycle(c1, injected_c1):
     w, m0, U, Ud, op = c1
     s, P, Dc = injected_c1
