@@ -203,7 +203,9 @@ tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, d
  * table holds an entry for its family and shape key (a, b, nrhs):
  *   TMAMG_TUNE_COARSE_APPLY  a = dof per coarse site, b = coarse sites;
  *                            0 vector ALU, 1 matrix cores (16 RHS tiles)
- *   TMAMG_TUNE_SAP1          level-1 SAP, same key and variants
+ *   TMAMG_TUNE_SAP1          level-1 SAP, same key; 0 vector ALU, 1 matrix
+ *                            cores, 2 matrix cores with a register budget for
+ *                            four workgroups per CU
  *   TMAMG_TUNE_RESTRICT0,
  *   TMAMG_TUNE_PROLONG0      a = N_v, b = fine sites; 0 vector ALU, 1 matrix cores
  *   TMAMG_TUNE_SAP0          fine SAP, a = block sites, b = fine sites;
@@ -232,7 +234,8 @@ tmamg_status tmamg_autotune(tmamg_ctx* ctx, const int* nrhs_list, int n, int rep
  * TMAMG_EINVAL if the file is unreadable or malformed (nothing is added). */
 tmamg_status tmamg_tune_load(const char* json_path, int* n_entries);
 tmamg_status tmamg_tune_save(const char* json_path);
-/* Set one entry (variant -1 removes it); read one (-1: none). */
+/* Set one entry (variant -1 removes it; TMAMG_EINVAL beyond the family's
+ * variants); read one (-1: none). */
 tmamg_status tmamg_tune_set(int family, long a, long b, long nrhs, int variant);
 int tmamg_tune_get(int family, long a, long b, long nrhs);
 int tmamg_tune_entries(void);

@@ -537,8 +537,10 @@ __global__ void __launch_bounds__(256) k_sap1_fin(SapArgs a, cplx<T>* __restrict
 // The residual and MR steps for 16 right-hand sides per workgroup on the
 // matrix cores (bf16 D_c, FP32 vectors); same data flow as k_sap1_resid
 // and k_sap1_mr, vst in dynamic LDS.
-template <int D>
-__global__ void __launch_bounds__(256) k_sap1_resid_mf(SapArgs a, const bf16pair* __restrict__ Dc,
+// MINB: workgroups per CU the register allocation aims for (4 helps on
+// large coarse lattices, where more resident sites hide the D_c loads).
+template <int D, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_sap1_resid_mf(SapArgs a, const bf16pair* __restrict__ Dc,
                                                        const cplx<float>* __restrict__ eta,
                                                        const cplx<float>* __restrict__ z,
                                                        cplx<float>* __restrict__ rho,
@@ -574,8 +576,8 @@ __global__ void __launch_bounds__(256) k_sap1_resid_mf(SapArgs a, const bf16pair
   }
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* __restrict__ Dc,
+template <int D, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_sap1_mr_mf(SapArgs a, const bf16pair* __restrict__ Dc,
                                                     cplx<float>* __restrict__ z,
                                                     const cplx<float>* __restrict__ rho_in,
                                                     const cplx<float>* __restrict__ q_in,
@@ -667,7 +669,7 @@ __global__ void __launch_bounds__(256) k_sap1_mr_mf(SapArgs a, const bf16pair* _
   }
 }
 
-template <int D>
+template <int D, int MINB>
 static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc, const cplx<float>* eta,
                          cplx<float>* z, int nrhs, const double* mu, const int* const bl[2], const int nb[2],
                          int sweeps, int mr, cplx<float>* const rho[2], cplx<float>* const q[2],
@@ -675,10 +677,10 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
   const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
   static bool attr = false;
   if (!attr && lds > 60 * 1024) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D, MINB>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D, MINB>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr = true;
   }
   SapArgs a;
@@ -697,10 +699,10 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
       const int units = nb[col] * cb.nbs * ng;
       if (units == 0) continue;
       a.bl = bl[col];
-      hipLaunchKernelGGL((k_sap1_resid_mf<D>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
+      hipLaunchKernelGGL((k_sap1_resid_mf<D, MINB>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
       for (int k = 0; k < mr; ++k) {
         const int in = (k + 1) & 1, out = k & 1;
-        hipLaunchKernelGGL((k_sap1_mr_mf<D>), dim3(units), dim3(256), lds_mr, st, a, Dc, z, rho[in], q[in],
+        hipLaunchKernelGGL((k_sap1_mr_mf<D, MINB>), dim3(units), dim3(256), lds_mr, st, a, Dc, z, rho[in], q[in],
                            part[in], rho[out], q[out], part[out], mu, k == 0 ? 1 : 0, nslot);
       }
       if (mr > 0) {
@@ -744,9 +746,13 @@ static bool sap_mf(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const c
                    cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
   if constexpr (mf_ok<T, S, D>()) {
     const int tv = tune_get(TUNE_SAP1, D, g.V, nrhs);
-    if (tv >= 0 ? tv == 1 : nrhs >= 8) {
-      sap_fused_mf<D>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, rho, q, part, st);
-      tune_used(TUNE_SAP1, 1);
+    if (tv >= 0 ? tv >= 1 : nrhs >= 8) {
+      // variant 2: register budget for four workgroups per CU (the rule
+      // takes it from 4096 coarse sites on)
+      const bool wide = tv >= 0 ? tv == 2 : g.V >= 4096;
+      if (wide) sap_fused_mf<D, 4>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, rho, q, part, st);
+      else sap_fused_mf<D, 1>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, rho, q, part, st);
+      tune_used(TUNE_SAP1, wide ? 2 : 1);
       return true;
     }
   }
@@ -774,7 +780,7 @@ bool launch_sap_coarse_fused(const CoarseGeom& g, int d, const int blk[4], const
   // one right-hand side per workgroup, or four (FP64: two) sharing each D_c load
   // eight or more right-hand sides with a bf16 D_c: 16 per workgroup on the matrix cores
 #define SAP_CASE(DD)                                                                                   \
-  if (nrhs == 1 && !(mf_ok<T, S, DD>() && tune_get(TUNE_SAP1, DD, g.V, 1) == 1)) {                  \
+  if (nrhs == 1 && !(mf_ok<T, S, DD>() && tune_get(TUNE_SAP1, DD, g.V, 1) >= 1)) {                  \
     sap_fused<T, S, DD, 1>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st);        \
     tune_used(TUNE_SAP1, 0);                                                                         \
   } else if (!sap_mf<T, S, DD>(g, cb, Dc, eta, z, nrhs, mu_dev, bl, nb, sweeps, mr_steps, rho, q, part, st))            \

@@ -709,9 +709,10 @@ void Hier<T, S>::autotune(int nrhs, int reps) {
     jobs.push_back({TUNE_SAP1, TMAMG_K_SAP1, d1, g1.V});
   }
   for (const Job& j : jobs) {
-    double ms[2] = {-1.0, -1.0};
+    double ms[3] = {-1.0, -1.0, -1.0};
+    const int nvar = tune_variants(j.fam);
     int best = -1;
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < nvar; ++v) {
       tune_put(j.fam, j.a, j.b, nrhs, v, nullptr, 0);
       tune_used(j.fam, -1);
       const double t = time_kernel(j.kernel, nrhs, reps);
@@ -719,7 +720,7 @@ void Hier<T, S>::autotune(int nrhs, int reps) {
       ms[v] = t;
       if (best < 0 || t < ms[best]) best = v;
     }
-    tune_put(j.fam, j.a, j.b, nrhs, best, ms, 2);
+    tune_put(j.fam, j.a, j.b, nrhs, best, ms, nvar);
   }
 }
 
@@ -947,7 +948,7 @@ tmamg_status tmamg_tune_save(const char* json_path) {
 tmamg_status tmamg_tune_set(int family, long a, long b, long nrhs, int variant) {
   return guarded([&]() {
     check(family >= 0 && family < TUNE_NFAM, "unknown kernel family");
-    check(variant >= -1 && variant < 2, "variant must be -1, 0 or 1");
+    check(variant >= -1 && variant < tune_variants(family), "variant out of range for this family");
     tune_put(family, a, b, nrhs, variant, nullptr, 0);
     return TMAMG_OK;
   });
