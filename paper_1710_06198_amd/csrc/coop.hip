@@ -677,7 +677,7 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
   const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
   static bool attr = false;
   if (!attr && lds > 60 * 1024) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D, MINB>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D, 1>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D, MINB>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -699,7 +699,8 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
       const int units = nb[col] * cb.nbs * ng;
       if (units == 0) continue;
       a.bl = bl[col];
-      hipLaunchKernelGGL((k_sap1_resid_mf<D, MINB>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
+      // the residual kernel's LDS allows two workgroups per CU anyway
+      hipLaunchKernelGGL((k_sap1_resid_mf<D, 1>), dim3(units), dim3(256), lds, st, a, Dc, eta, z, rho[1], mu);
       for (int k = 0; k < mr; ++k) {
         const int in = (k + 1) & 1, out = k & 1;
         hipLaunchKernelGGL((k_sap1_mr_mf<D, MINB>), dim3(units), dim3(256), lds_mr, st, a, Dc, z, rho[in], q[in],
