@@ -510,7 +510,12 @@ __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx
   const long V = g.V;
   const int bv = g.bvol;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  T* red = reinterpret_cast<T*>(lds + 12 * bv);
+  // batches (MINB 3): the block solution e lives in LDS next to the MR
+  // vector, each thread touching only its own site (no barrier), which
+  // frees the 24 registers that otherwise spill at three workgroups per CU
+  constexpr bool ELDS = MINB == 3;
+  cplx<T>* el = lds + 12 * bv;
+  T* red = reinterpret_cast<T*>(lds + (ELDS ? 24 : 12) * bv);
   // workgroup -> (block, rhs): the right-hand sides of one block run on one
   // XCD one after the other, so its links and clover come from that L2
   // after the first; with one right-hand side this is the identity
@@ -523,13 +528,17 @@ __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx
   const cplx<T>* zr = z + (long)r * 12 * V;
   int c[4];
   fine_coords(g, s, c);
-  cplx<T> rho[12], e[12], q[12];
+  cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
   {
     cplx<T> dz[12];
     site_dslash(op, zr, s, mu, dz);
     const cplx<T>* er = eta + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) { rho[k] = er[k * FT] - dz[k]; e[k] = mk<T>(0, 0); }
+    for (int k = 0; k < 12; ++k) {
+      rho[k] = er[k * FT] - dz[k];
+      if constexpr (ELDS) el[k * bv + loc] = mk<T>(0, 0);
+      else e[k] = mk<T>(0, 0);
+    }
   }
   for (int it = 0; it < mr_steps; ++it) {
 #pragma unroll
@@ -556,24 +565,31 @@ __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx
     cplx<T> alpha = qq > (T)0 ? mk(qr_re / qq, qr_im / qq) : mk<T>(0, 0);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      cfma(e[k], alpha, rho[k]);
+      if constexpr (ELDS) {
+        cplx<T> ek = el[k * bv + loc];
+        cfma(ek, alpha, rho[k]);
+        el[k * bv + loc] = ek;
+      } else {
+        cfma(e[k], alpha, rho[k]);
+      }
       rho[k] -= alpha * q[k];
     }
   }
   cplx<T>* zo = z + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) zo[k * FT] += e[k];
+  for (int k = 0; k < 12; ++k) zo[k * FT] += ELDS ? el[k * bv + loc] : e[k];
 }
 
 template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
                      const int* block_list, int nblk, int mr_steps, hipStream_t st) {
-  size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
+  const size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
   const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
   if constexpr (sizeof(T) == 4) {
     const int tv = tune_get(TUNE_SAP0, op.g.bvol, op.g.V, nrhs);
     if (tv >= 0 ? tv == 1 : nrhs > 1) {
-      hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
+      const size_t sh3 = sh + (size_t)12 * op.g.bvol * sizeof(cplx<T>);   // and e
+      hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh3, st, op, eta, z, mu_dev,
                          block_list, nblk, nrhs, mr_steps);
       tune_used(TUNE_SAP0, 1);
       return;
