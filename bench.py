@@ -313,8 +313,8 @@ def main():
     if args.graph is None:
         args.graph = 1 if args.workload == "c3" else 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(sharding across GPUs is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the solver runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is not implemented)"}))
         return 2
 
     import torch
