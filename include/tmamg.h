@@ -164,8 +164,15 @@ enum {
   TMAMG_OP_DC = 4,        /* coarse D_c(mu) on level 1 or 2 */
   TMAMG_OP_SAP = 5,       /* k SAP sweeps from zero on level 0 or 1: out ~ D^-1 in */
   TMAMG_OP_PREC = 6,      /* one multigrid cycle B_MG on level 0 or 1 */
-  TMAMG_OP_COARSEST = 7   /* coarsest-level GMRES from zero (coarsest_iters, coarsest_tol) on
+  TMAMG_OP_COARSEST = 7,  /* coarsest-level GMRES from zero (coarsest_iters, coarsest_tol) on
                              level nlevels-1: out ~ D_c^-1 in */
+  TMAMG_OP_SCHUR64 = 8,   /* even-odd reduced fine operator in FP64 (Sec. 1.2 even-odd
+                             preconditioning): out = (D_ee - D_eo D_oo^-1 D_oe) in on the
+                             sites with x+y+z+t even; odd entries of in are ignored, odd
+                             entries of out are 0.  Level 0.  Assumes the Hermitian part
+                             of the site-diagonal term is positive definite (m0 + 4 above
+                             the clover term's spectral radius) */
+  TMAMG_OP_SCHUR32 = 9    /* the same in FP32 (rounded in/out) */
 };
 tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
                          const double* mu_rhs);
@@ -193,7 +200,8 @@ enum {
   TMAMG_K_DC1 = 5,        /* coarse operator, level 1 */
   TMAMG_K_DC2 = 6,        /* coarse operator, level 2 */
   TMAMG_K_SAP1 = 7,       /* coarse SAP on level 1, one sweep (both colours) */
-  TMAMG_K_COPY = 8        /* plain device copy of 512 MiB (counter calibration) */
+  TMAMG_K_COPY = 8,       /* plain device copy of 512 MiB (counter calibration) */
+  TMAMG_K_SCHUR32 = 9     /* even-odd reduced fine operator, FP32 (both half passes) */
 };
 tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms);
 

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("TMAMG_LIB", os.path.join(HERE, "libtmamg.so"))
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16 = 0, 1, 2, 3
-OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST = range(8)
+OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST, OP_SCHUR64, OP_SCHUR32 = range(10)
 
 EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",
@@ -25,7 +25,7 @@ EXPORTS = [
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
     "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
 ]
-K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY = range(9)
+K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY, K_SCHUR32 = range(10)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
 
 

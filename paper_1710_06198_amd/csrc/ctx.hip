@@ -598,11 +598,23 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
   ensure(nrhs);
   upload_mu(nrhs, mu_host);
   const long n0 = 12 * fg.V;
-  if (op == TMAMG_OP_D64 || op == TMAMG_OP_D32) {
+  if (op == TMAMG_OP_D64 || op == TMAMG_OP_D32 || op == TMAMG_OP_SCHUR64 || op == TMAMG_OP_SCHUR32) {
     check(level == 0, "D acts on level 0");
     launch_spinor_to_internal<double>(fg, in, b64.p, nrhs, st);
     if (op == TMAMG_OP_D64) {
       launch_dslash<double>(op64(), b64.p, t64.p, nrhs, mu_dev.p, st);
+    } else if (op == TMAMG_OP_SCHUR64) {
+      launch_schur<double>(op64(), b64.p, r64.p, t64.p, nrhs, mu_dev.p, st);
+    } else if (op == TMAMG_OP_SCHUR32) {
+      if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
+      DevArr<cplx<float>> a, b, c;
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * n0);
+      c.alloc((size_t)nrhs * n0);
+      launch_convert<double, float>(b64.p, a.p, (long)nrhs * n0, st);
+      launch_schur<float>(op32(), a.p, c.p, b.p, nrhs, mu_dev.p, st);
+      launch_convert<float, double>(b.p, t64.p, (long)nrhs * n0, st);
+      HIPCHK(hipStreamSynchronize(st));
     } else {
       if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
       DevArr<cplx<float>> a, b;
@@ -674,6 +686,19 @@ double Ctx::time_kernel(int kernel, int nrhs, int reps) {
     launch_random<float>(a.p, (long)nrhs * n0, 22, st);
     FineOp<float> o = op32();
     return time_launches(st, reps, [&]() { launch_dslash<float>(o, a.p, b.p, nrhs, mu_t.p, st); });
+  }
+  if (kernel == TMAMG_K_SCHUR32) {
+    if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
+    DevArr<double> mu_t;
+    mu_t.alloc(nrhs);
+    hipLaunchKernelGGL(k_fill_double, dim3((nrhs + 63) / 64), dim3(64), 0, st, mu_t.p, mu, nrhs);
+    DevArr<cplx<float>> a, b, t;
+    a.alloc((size_t)nrhs * n0);
+    b.alloc((size_t)nrhs * n0);
+    t.alloc((size_t)nrhs * n0);
+    launch_random<float>(a.p, (long)nrhs * n0, 23, st);
+    FineOp<float> o = op32();
+    return time_launches(st, reps, [&]() { launch_schur<float>(o, a.p, t.p, b.p, nrhs, mu_t.p, st); });
   }
   if (kernel == TMAMG_K_COPY) {
     const size_t bytes = (size_t)512 << 20;

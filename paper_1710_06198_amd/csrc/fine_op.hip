@@ -603,3 +603,116 @@ template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*
                                       const int*, int, int, hipStream_t);
 template void launch_sap_fine<float>(const FineOp<float>&, const cplx<float>*, cplx<float>*, int, const double*,
                                      const int*, int, int, hipStream_t);
+
+// ------------------------------------------------------------------ even-odd reduction
+// D_hat(mu) = D_ee - D_eo D_oo^-1 D_oe on the even sites (x + y + z + t even):
+// the hopping term only joins opposite parities and A + i mu g5 is
+// site-diagonal.  Two gather passes over one parity each: on the odd sites
+// t = (A + i mu g5)^-1 sum_hops(psi), on the even sites
+// out = (A + i mu g5) psi - sum_hops(t); odd outputs are 0.
+
+// y = (A_ch + i s mu)^-1 v for one chirality block of a site (s = +1 for
+// the upper spins, -1 for the lower): Gaussian elimination without pivoting,
+// stable because the Hermitian part A_ch is positive definite whenever
+// m0 + 4 exceeds the spectral radius of the clover term (every workload here).
+template <typename T>
+TM_D void clover_block_solve(const T* __restrict__ cl, unsigned s, T smu, const cplx<T>* v, cplx<T>* y) {
+  cplx<T> a[6][6], b[6];
+  const T* p = cl + tsite(s, 36);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    a[i][i] = mk<T>(p[i * FT], smu);
+    b[i] = v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      const int k = 6 + 2 * herm_idx(i, j);
+      a[i][j] = mk<T>(p[k * FT], p[(k + 1) * FT]);
+      a[j][i] = conj(a[i][j]);
+    }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T d = (T)1 / norm2(a[k][k]);
+    const cplx<T> inv = d * conj(a[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < 6; ++i) {
+      const cplx<T> f = a[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < 6; ++j) a[i][j] -= f * a[k][j];
+      b[i] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    cplx<T> t = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) t -= a[i][j] * y[j];
+    const T d = (T)1 / norm2(a[i][i]);
+    y[i] = t * (d * conj(a[i][i]));
+  }
+}
+
+// PAR = 1: t = D_oo^-1 D_oe psi on the odd sites (and out = 0 there); PAR = 0:
+// out = D_ee psi - D_eo t on the even sites.  One thread per site of the
+// lattice, all right-hand sides along y; threads on the other parity only
+// exit.  (Packing one parity into consecutive threads halves the idle
+// lanes but makes every lane's loads stride-2 in the tiled layout, which
+// measured slower: 0.42 against 0.37 ms on 24^3 x 48.)
+template <typename T, int PAR>
+__global__ void __launch_bounds__(256) k_schur_half(FineOp<T> op, const cplx<T>* __restrict__ psi,
+                                                    cplx<T>* __restrict__ t, cplx<T>* __restrict__ out,
+                                                    const double* __restrict__ mu_dev) {
+  const long V = op.g.V;
+  const unsigned s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= V) return;
+  int c[4];
+  fine_coords(op.g, s, c);
+  if (((c[0] + c[1] + c[2] + c[3]) & 1) != PAR) return;
+  const int r = blockIdx.y;
+  const T mu = (T)mu_dev[r];
+  const cplx<T>* pr = psi + (long)r * 12 * V;
+  cplx<T>* o = out + (long)r * 12 * V + tsite(s, 12);
+  const cplx<T>* src = PAR == 1 ? pr : t + (long)r * 12 * V;   // t: odd sites only
+  cplx<T> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
+  site_hops_dir<0>(op, src, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<1>(op, src, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<2>(op, src, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<3>(op, src, s, c, acc);
+  compiler_fence(acc);
+  if constexpr (PAR == 1) {
+    cplx<T> y[12];
+    clover_block_solve(op.clover, s, mu, acc, y);
+    clover_block_solve(op.clover + 36 * V, s, -mu, acc + 6, y + 6);
+    cplx<T>* tt = t + (long)r * 12 * V + tsite(s, 12);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      tt[k * FT] = y[k];
+      o[k * FT] = mk<T>(0, 0);
+    }
+  } else {
+    cplx<T> p[12], d[12];
+    load_spinor(pr, s, V, p);
+    site_diag(op, s, mu, p, d);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k * FT] = d[k] - acc[k];
+  }
+}
+
+template <typename T>
+void launch_schur(const FineOp<T>& op, const cplx<T>* in, cplx<T>* tmp, cplx<T>* out, int nrhs, const double* mu_dev,
+                  hipStream_t st) {
+  const dim3 grid((unsigned)((op.g.V + 255) / 256), (unsigned)nrhs);
+  hipLaunchKernelGGL((k_schur_half<T, 1>), grid, dim3(256), 0, st, op, in, tmp, out, mu_dev);
+  hipLaunchKernelGGL((k_schur_half<T, 0>), grid, dim3(256), 0, st, op, in, tmp, out, mu_dev);
+}
+template void launch_schur<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, cplx<double>*, int,
+                                   const double*, hipStream_t);
+template void launch_schur<float>(const FineOp<float>&, const cplx<float>*, cplx<float>*, cplx<float>*, int,
+                                  const double*, hipStream_t);

@@ -39,6 +39,11 @@ void launch_clover_build(const FineGeom& g, const cplx<double>* links64, const C
 template <typename T>
 void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrhs,
                    const double* mu_dev, hipStream_t st);
+// ---- even-odd reduction: out_r = D_hat(mu_r) in_r on the even sites (odd
+// outputs 0; odd inputs ignored), tmp: scratch field of the same size
+template <typename T>
+void launch_schur(const FineOp<T>& op, const cplx<T>* in, cplx<T>* tmp, cplx<T>* out, int nrhs, const double* mu_dev,
+                  hipStream_t st);
 // out_r = Gamma5 in_r (any level: d dof per site, sites*d elements, SoA fine or AoS coarse)
 template <typename T>
 void launch_gamma5_fine(const FineGeom& g, const cplx<T>* in, cplx<T>* out, int nrhs, hipStream_t st);
