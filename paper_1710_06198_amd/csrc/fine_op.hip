@@ -383,8 +383,11 @@ TM_D void dslash_block_rhs(const FineOp<T>& op, const cplx<T>* __restrict__ inr,
 }
 
 // A single right-hand side streams links and clover (non-temporal loads).
-// A batch runs all its right-hand sides in one workgroup, one after the
-// other, so the block's links and clover come from L2 after the first.
+// A batch gives each (block, right-hand side) pair its own workgroup, the
+// right-hand sides of one block back to back on one XCD, so the block's
+// links and clover come from that L2 after the first (a loop over the
+// right-hand sides inside one workgroup kept the links in registers,
+// 211 VGPRs, half the occupancy).
 template <typename T, bool BATCH>
 __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out, const double* __restrict__ mu_dev,
@@ -395,22 +398,18 @@ __global__ void __launch_bounds__(256) k_dslash(FineOp<T> op, const cplx<T>* __r
   const int bv = g.bvol;
   cplx<T>* psl = reinterpret_cast<cplx<T>*>(smem_raw);   // [12][bv]
   cplx<T>* hb = psl + 12 * bv;                          // [6][bv]
-  // XCD x (= blockIdx.x % 8) takes blocks [x * per, (x + 1) * per)
+  // XCD x (= blockIdx.x % 8) takes blocks [x * per, (x + 1) * per), and in a
+  // batch each of them nrhs times in a row
   const int per = (g.nblocks + 7) / 8;
-  const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int rest = (int)(blockIdx.x >> 3);
+  const int r = BATCH ? rest % nrhs : 0;
+  const int blk = (int)(blockIdx.x & 7) * per + (BATCH ? rest / nrhs : rest);
   if (blk >= g.nblocks) return;
   const int loc = threadIdx.x;
   const unsigned s = (unsigned)blk * bv + loc;
   int c[4];
   fine_coords(g, s, c);
-  if constexpr (!BATCH) {
-    dslash_block_rhs<T, true>(op, in, out, (T)mu_dev[0], psl, hb, s, loc, c);
-  } else {
-#pragma unroll 1
-    for (int r = 0; r < nrhs; ++r)
-      dslash_block_rhs<T, false>(op, in + (long)r * 12 * V, out + (long)r * 12 * V, (T)mu_dev[r], psl, hb, s, loc,
-                                 c);
-  }
+  dslash_block_rhs<T, !BATCH>(op, in + (long)r * 12 * V, out + (long)r * 12 * V, (T)mu_dev[r], psl, hb, s, loc, c);
 }
 
 template <typename T>
@@ -423,8 +422,8 @@ void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrh
     hipLaunchKernelGGL((k_dslash<T, false>), dim3((unsigned)(8 * per)), dim3(op.g.bvol), lds, st, op, in, out, mu_dev,
                        nrhs);
   else
-    hipLaunchKernelGGL((k_dslash<T, true>), dim3((unsigned)(8 * per)), dim3(op.g.bvol), lds, st, op, in, out, mu_dev,
-                       nrhs);
+    hipLaunchKernelGGL((k_dslash<T, true>), dim3((unsigned)(8 * per * nrhs)), dim3(op.g.bvol), lds, st, op, in, out,
+                       mu_dev, nrhs);
 }
 template void launch_dslash<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                     hipStream_t);
