@@ -63,10 +63,12 @@ void launch_multidot(const cplx<T>* V, long vstride, int nvec, const cplx<T>* w,
 }
 
 // out[(o / nvec)*ostride + o % nvec] = sum_b partial[o*NB + b] (complex), one wave per output
-__global__ void k_finalize(const double* __restrict__ partial, int nout, int nvec, int NB, double* out, int ostride) {
+__global__ void k_finalize(const double* __restrict__ partial, int nout, int nvec, int NB, double* out, int ostride,
+                           const int* __restrict__ mask) {
   const int o = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (o >= nout) return;
+  if (mask && !mask[o / nvec]) return;
   double a = 0, c = 0;
   for (int b = lane; b < NB; b += 64) { a += partial[2 * ((long)o * NB + b)]; c += partial[2 * ((long)o * NB + b) + 1]; }
   a = wave_sum(a);
@@ -77,8 +79,9 @@ __global__ void k_finalize(const double* __restrict__ partial, int nout, int nve
     out[2 * d + 1] = c;
   }
 }
-void launch_finalize(const double* partial, int nout, int nvec, int NB, double* out, int ostride, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3((nout + 3) / 4), dim3(256), 0, st, partial, nout, nvec, NB, out, ostride);
+void launch_finalize(const double* partial, int nout, int nvec, int NB, double* out, int ostride, hipStream_t st,
+                     const int* mask) {
+  hipLaunchKernelGGL(k_finalize, dim3((nout + 3) / 4), dim3(256), 0, st, partial, nout, nvec, NB, out, ostride, mask);
 }
 
 template <typename T>
@@ -138,9 +141,10 @@ void launch_multiaxpy(cplx<T>* w, const cplx<T>* V, long vstride, int nvec, cons
   hipLaunchKernelGGL(k_multiaxpy<T>, grid, dim3(256), 0, st, w, V, vstride, nvec, coef, cstride, n, sign, active);
 }
 
+// y may be x (in place): no restrict on the two
 template <typename T>
-__global__ void k_scale_dev(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, const double* __restrict__ s,
-                            long n, const int* __restrict__ active) {
+__global__ void k_scale_dev(const cplx<T>* x, cplx<T>* y, const double* __restrict__ s, long n,
+                            const int* __restrict__ active) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -243,6 +247,27 @@ __global__ void k_krylov_start(KrylovDev k, double reltol, const double* abstol,
 }
 void launch_krylov_start(const KrylovDev& k, double reltol, const double* abstol, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_krylov_start, dim3((nrhs + 63) / 64), dim3(64), 0, st, k, reltol, abstol, nrhs);
+}
+
+__global__ void k_cgs_decide(KrylovDev k, int j, int nrhs, double eta2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int m = k.m;
+  const double* c1 = k.c1 + 2L * r * (m + 1);
+  double* c2 = k.c2 + 2L * r * (m + 1);
+  int need = 0;
+  if (k.active[r]) {
+    double s = 0;
+    for (int i = 0; i <= j; ++i) s += c1[2 * i] * c1[2 * i] + c1[2 * i + 1] * c1[2 * i + 1];
+    const double w2 = c1[2 * (j + 1)];
+    need = !(w2 - s >= eta2 * w2);   // NaN takes the second pass too
+  }
+  k.reorth[r] = need;
+  if (!need)
+    for (int i = 0; i <= j; ++i) { c2[2 * i] = 0; c2[2 * i + 1] = 0; }
+}
+void launch_cgs_decide(const KrylovDev& k, int j, int nrhs, double eta2, hipStream_t st) {
+  hipLaunchKernelGGL(k_cgs_decide, dim3((nrhs + 63) / 64), dim3(64), 0, st, k, j, nrhs, eta2);
 }
 
 __global__ void k_krylov_step(KrylovDev k, int j, int nrhs) {

@@ -62,7 +62,9 @@ int reduce_blocks(long n);
 template <typename T>
 void launch_multidot(const cplx<T>* V, long vstride, int nvec, const cplx<T>* w, long n, int nrhs,
                      double* partial, int NB, const int* active, hipStream_t st);
-void launch_finalize(const double* partial, int nout, int nvec, int NB, double* out, int ostride, hipStream_t st);
+// mask (may be null): outputs of right-hand sides with mask[r] == 0 are left as they are
+void launch_finalize(const double* partial, int nout, int nvec, int NB, double* out, int ostride, hipStream_t st,
+                     const int* mask = nullptr);
 template <typename T>
 void launch_norm2(const cplx<T>* w, long n, int nrhs, double* partial, int NB, const int* active, hipStream_t st);
 void launch_finalize_real(const double* partial, int nout, int NB, double* out, hipStream_t st);
@@ -104,9 +106,15 @@ struct KrylovDev {
   int* active = nullptr;     // [nrhs]
   int* kdone = nullptr;      // [nrhs]
   int* status = nullptr;     // [nrhs]: 0 running, 1 converged, 2 breakdown/NaN
+  int* reorth = nullptr;     // [nrhs]: second Gram-Schmidt pass needed this step
 };
 // start of a cycle: nrm holds ||r||, sets beta0, g, active, inv
 void launch_krylov_start(const KrylovDev& k, double reltol, const double* abstol, int nrhs, hipStream_t st);
+// after the first classical Gram-Schmidt pass of step j (c1 holds the j + 1
+// coefficients and, at j + 1, |w|^2 before the pass): reorth[r] = 1 where the
+// pass cancelled more than the factor eta2 of |w|^2 (|w'|^2 = |w|^2 - sum |c1|^2
+// < eta2 |w|^2), else c2 is zeroed and the second pass is skipped
+void launch_cgs_decide(const KrylovDev& k, int j, int nrhs, double eta2, hipStream_t st);
 // iteration j: c1 + c2 -> H column, nrm -> h_{j+1,j}; Givens; convergence
 void launch_krylov_step(const KrylovDev& k, int j, int nrhs, hipStream_t st);
 // triangular solve for y (uses kdone)

@@ -63,7 +63,7 @@ struct Krylov {
   bool flex = false;
   DevArr<cplx<T>> V, Z, w;
   DevArr<double> H, cs, sn, g, c1, c2, nrm, inv, beta0, tol, y, partial;
-  DevArr<int> active, kdone, status;
+  DevArr<int> active, kdone, status, reorth;
   void ensure(long n_, int m_, int nrhs, bool flex_, hipStream_t st);
   KrylovDev dev() const;
 };

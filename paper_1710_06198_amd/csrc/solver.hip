@@ -67,6 +67,7 @@ void Krylov<T>::ensure(long n_, int m_, int nrhs, bool flex_, hipStream_t st) {
   active.alloc(cap);
   kdone.alloc(cap);
   status.alloc(cap);
+  reorth.alloc(cap);
   launch_fill_zero(V.p, V.bytes(), st);
   if (flex) launch_fill_zero(Z.p, Z.bytes(), st);
   launch_fill_zero(w.p, w.bytes(), st);
@@ -81,7 +82,7 @@ KrylovDev Krylov<T>::dev() const {
   k.m = m;
   k.H = H.p; k.cs = cs.p; k.sn = sn.p; k.g = g.p; k.c1 = c1.p; k.c2 = c2.p;
   k.nrm = nrm.p; k.inv = inv.p; k.beta0 = beta0.p; k.tol = tol.p; k.y = y.p;
-  k.active = active.p; k.kdone = kdone.p; k.status = status.p;
+  k.active = active.p; k.kdone = kdone.p; k.status = status.p; k.reorth = reorth.p;
   return k;
 }
 
@@ -117,17 +118,22 @@ int krylov_cycle(Krylov<T>& K, const OpFn<T>& A, const OpFn<T>* M, const cplx<T>
       zj = K.Z.p + (long)j * vs;
       (*M)(vj, zj);
     }
-    A(zj, K.w.p);
-    launch_multidot(K.V.p, vs, j + 1, K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
-    launch_finalize(K.partial.p, nrhs * (j + 1), j + 1, NB, kd.c1, K.m + 1, st);
-    launch_multiaxpy(K.w.p, K.V.p, vs, j + 1, kd.c1, K.m + 1, n, nrhs, -1.0, kd.active, st);
-    launch_multidot(K.V.p, vs, j + 1, K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
-    launch_finalize(K.partial.p, nrhs * (j + 1), j + 1, NB, kd.c2, K.m + 1, st);
-    launch_multiaxpy(K.w.p, K.V.p, vs, j + 1, kd.c2, K.m + 1, n, nrhs, -1.0, kd.active, st);
-    launch_norm2(K.w.p, n, nrhs, K.partial.p, NB, kd.active, st);
+    // the new vector is formed in its own basis slot, so the first pass's
+    // dot products also give |w|^2 (the last of j + 2); the second pass
+    // runs only where the first cancelled more than a factor 10 of |w|
+    cplx<T>* wj = K.V.p + (long)(j + 1) * vs;
+    A(zj, wj);
+    launch_multidot(K.V.p, vs, j + 2, wj, n, nrhs, K.partial.p, NB, kd.active, st);
+    launch_finalize(K.partial.p, nrhs * (j + 2), j + 2, NB, kd.c1, K.m + 1, st);
+    launch_multiaxpy(wj, K.V.p, vs, j + 1, kd.c1, K.m + 1, n, nrhs, -1.0, kd.active, st);
+    launch_cgs_decide(kd, j, nrhs, 0.01, st);
+    launch_multidot(K.V.p, vs, j + 1, wj, n, nrhs, K.partial.p, NB, kd.reorth, st);
+    launch_finalize(K.partial.p, nrhs * (j + 1), j + 1, NB, kd.c2, K.m + 1, st, kd.reorth);
+    launch_multiaxpy(wj, K.V.p, vs, j + 1, kd.c2, K.m + 1, n, nrhs, -1.0, kd.reorth, st);
+    launch_norm2(wj, n, nrhs, K.partial.p, NB, kd.active, st);
     launch_finalize_real(K.partial.p, nrhs, NB, kd.nrm, st);
     launch_krylov_step(kd, j, nrhs, st);
-    if (j + 1 < maxit) launch_scale_dev(K.w.p, K.V.p + (long)(j + 1) * vs, kd.inv, n, nrhs, nullptr, st);
+    if (j + 1 < maxit) launch_scale_dev(wj, wj, kd.inv, n, nrhs, nullptr, st);
     done = j + 1;
     if (host_check) {
       HIPCHK(hipMemcpyAsync(host_flags, kd.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
