@@ -16,6 +16,9 @@ no blocking or fusion beyond what the definition states:
             the adaptive setup, two-step and shifted solves (Sec. 1.1)
   force.py  the pseudofermion force of S_f = phi^dag (D D^dag)^-1 phi
   mcrit.py  the bare mass m0 from the smallest-real-part eigenvalue
+  evenodd.py  the even-odd Schur complement of D(mu)
+  nd.py     the non-degenerate doublet D_ND(mubar, epsbar) of Eq. (2) and its
+            unit-link momentum-space solve
 
 All functions are pinned by tests/test_oracle_*.py against closed forms,
 exact identities, brute force on tiny lattices and dense solves.

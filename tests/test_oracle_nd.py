@@ -1,0 +1,52 @@
+"""Pins of the oracle's non-degenerate doublet operator (Sec. 1.1, Eq. 2)
+against what the mathematics fixes: the unit-link momentum-space form (an
+8 x 8 spin-flavour matrix per momentum, solved by FFT), the Hermiticity of
+Q_ND = (Gamma5 x tau_1) D_ND on random SU(3) links (Sec. 2.1), and the
+decoupled case epsbar = 0, which reduces to two light-sector closed forms."""
+import numpy as np
+import pytest
+import torch
+
+from lattice_inputs import gauge_links, gaussian_spinor, unit_links
+from oracle.dirac import WilsonClover, free_field_solve, spinor_to_field, vdot, norm
+from oracle.nd import NDOperator, free_field_nd_solve
+
+
+def doublet(dims, seed):
+    return spinor_to_field(gaussian_spinor(dims, seed, n=2))
+
+
+@pytest.mark.parametrize("mubar,epsbar", [(0.13, 0.11), (0.05, 0.2), (0.0, 0.3)])
+def test_unit_link_nd_matches_momentum_space_solve(mubar, epsbar):
+    dims = (4, 4, 4, 6)
+    m0 = -0.2
+    op = WilsonClover(unit_links(dims), m0, 1.7)   # the clover term vanishes at U = 1
+    nd = NDOperator(op, mubar, epsbar)
+    b = doublet(dims, 41)
+    x = free_field_nd_solve(b, m0, mubar, epsbar)
+    assert norm(nd.apply(x) - b) / norm(b) < 1e-12
+
+
+def test_decoupled_doublet_is_two_light_solves():
+    dims = (4, 4, 2, 6)
+    m0, mu = -0.25, 0.09
+    b = doublet(dims, 7)
+    x = free_field_nd_solve(b, m0, mu, 0.0)
+    assert norm(x[0] - free_field_solve(b[0], m0, mu)) / norm(x[0]) < 1e-12
+    assert norm(x[1] - free_field_solve(b[1], m0, -mu)) / norm(x[1]) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_q_nd_is_hermitian(seed):
+    dims = (4, 4, 4, 4)
+    op = WilsonClover(gauge_links(dims, seed=seed, eps=0.4), -0.1, 1.6)
+    nd = NDOperator(op, 0.12, 0.15)
+    a, c = doublet(dims, 10 + seed), doublet(dims, 20 + seed)
+    lhs = vdot(a, nd.apply_q(c))
+    rhs = vdot(nd.apply_q(a), c)
+    assert abs(lhs - rhs) < 1e-11 * norm(a) * norm(c)
+    # the same flavour swap with +mubar in both flavours is not Hermitian:
+    # the sign of the twist in the second flavour is what Eq. 2 fixes
+    q_bad = lambda f: op.g5 * torch.stack([op.apply(f[1], 0.12) - 0.15 * f[0],
+                                           op.apply(f[0], 0.12) - 0.15 * f[1]])
+    assert abs(vdot(a, q_bad(c)) - vdot(q_bad(a), c)) > 1e-3 * norm(a) * norm(c)
