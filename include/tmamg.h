@@ -133,6 +133,17 @@ tmamg_status tmamg_solve(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const
 tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
                                  tmamg_info* info);
 
+/* Non-degenerate doublet (Sec. 1.1, Eq. 2): solve
+ *   D_ND(mubar, epsbar) x = b,  D_ND = [[D(mubar), -epsbar], [-epsbar, D(-mubar)]]
+ * with the hierarchy built at setup (P_ND = P x I_2: each flavour's
+ * multigrid cycle at its own twisted mass +-mubar preconditions one flexible
+ * Krylov space over both flavours; the coupling enters the outer operator).
+ * b, x: device, canonical spinors [2] (flavour-major, the flavours' fields
+ * back to back).  Stops when ||b - D_ND x|| / ||b|| <= tol over both
+ * flavours together (FP64 true residual). */
+tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar, double epsbar, double tol,
+                            tmamg_info* info);
+
 /* Pseudofermion action S_f = phi^dag (D D^dag)^-1 phi at the setup mu and
  * its force F_mu(x) = sum_a (dS/dw^a) T^a for U -> exp(w) U, T^a = i lambda^a/2
  * (dS/dt = -2 sum tr(F w)); F is traceless anti-Hermitian.

@@ -24,6 +24,7 @@ EXPORTS = [
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
     "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
+    "tmamg_solve_nd",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY, K_SCHUR32 = range(10)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.tmamg_solve.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_solve_shifted.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_force.argtypes = [vp, vp, vp, P(d), d, P(Info)]
+    lib.tmamg_solve_nd.argtypes = [vp, vp, vp, d, d, d, P(Info)]
     lib.tmamg_force_from_fields.argtypes = [vp, vp, vp, vp]
     lib.tmamg_force_link_gradient.argtypes = [vp, vp, vp, d]
     lib.tmamg_apply.argtypes = [vp, i, i, vp, vp, i, P(d)]
@@ -211,6 +213,16 @@ class Solver:
         info = Info()
         st = self.lib.tmamg_solve_shifted(self.h, _ptr(b), _ptr(x), b.shape[0], _dvec(sigma), float(tol),
                                           ctypes.byref(info))
+        _check(st)
+        return info
+
+    def solve_nd(self, b, x, mubar, epsbar, tol=1e-10):
+        """Doublet D_ND(mubar, epsbar) x = b (Eq. 2); b, x: complex128 [2][T][Z][Y][X][4][3]."""
+        if b.shape[0] != 2 or x.shape[0] != 2:
+            raise ValueError("a doublet has two flavours: b and x need a leading axis of 2")
+        info = Info()
+        st = self.lib.tmamg_solve_nd(self.h, _ptr(b), _ptr(x), float(mubar), float(epsbar), float(tol),
+                                     ctypes.byref(info))
         _check(st)
         return info
 

@@ -203,6 +203,19 @@ void launch_add_to64(const cplx<T>* x, cplx<double>* y, long count, hipStream_t 
   hipLaunchKernelGGL(k_add_to64<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, count);
 }
 
+// Flavour coupling of the doublet operator (Sec. 1.1, Eq. 2): with the two
+// flavours stored back to back (n elements each), y_f += a x_{1-f}.
+template <typename T>
+__global__ void k_flavour_couple(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, double a, long n) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= 2 * n) return;
+  y[k] += (T)a * x[k < n ? k + n : k - n];
+}
+template <typename T>
+void launch_flavour_couple(const cplx<T>* x, cplx<T>* y, double a, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_flavour_couple<T>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st, x, y, a, n);
+}
+
 // plain streaming copy (16-byte accesses); the reference kernel of known
 // traffic for counter calibration
 __global__ void k_copy16(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
@@ -383,6 +396,7 @@ void launch_krylov_update(cplx<T>* x, const cplx<T>* Z, long zstride, const Kryl
   template void launch_axpby<T>(const cplx<T>*, cplx<T>*, double, double, long, hipStream_t);                  \
   template void launch_xmy<T>(const cplx<T>*, cplx<T>*, long, hipStream_t);                                    \
   template void launch_add_to64<T>(const cplx<T>*, cplx<double>*, long, hipStream_t);                          \
+  template void launch_flavour_couple<T>(const cplx<T>*, cplx<T>*, double, long, hipStream_t);                 \
   template void launch_krylov_update<T>(cplx<T>*, const cplx<T>*, long, const KrylovDev&, long, int, hipStream_t);
 INST_T(double)
 INST_T(float)

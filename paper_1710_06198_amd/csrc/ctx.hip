@@ -407,12 +407,26 @@ void Ctx::upload_mu(int nrhs, const double* mu_host) {
 // cycle's Krylov space, operator and multigrid run in FP32 (P, D_c in the
 // storage type) on r rounded to FP32, stopped at inner_tol * ||r|| (defect
 // correction); the correction is added to x in FP64.
-tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info) {
+// eps_nd set: the two right-hand sides are the flavours of one doublet
+// system D_ND x = b (Sec. 1.1, Eq. 2), twisted masses +-mubar in mu_host and
+// coupling -epsbar; one Krylov space spans both flavours, and the
+// preconditioner is the multigrid cycle of each flavour's own D(+-mubar)
+// (the coupling is left to the flexible outer iteration).
+tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info, const double* eps_nd) {
   const long n = 12 * fg.V;
+  const bool nd = eps_nd != nullptr;
+  const double eps = nd ? *eps_nd : 0.0;
+  if (nd) check(nrhs == 2, "a doublet has two flavours");
+  const int nk = nd ? 1 : nrhs;   // Krylov systems
+  auto sys_norms = [&](const cplx<double>* v) {
+    std::vector<double> h = norms(v, nrhs);
+    if (nd) h = {std::hypot(h[0], h[1])};
+    return h;
+  };
   upload_mu(nrhs, mu_host);
   launch_fill_zero(x64.p, (size_t)nrhs * n * sizeof(cplx<double>), st);
   HIPCHK(hipMemcpyAsync(r64.p, b64.p, (size_t)nrhs * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
-  std::vector<double> bn = norms(b64.p, nrhs);
+  std::vector<double> bn = sys_norms(b64.p);
   for (double v : bn)
     if (!std::isfinite(v)) throw TmError{TMAMG_ENUMERIC, "right-hand side holds NaN/Inf"};
   const bool mixed = par.precision == TMAMG_MIXED;
@@ -422,25 +436,29 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
   OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) {
     hipEvent_t e0 = timer.begin(st);
     launch_dslash<double>(o64, in, out, nrhs, mu_d, st);
+    if (nd) launch_flavour_couple<double>(in, out, -eps, n, st);
     timer.end(PhaseTimer::OUTER_OP, e0, st);
   };
   OpFn<float> A32 = [&](const cplx<float>* in, cplx<float>* out) {
     hipEvent_t e0 = timer.begin(st);
     launch_dslash<float>(o32, in, out, nrhs, mu_d, st);
+    if (nd) launch_flavour_couple<float>(in, out, -eps, n, st);
     timer.end(PhaseTimer::OUTER_OP, e0, st);
   };
   OpFn<double> M64 = [&](const cplx<double>* in, cplx<double>* out) { hier->precond_d(in, out, nrhs, mu_d); };
   OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, nrhs, mu_d); };
+  Krylov<double>& k64 = nd ? KN64 : K64;
+  Krylov<float>& k32 = nd ? KN32 : K32;
   const bool use_m = par.nlevels >= 1;
   int iters = 0, cycles = 0;
   tmamg_status status = TMAMG_NOT_CONVERGED;
   double worst = 0;
-  std::vector<double> at(nrhs);
+  std::vector<double> at(nk);
   while (true) {
-    std::vector<double> rn = norms(r64.p, nrhs);
+    std::vector<double> rn = sys_norms(r64.p);
     worst = 0;
     bool all = true;
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < nk; ++r) {
       if (!std::isfinite(rn[r])) throw TmError{TMAMG_ENUMERIC, "residual became NaN/Inf"};
       double rel = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
       worst = std::max(worst, rel);
@@ -450,16 +468,16 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     if (iters >= par.max_iter) break;
     int it;
     if (!mixed) {
-      for (int r = 0; r < nrhs; ++r) at[r] = 0.9 * tol * bn[r];
-      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-      it = krylov_cycle<double>(K64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nrhs,
+      for (int r = 0; r < nk; ++r) at[r] = 0.9 * tol * bn[r];
+      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nk * sizeof(double), hipMemcpyHostToDevice, st));
+      it = krylov_cycle<double>(k64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nk,
                                 std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
     } else {
-      for (int r = 0; r < nrhs; ++r) at[r] = std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]);
-      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      for (int r = 0; r < nk; ++r) at[r] = std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]);
+      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nk * sizeof(double), hipMemcpyHostToDevice, st));
       launch_convert<double, float>(r64.p, r32.p, (long)nrhs * n, st);
       launch_fill_zero(e32.p, (size_t)nrhs * n * sizeof(cplx<float>), st);
-      it = krylov_cycle<float>(K32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, nrhs,
+      it = krylov_cycle<float>(k32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, nk,
                                std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
       launch_add_to64<float>(e32.p, x64.p, (long)nrhs * n, st);
     }
@@ -467,6 +485,7 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     cycles += 1;
     // reliable update: r = b - D x in FP64
     launch_dslash<double>(o64, x64.p, t64.p, nrhs, mu_d, st);
+    if (nd) launch_flavour_couple<double>(x64.p, t64.p, -eps, n, st);
     launch_xmy<double>(b64.p, t64.p, (long)nrhs * n, st);
     std::swap(r64.p, t64.p);
     if (it == 0 && cycles > 3) break;   // no progress possible
@@ -526,6 +545,33 @@ tmamg_status Ctx::solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
+tmamg_status Ctx::solve_nd(const cplx<double>* b, cplx<double>* x, double mubar, double epsbar, double tol,
+                           tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
+  check(b && x, "bad solve arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  check(std::isfinite(mubar) && std::isfinite(epsbar), "non-finite doublet masses");
+  auto t0 = clk::now();
+  ensure(2);
+  const long n = 12 * fg.V;
+  const bool flex = par.nlevels >= 1;
+  if (par.precision == TMAMG_FP64)
+    KN64.ensure(2 * n, par.restart, 1, flex, st);
+  else
+    KN32.ensure(2 * n, par.restart, 1, flex, st);
+  const double mus[2] = {mubar, -mubar};
+  tmamg_info loc{};
+  launch_spinor_to_internal<double>(fg, b, b64.p, 2, st);
+  tmamg_status s = solve_core(2, mus, tol, &loc, &epsbar);
+  launch_spinor_to_canonical<double>(fg, x64.p, x, 2, st);
+  HIPCHK(hipStreamSynchronize(st));
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   loc.status = s;
   if (info) *info = loc;
   return s;
@@ -842,6 +888,15 @@ tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrh
     check(ctx != nullptr, "null context");
     return C(ctx)->solve_shifted(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, sigma,
                                  tol, info);
+  });
+}
+
+tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar, double epsbar, double tol,
+                            tmamg_info* info) {
+  return guarded([&]() {
+    check(ctx != nullptr, "null context");
+    return C(ctx)->solve_nd(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), mubar, epsbar, tol,
+                            info);
   });
 }
 

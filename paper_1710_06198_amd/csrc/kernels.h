@@ -86,6 +86,10 @@ void launch_xmy(const cplx<T>* x, cplx<T>* y, long count, hipStream_t st);
 // y(fp64) += x(T)
 template <typename T>
 void launch_add_to64(const cplx<T>* x, cplx<double>* y, long count, hipStream_t st);
+// doublet flavour coupling: x, y hold two flavours of n elements back to
+// back; y_f += a x_{1-f} (x and y distinct)
+template <typename T>
+void launch_flavour_couple(const cplx<T>* x, cplx<T>* y, double a, long n, hipStream_t st);
 // streaming copy of bytes (a multiple of 16)
 void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);

@@ -208,6 +208,8 @@ struct Ctx {
   // solve workspace
   Krylov<double> K64;
   Krylov<float> K32;
+  Krylov<double> KN64;   // doublet solves: one Krylov space over both flavours
+  Krylov<float> KN32;
   DevArr<cplx<double>> b64, x64, r64, t64;
   DevArr<cplx<float>> r32, e32;
   DevArr<double> mu_dev, abstol_dev, red_partial, red_out;
@@ -225,7 +227,10 @@ struct Ctx {
   void setup_update(const cplx<double>* U, int iters);
   void ensure(int nrhs);
   std::vector<double> norms(const cplx<double>* v, int nrhs);
-  tmamg_status solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info);
+  tmamg_status solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info,
+                          const double* eps_nd = nullptr);
+  tmamg_status solve_nd(const cplx<double>* b, cplx<double>* x, double mubar, double epsbar, double tol,
+                        tmamg_info* info);
   tmamg_status solve(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
                      tmamg_info* info);
   tmamg_status solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,

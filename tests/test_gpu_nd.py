@@ -1,0 +1,109 @@
+"""GPU parity of the non-degenerate doublet solve (Sec. 1.1, Eq. 2) through
+the C ABI: the FP64 true residual of D_ND(mubar, epsbar) x = b recomputed by
+the oracle's doublet operator, the unit-link solve against the oracle's
+momentum-space closed form, and the decoupled case against two light-sector
+solves."""
+import sys
+
+import pytest
+import torch
+
+from lattice_inputs import workload, load_m0, unit_links
+from oracle.dirac import WilsonClover, norm
+from oracle.nd import NDOperator, free_field_nd_solve
+from tests.gpu_common import links, spinors, kappa_of, rel, field, to_dev
+
+pytestmark = pytest.mark.gpu
+
+tm = pytest.importorskip("paper_1710_06198_amd")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = workload("c1")
+    m0 = load_m0()["c1"]
+    U, Ud = links(w.dims, w.eps, w.seeds["links"])
+    return w, m0, U, Ud, WilsonClover(U, m0, w.csw)
+
+
+def solver(w, precision, nlevels=2):
+    p = dict(nlevels=nlevels, agg=w.agg, nv=w.nv, setup_iters=w.setup_iters, init_smooth=w.init_smooth,
+             sap_sweeps=w.sap_sweeps, mr_steps=w.mr_steps, restart=w.restart, precision=precision)
+    if precision == tm.MIXED:
+        p["storage"] = tm.STORE_BF16
+    return tm.Solver(w.dims, tm.default_params(**p))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mubar,epsbar", [(0.12, 0.10), (0.15, 0.05)])
+def test_doublet_solve_true_residual(c1, precision, mubar, epsbar):
+    """Bar: ||b - D_ND x|| / ||b|| <= 1e-10 with D_ND the oracle's (FP64)."""
+    w, m0, U, Ud, op = c1
+    say(f"doublet solve c1 {precision} mubar={mubar} epsbar={epsbar}")
+    s = solver(w, tm.FP64 if precision == "fp64" else tm.MIXED)
+    s.setup(Ud, kappa_of(m0), w.csw, mubar)
+    b, bd = spinors(w.dims, 6101, 2)
+    x = torch.empty_like(bd)
+    info = s.solve_nd(bd, x, mubar, epsbar, tol=1e-10)
+    assert info.status == 0
+    nd = NDOperator(op, mubar, epsbar)
+    bf = field(b)
+    res = norm(bf - nd.apply(field(x.cpu()))) / norm(bf)
+    say(f"  {info.outer_iters} outer iterations, oracle residual {res:.2e} (library {info.true_rel_resid:.2e})")
+    assert res <= 1e-10
+    assert abs(res - info.true_rel_resid) <= 1e-12
+
+
+def test_doublet_unit_links_matches_closed_form():
+    """Unit links: the doublet solve against the oracle's FFT solve with one
+    8 x 8 spin-flavour matrix per momentum.  Bar 1e-8: the residual bound
+    1e-10 times the condition number of the free doublet at m0 = 0.1."""
+    dims = (8, 8, 8, 8)
+    m0, mubar, epsbar = 0.1, 0.06, 0.04
+    p = tm.default_params(nlevels=2, nv=(12, 0), precision=tm.MIXED, storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    s.setup(to_dev(unit_links(dims)), kappa_of(m0), 1.7, mubar)
+    b, bd = spinors(dims, 6102, 2)
+    x = torch.empty_like(bd)
+    info = s.solve_nd(bd, x, mubar, epsbar, tol=1e-10)
+    assert info.status == 0
+    err = rel(field(x.cpu()), free_field_nd_solve(field(b), m0, mubar, epsbar))
+    say(f"  free doublet: {err:.2e} after {info.outer_iters} outer iterations")
+    assert err < 1e-8
+
+
+def test_decoupled_doublet_equals_light_solves(c1):
+    """epsbar = 0: the doublet splits into D(mubar) x_0 = b_0 and
+    D(-mubar) x_1 = b_1; both routes meet the 1e-10 residual, so their
+    solutions agree to the condition number times 1e-10 (bar 1e-7)."""
+    w, m0, U, Ud, op = c1
+    mubar = 0.08
+    s = solver(w, tm.MIXED)
+    s.setup(Ud, kappa_of(m0), w.csw, mubar)
+    b, bd = spinors(w.dims, 6103, 2)
+    x = torch.empty_like(bd)
+    assert s.solve_nd(bd, x, mubar, 0.0, tol=1e-10).status == 0
+    y = torch.empty_like(bd)
+    assert s.solve(bd, y, [mubar, -mubar], tol=1e-10).status == 0
+    err = rel(x.cpu(), y.cpu())
+    say(f"  decoupled doublet vs two solves: {err:.2e}")
+    assert err < 1e-7
+
+
+def test_doublet_argument_errors(c1):
+    w, m0, U, Ud, op = c1
+    s = solver(w, tm.MIXED)
+    b, bd = spinors(w.dims, 6104, 2)
+    x = torch.empty_like(bd)
+    with pytest.raises(tm.TmamgError):
+        s.solve_nd(bd, x, 0.1, 0.1)          # before setup
+    s.setup(Ud, kappa_of(m0), w.csw, 0.1)
+    with pytest.raises(ValueError):
+        s.solve_nd(bd[:1], x[:1], 0.1, 0.1)  # one flavour
+    with pytest.raises(tm.TmamgError):
+        s.solve_nd(bd, x, float("nan"), 0.1)
