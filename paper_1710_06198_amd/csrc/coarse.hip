@@ -6,6 +6,7 @@
 
 #include "kernels.h"
 #include "mfma.h"
+#include "solver.h"
 
 template <typename S> using SP = typename Store<S>::pair;
 
@@ -898,8 +899,8 @@ void launch_galerkin_coarse(const CoarseGeom& g, int d, const int agg[4], const 
   if (shc <= 150 * 1024) {
     static bool attr = false;   // per instantiation: raise the dynamic LDS limit once
     if (!attr && shc > 64 * 1024) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_coarse_cols<T, S>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_coarse_cols<T, S>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
       attr = true;
     }
     hipLaunchKernelGGL((k_galerkin_coarse_cols<T, S>), dim3((unsigned)g2.V, 2, (nv + GAL_GC - 1) / GAL_GC),

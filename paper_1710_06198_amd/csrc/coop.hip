@@ -21,6 +21,7 @@
 
 #include "kernels.h"
 #include "mfma.h"
+#include "solver.h"
 
 template <typename S> using SP = typename Store<S>::pair;
 
@@ -283,8 +284,8 @@ static void coarse_apply_mf(const CoarseGeom& g, const bf16pair* Dc, const cplx<
   const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
   static bool attr = false;
   if (!attr && lds > 64 * 1024) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_apply_mf<D>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_apply_mf<D>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
   hipLaunchKernelGGL((k_coarse_apply_mf<D>), dim3((unsigned)g.V, (nrhs + MF_NR - 1) / MF_NR), dim3(256), lds, st, g,
@@ -677,10 +678,10 @@ static void sap_fused_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc
   const size_t lds = (size_t)MF_NR * 9 * D * sizeof(cplx<float>);
   static bool attr = false;
   if (!attr && lds > 60 * 1024) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D, 1>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D, MINB>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_resid_mf<D, 1>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_mr_mf<D, MINB>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
   SapArgs a;

@@ -1039,10 +1039,10 @@ void launch_galerkin_fine(const FineOp<T>& op, const SP<S>* P, int nv, SP<S>* Dc
   if (use4 && lds4 > 64 * 1024) {
     static bool attr = false;
     if (!attr) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 3>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 4>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 3>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_proj4<T, S, 4>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
       attr = true;
     }
   }
