@@ -407,14 +407,16 @@ def main():
     log(f"[bench] setup update: {upd['mixed']}")
 
     # non-degenerate doublet (Eq. 2) with the light sector's hierarchy (the
-    # same P, as for the heavy doublet of an Nf = 2+1+1 run): setup, then the
-    # timed doublet solve on a two-flavour source
+    # same P, as for the heavy doublet of an Nf = 2+1+1 run): setup, one
+    # doublet solve that allocates its workspace, then the timed doublet
+    # solve on the same two-flavour source
     nd_mu, nd_eps = 0.13, 0.11
     b2 = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"] + 7, n=2)).to(dev)
     x2 = torch.empty_like(b2)
 
     def nd_job(solver):
         solver.setup(U, kappa, w.csw, w.mu)
+        solver.solve_nd(b2, x2, nd_mu, nd_eps, tol=w.tol)   # allocates the two-flavour Krylov basis
         inf = solver.solve_nd(b2, x2, nd_mu, nd_eps, tol=w.tol).as_dict()
         return {"solve_s": inf["t_solve_s"], "outer_iters": inf["outer_iters"],
                 "true_rel_resid": inf["true_rel_resid"]}
