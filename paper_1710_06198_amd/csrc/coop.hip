@@ -1546,7 +1546,9 @@ static hipError_t site_gmres_launch(const SiteGmres& a, const SP<S>* Dc, const c
   return launch_resident(kern, (int)a.g.V, args, dyn, st);
 }
 
-// one right-hand side, FP32 over a 16-bit D_c, at most 256 sites
+// FP32 over a 16-bit D_c, at most 256 sites, one launch per right-hand side
+// (up to two: one launch at 300 us per RHS on the 24^3x48 hierarchy beats
+// the shared-site kernel's 750 us for a pair)
 template <typename T, typename S>
 static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cplx<T>* b, cplx<T>* x, int nrhs,
                            const double* mu_dev, int m, double reltol, cplx<T>* Vbasis, double* dws, size_t dws_cap,
@@ -1554,7 +1556,7 @@ static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
   if constexpr (!std::is_same<T, float>::value || sizeof(SP<S>) != 4) {
     return false;
   } else {
-    if (nrhs != 1 || g.V > 256 || m + 1 > 4 * SITE_SLOTS) return false;
+    if (nrhs < 1 || nrhs > 2 || g.V > 256 || m + 1 > 4 * SITE_SLOTS) return false;
     const int G = (int)g.V;
     const int Gp = (G + 1) & ~1;
     if ((size_t)2 * Gp * (m + 2) > dws_cap || iws_cap < 8) return false;
@@ -1572,17 +1574,24 @@ static bool try_site_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
     ws.err = iws + 2;
     ws.stat = iws + 3;
     ws.reorth = iws + 7;
-    hipError_t e;
-    switch (d) {
-      case 24: e = site_gmres_launch<S, 24>(a, Dc, b, x, mu_dev, ws, st); break;
-      case 32: e = site_gmres_launch<S, 32>(a, Dc, b, x, mu_dev, ws, st); break;
-      case 48: e = site_gmres_launch<S, 48>(a, Dc, b, x, mu_dev, ws, st); break;
-      case 64: e = site_gmres_launch<S, 64>(a, Dc, b, x, mu_dev, ws, st); break;
-      default: return false;
-    }
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
+    // the launches share the workspace in stream order; a failure leaves x to
+    // the caller's fallback, which solves every right-hand side again
+    const long n = g.V * (long)d;
+    for (int r = 0; r < nrhs; ++r) {
+      const cplx<float>* br = b + r * n;
+      cplx<float>* xr = x + r * n;
+      hipError_t e;
+      switch (d) {
+        case 24: e = site_gmres_launch<S, 24>(a, Dc, br, xr, mu_dev + r, ws, st); break;
+        case 32: e = site_gmres_launch<S, 32>(a, Dc, br, xr, mu_dev + r, ws, st); break;
+        case 48: e = site_gmres_launch<S, 48>(a, Dc, br, xr, mu_dev + r, ws, st); break;
+        case 64: e = site_gmres_launch<S, 64>(a, Dc, br, xr, mu_dev + r, ws, st); break;
+        default: return false;
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
     }
     return true;
   }
