@@ -107,3 +107,26 @@ def test_doublet_argument_errors(c1):
         s.solve_nd(bd[:1], x[:1], 0.1, 0.1)  # one flavour
     with pytest.raises(tm.TmamgError):
         s.solve_nd(bd, x, float("nan"), 0.1)
+
+
+def test_doublet_three_level_mixed():
+    """Three levels (4^4 then 2^4 aggregates, the bench's shape of hierarchy)
+    on 8^3x16: the two flavours' coarsest solves run as one launch each.
+    Bar: the oracle's doublet residual <= 1e-10."""
+    dims = (8, 8, 8, 16)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1235)
+    op = WilsonClover(U, m0, 1.6)
+    p = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(1, 1, 1, 2),
+                          precision=tm.MIXED, storage=tm.STORE_BF16)
+    s = tm.Solver(dims, p)
+    mubar, epsbar = 0.13, 0.11
+    s.setup(Ud, kappa_of(m0), 1.6, 0.01)
+    b, bd = spinors(dims, 6105, 2)
+    x = torch.empty_like(bd)
+    info = s.solve_nd(bd, x, mubar, epsbar, tol=1e-10)
+    assert info.status == 0
+    bf = field(b)
+    res = norm(bf - NDOperator(op, mubar, epsbar).apply(field(x.cpu()))) / norm(bf)
+    say(f"  three-level doublet: {info.outer_iters} outer iterations, oracle residual {res:.2e}")
+    assert res <= 1e-10
