@@ -130,3 +130,39 @@ def test_doublet_three_level_mixed():
     res = norm(bf - NDOperator(op, mubar, epsbar).apply(field(x.cpu()))) / norm(bf)
     say(f"  three-level doublet: {info.outer_iters} outer iterations, oracle residual {res:.2e}")
     assert res <= 1e-10
+
+
+def test_doublet_graph_replay_matches_eager():
+    """Intermediate-level solves replayed from captured HIP graphs (two
+    flavours, so two coarsest launches per capture) give the same bits and
+    iteration counts as plain launches, over three doublet solves in a row
+    with eager work between them."""
+    dims = (8, 8, 16, 16)
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, 0.3, 1238)
+    op = WilsonClover(U, m0, 1.6)
+    base = dict(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(1, 1, 2, 2), setup_iters=1,
+                l2_iters=6, coarsest_iters=10, precision=tm.MIXED, storage=tm.STORE_BF16)
+    solvers = []
+    for g in (0, 1):
+        s = tm.Solver(dims, tm.default_params(use_graph=g, **base))
+        s.setup(Ud, kappa_of(m0), 1.6, 0.003)
+        solvers.append(s)
+    for seed, (mubar, epsbar) in ((6201, (0.13, 0.11)), (6202, (0.13, 0.11)), (6203, (0.2, 0.05))):
+        b, bd = spinors(dims, seed, 2)
+        xs, iters = [], []
+        for s in solvers:
+            x = torch.empty_like(bd)
+            info = s.solve_nd(bd, x, mubar, epsbar, tol=1e-10)
+            assert info.status == 0
+            xs.append(x)
+            iters.append(info.outer_iters)
+            y = torch.empty_like(bd)
+            s.apply(tm.OP_D64, 0, x, y, [mubar, -mubar])   # eager work between the solves
+            torch.cuda.synchronize()
+        say(f"  doublet graph replay seed {seed}: outer {iters}")
+        assert iters[0] == iters[1]
+        assert torch.equal(xs[0], xs[1])
+        bf = field(b)
+        res = norm(bf - NDOperator(op, mubar, epsbar).apply(field(xs[1].cpu()))) / norm(bf)
+        assert res <= 1e-10
