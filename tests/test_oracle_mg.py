@@ -270,3 +270,65 @@ def test_c1_two_step_and_shifted(c1_hierarchy):
     x = mg.shifted_solve(H, b, sigma, w.mu, 1e-11)
     lhs = op.apply(op.apply_dag(x, w.mu), w.mu) + sigma * x
     assert norm(lhs - b) / norm(b) < 1e-8
+
+
+def test_three_level_exactly_resolved_case_one_iteration():
+    """Three levels, both coarsenings square and unitary (one-site aggregates,
+    N_v = 6 at each, so 2 N_v equals the dof of the finer site).  The coarsest
+    GMRES is run to 1e-14, so the level-1 cycle is an exact inverse of D_c,
+    the intermediate FGMRES (preconditioned by that cycle, Sec. 1.1) needs one
+    step per call, and the fine FGMRES converges in one iteration.  A wrong
+    operator, transfer or sign anywhere in the intermediate branch breaks
+    either count."""
+    dims = (2, 2, 2, 4)
+    op = WilsonClover(gauge_links(dims, 0.35, 61), -0.2, 1.2)
+    mu = 0.04
+    p = mg.MGParams(nlevels=3, agg=((1, 1, 1, 1), (1, 1, 1, 1)), nv=(6, 6),
+                    sap_block=((1, 1, 2, 2), (1, 1, 2, 2)), setup_iters=0,
+                    l2_tol=1e-14, l2_restart=10, l2_maxiter=10,
+                    coarsest_tol=1e-14, coarsest_maxiter=400)
+    H = mg.Hierarchy(op, p, mu)
+    H.setup(mg.setup_vectors(p, dims, 62))
+    assert len(H.levels) == 2 and H.levels[1].nxt is not None and H.levels[1].nxt.nxt is None
+    H.stats = {"coarse_iters": 0, "coarsest_iters": 0}
+    b = rnd(dims, 63)
+    res = H.solve(b, 1e-10, restart=10, maxiter=10)
+    assert res.converged and res.iters == 1
+    assert norm(op.apply(res.x, mu) - b) / norm(b) < 1e-10
+    # one fine iteration = one intermediate solve, which took a single step
+    assert H.stats["coarse_iters"] == 1
+    # and the intermediate solve reproduces D_c^-1 on its own
+    lvl1 = H.levels[1]
+    rc = rnd(lvl1.op.dims, 64, dof=12)
+    ec = H.coarse_solve(lvl1, rc, mu)
+    assert norm(lvl1.op.apply(ec, mu) - rc) / norm(rc) < 1e-12
+
+
+def test_setup_iterations_improve_convergence():
+    """Quality trend of the adaptive setup (its result is not unique, so
+    this is the check the method admits): the outer FGMRES iteration count
+    does not grow with the number of setup iterations (0, 1, 3), and three
+    iterations at least halve the count of the initial phase alone.
+
+    Input: the 8^4 workload's links with periodic time and m0 = -0.17, where
+    SAP alone needs 82 iterations.  With the workload's antiperiodic time the
+    lowest momentum keeps |lambda| near sin(pi/8) and SAP alone converges
+    in 22 iterations, so no coarse space (random or adapted) can show a
+    trend there."""
+    w = workload("c1")
+    op = WilsonClover(gauge_links(w.dims, w.eps, w.seeds["links"]), -0.17, w.csw, antiperiodic=False)
+    mu = 0.001
+    b = spinor_to_field(gaussian_spinor(w.dims, w.seeds["source"])[0])
+    its = {}
+    for n in (0, 1, 3):
+        p = mg.MGParams(nlevels=2, agg=w.agg, nv=w.nv, sap_block=w.sap_block,
+                        setup_iters=n, mr_steps=w.mr_steps)
+        H = mg.Hierarchy(op, p, mu)
+        H.setup(mg.setup_vectors(p, w.dims, w.seeds["testvec"]))
+        r = H.solve(b, 1e-10, restart=w.restart)
+        assert r.converged
+        assert norm(b - op.apply(r.x, mu)) / norm(b) <= 1e-10
+        its[n] = r.iters
+    print("outer iterations by setup iterations:", its)
+    assert its[0] >= its[1] >= its[3]
+    assert 2 * its[3] <= its[0]
