@@ -1,16 +1,21 @@
 """Benchmark: DD-alpha-AMG time to solution on one MI355X.
 
-Workload (default): the 24^3 x 48 precision-form case - synthetic links
+Workload (default, c3): the 32^3 x 64 mixed+batched job - synthetic links
 (spread 0.25), c_sw = 1.6, mu = 0.0015, 3-level DD-alpha-AMG (4^4 then 2^4
-aggregates, N_v = 24/32, SAP 4^4 / 3^4 with 4 MR steps, 3 setup
-iterations), FP32 stencil/SAP with bf16 P and D_c, FP64 outer FGMRES with
-reliable updates, one Gaussian right-hand side solved to relative residual
-1e-10.  A step is one full job: setup (link conversion, clover, adaptive
-setup) plus the solve.  The plain FP64 DD-alpha-AMG on the same GPU is
-timed alongside for the speed-up, and the fine stencil's HBM roofline is
-measured with HIP events on the library's stream.
+aggregates, N_v = 24/32, SAP 4^4 / 2^4 with 4 MR steps, 3 setup
+iterations), FP32 stencil/SAP with bf16 P and D_c on the matrix cores, FP64
+outer FGMRES with reliable updates, intermediate-level solves replayed from
+HIP graphs.  A step is one whole job: the setup, 12 spin-colour point
+sources at random sites solved as one batch of D(mu) x = b, and 8 shifted
+systems (D D^dag + sigma_k) x = b (sigma_k log-spaced in [1e-5, 1], one
+Gaussian source) as a second batch of two-step solves, every result to
+relative residual 1e-10.  The plain FP64 DD-alpha-AMG on the same GPU runs
+the same job (warmed up and timed the same way) for the speed-up; the fine
+SAP (the kernel with the largest share of the job) and the fine stencil
+are measured against the HBM roofline with HIP events on the library's
+stream; the oracle's cost of the job is estimated from its own timings.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4]
 """
 from __future__ import annotations
 
@@ -160,6 +165,87 @@ def cpu_baseline(w, m0, budget_dims=(8, 8, 8, 8)):
     }
 
 
+def oracle_unit_costs(w, m0, sample_dims=(16, 16, 16, 32)):
+    """The oracle's time for one application of each unit of work the job
+    is made of, measured on a 16^3 x 32 lattice with the workload's link
+    spread, c_sw, mu and exactly its hierarchy shape (4^4 then 2^4
+    aggregates, N_v 24/32, SAP blocks 4^4 and 2^4, 4 MR steps, at most 6
+    intermediate and 10 coarsest steps), then scaled to the workload's
+    volume by the site ratio.  Units: one fine operator application D, one
+    fine SAP application (k sweeps from zero), one multigrid cycle B_MG
+    (Eq. (1), with the coarse solves run to their step limits).  P and D_c
+    are timing stand-ins (orthonormalised random vectors, random coarse
+    blocks of the Galerkin shapes): the cost of these steps does not depend
+    on the numbers in them."""
+    import torch
+    from lattice_inputs import gauge_links, gaussian_spinor
+    from oracle.dirac import WilsonClover, spinor_to_field
+    from oracle import mg
+    t_all = time.time()
+    U = gauge_links(sample_dims, w.eps, w.seeds["links"])
+    op = WilsonClover(U, m0, w.csw)
+    v = spinor_to_field(gaussian_spinor(sample_dims, w.seeds["source"])[0])
+    p = mg.MGParams(nlevels=3, agg=w.agg, nv=w.nv, sap_block=w.sap_block, sap_sweeps=w.sap_sweeps,
+                    mr_steps=w.mr_steps, setup_iters=0, init_smooth=0, l2_restart=6, l2_maxiter=6, l2_tol=0.0,
+                    coarsest_tol=0.0, coarsest_maxiter=10)
+    H = mg.Hierarchy(op, p, w.mu)
+    gen = torch.Generator().manual_seed(7)
+
+    def rnd(*shape):
+        return torch.complex(torch.randn(*shape, generator=gen, dtype=torch.float64),
+                             torch.randn(*shape, generator=gen, dtype=torch.float64))
+
+    def coarse_stand_in(dims, d):
+        lx, ly, lz, lt = dims
+        S = 0.1 * rnd(lt, lz, ly, lx, d, d) + 4.0 * torch.eye(d, dtype=torch.complex128)
+        return mg.CoarseOp(S, 0.1 * rnd(4, lt, lz, ly, lx, d, d), 0.1 * rnd(4, lt, lz, ly, lx, d, d))
+
+    fine = H.levels[0]
+    fine.tv = mg.random_test_vectors(sample_dims, 12, w.nv[0], w.seeds["testvec"])
+    fine.P = mg.build_prolongation(fine.tv, w.agg[0], sample_dims, 12)
+    d1 = tuple(sample_dims[m] // w.agg[0][m] for m in range(4))
+    lvl1 = mg.Level(coarse_stand_in(d1, 2 * w.nv[0]), 1)
+    fine.nxt = lvl1
+    H.levels.append(lvl1)
+    lvl1.tv = mg.random_test_vectors(d1, 2 * w.nv[0], w.nv[1], w.seeds["testvec"] + 100)
+    lvl1.P = mg.build_prolongation(lvl1.tv, w.agg[1], d1, 2 * w.nv[0])
+    d2 = tuple(d1[m] // w.agg[1][m] for m in range(4))
+    lvl1.nxt = mg.Level(coarse_stand_in(d2, 2 * w.nv[1]), 2)
+
+    def timed(f):
+        t0 = time.time()
+        f()
+        return time.time() - t0
+
+    t_D = min(timed(lambda: op.apply(v, w.mu)) for _ in range(2))
+    t_S = timed(lambda: mg.sap(op, v, torch.zeros_like(v), w.mu, w.sap_block[0], w.sap_sweeps[0], w.mr_steps))
+    t_B = timed(lambda: H.precondition(fine, v, w.mu))
+    vol = 1
+    for d in sample_dims:
+        vol *= d
+    scale = w.volume / vol
+    return {"D": t_D * scale, "SAP": t_S * scale, "B": t_B * scale, "scale": scale,
+            "sample_dims": list(sample_dims), "sample_s": time.time() - t_all,
+            "sample_units_s": {"D": t_D, "SAP": t_S, "B": t_B}}
+
+
+def job_unit_counts(w, infos):
+    """Units of oracle work in one job of the batched workload, from the
+    library's own iteration counts: every outer FGMRES iteration applies
+    B_MG and D once per right-hand side of its batch; the setup smooths N_v
+    vectors init_smooth times, applies B_MG to them setup_iters times, and
+    forms D P for 2 N_v columns at each of its 1 + setup_iters builds; each
+    restart cycle adds one FP64 residual per right-hand side."""
+    nv0 = w.nv[0]
+    npt, nsh = w.extra["n_point"], w.extra["n_shift"]
+    ip, ish = infos
+    B = ip["outer_iters"] * npt + ish["outer_iters"] * nsh + w.setup_iters * nv0
+    D = (ip["outer_iters"] + ip["cycles"]) * npt + (ish["outer_iters"] + ish["cycles"]) * nsh \
+        + (1 + w.setup_iters) * 2 * nv0
+    SAP = w.init_smooth * nv0
+    return {"B": B, "D": D, "SAP": SAP}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -180,20 +266,49 @@ def _timed(fn):
     return out, time.perf_counter() - t0
 
 
+SAP_BYTES_FIXED, SAP_BYTES_RHS = 576, 384
+
+
+def sap_roofline(tm, solver, V, nrhs, reps):
+    """The fine SAP kernel (one colour of blocks, all MR steps) for nrhs
+    right-hand sides, timed with HIP events on the library's stream.
+    Algorithmic bytes per site of the colour: links and clover once (576 B
+    FP32), and per right-hand side the source, the iterate read and written
+    and the neighbouring iterate for the block residual (4 x 96 B)."""
+    ms = solver.time_kernel(tm.K_SAP0, nrhs, reps)
+    sites = V // 2
+    byts = sites * (SAP_BYTES_FIXED + SAP_BYTES_RHS * nrhs)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "k_sap_fine<float, 3> (fine SAP, one colour, 4 MR steps per block)",
+            "rhs": nrhs, "sites_per_launch": sites,
+            "bytes_per_launch": byts, "bytes_per_site": f"{SAP_BYTES_FIXED} + {SAP_BYTES_RHS} x rhs",
+            "ms_per_launch": ms}
+
+
+def stencil_roofline(tm, solver, V, reps, nrhs=1):
+    ms = solver.time_kernel(tm.K_DSLASH32, nrhs, reps)
+    byts = V * (576 + 192 * nrhs)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"kernel": "k_dslash<float>" + (", true" if nrhs > 1 else ""), "rhs": nrhs, "ms": ms,
+            "bytes_per_launch": byts, "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+
 def bench_batched(args):
-    """32^3 x 64: 12 spin-colour point sources at random sites solved as one
-    batch of D(mu) x = b, plus 8 shifted systems (D D^dag + sigma_k) x = b
-    (sigma_k log-spaced in [1e-5, 1]) on one Gaussian source as a second
-    batch (two-step solves with mu' = sqrt(mu^2 + sigma)), mixed precision
-    against the plain FP64 DD-alpha-AMG.  Restart 12 bounds the Krylov
-    memory of 12-wide batches."""
+    """32^3 x 64 (the metric's configuration): setup, 12 spin-colour point
+    sources at random sites as one batch of D(mu) x = b, and 8 shifted
+    systems (D D^dag + sigma_k) x = b (sigma_k log-spaced in [1e-5, 1]) on
+    one Gaussian source as a second batch of two-step solves, mixed
+    precision, against the plain FP64 DD-alpha-AMG running the same job.
+    Restart 12 bounds the Krylov memory of 12-wide batches."""
     import torch
     import paper_1710_06198_amd as tm
-    from lattice_inputs import workload, gauge_links, gaussian_spinor, point_sources, rational_shifts, load_m0
+    from lattice_inputs import workload, gauge_links, point_sources, gaussian_spinor, rational_shifts, load_m0
     w = workload("c3")
     m0 = load_m0()[w.name]
     kappa = 1.0 / (2 * m0 + 8)
     dev = torch.device("cuda:0")
+    V = w.volume
     log(f"[bench] workload c3 dims {w.dims}: generating inputs")
     U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
     npt, nsh = w.extra["n_point"], w.extra["n_shift"]
@@ -201,41 +316,112 @@ def bench_batched(args):
     g1 = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"] + 100, n=1)).to(dev)
     bs = g1.expand(nsh, *g1.shape[1:]).contiguous()
     sig = [float(x) for x in rational_shifts(nsh)]
-    res = {}
-    for prec, name in ((tm.MIXED, "mixed"), (tm.FP64, "fp64")):
-        if name == "fp64" and args.no_fp64:
-            continue
-        p = solver_params(tm, w, prec, args.graph)
-        p.restart = 12
-        s = tm.Solver(w.dims, p)
-        if name == "mixed" and args.tune:
-            s.setup(U, kappa, w.csw, w.mu)
-            res["autotuned_variants"] = autotune(tm, s, [1, npt, nsh] + list(w.nv), args)
-        _, t_setup = _timed(lambda: s.setup(U, kappa, w.csw, w.mu))
-        xp = torch.empty_like(bp)
-        ip, t_pt = _timed(lambda: s.solve(bp, xp, tol=w.tol))
-        xs = torch.empty_like(bs)
-        ish, t_sh = _timed(lambda: s.solve_shifted(bs, xs, sig, tol=w.tol))
-        res[name] = {"setup_s": t_setup, "point_sources_s": t_pt, "shifted_s": t_sh,
-                     "total_s": t_setup + t_pt + t_sh, "point_outer_iters": ip.outer_iters,
-                     "point_true_rel_resid": ip.true_rel_resid, "shifted_outer_iters": ish.outer_iters,
-                     "shifted_true_rel_resid": ish.true_rel_resid}
-        log(f"[bench]   {name}: {res[name]}")
-        s.close()
-        del xp, xs
+    xp = torch.empty_like(bp)
+    xs = torch.empty_like(bs)
+    stream = torch.cuda.Stream(device=dev)
+
+    def job(solver):
+        solver.setup(U, kappa, w.csw, w.mu)
+        ip = solver.solve(bp, xp, tol=w.tol).as_dict()
+        ish = solver.solve_shifted(bs, xs, sig, tol=w.tol).as_dict()
+        return ip, ish
+
+    def run(solver, warmup, steps, name):
+        for i in range(warmup):
+            ip, ish = job(solver)
+            log(f"[bench] {name} warmup {i}: sources {ip['outer_iters']} it, shifts {ish['outer_iters']} it")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = []
+        for i in range(steps):
+            recs.append(job(solver))
+            ip, ish = recs[-1]
+            log(f"[bench] {name} step {i}: setup {ip['t_setup_s']:.3f} s, sources {ip['t_solve_s']:.3f} s "
+                f"({ip['outer_iters']} it, {ip['true_rel_resid']:.1e}), shifts {ish['t_solve_s']:.3f} s "
+                f"({ish['outer_iters']} it, {ish['true_rel_resid']:.1e})")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n = len(recs)
+        return {"s_per_step": (t1 - t0) / n, "setup_s": sum(r[0]["t_setup_s"] for r in recs) / n,
+                "point_sources_s": sum(r[0]["t_solve_s"] for r in recs) / n,
+                "shifted_s": sum(r[1]["t_solve_s"] for r in recs) / n, "steps": n, "warmup": warmup,
+                "point_outer_iters": recs[-1][0]["outer_iters"], "point_cycles": recs[-1][0]["cycles"],
+                "point_true_rel_resid": max(r[0]["true_rel_resid"] for r in recs),
+                "point_level1_steps": recs[-1][0]["l2_iters_total"],
+                "point_coarsest_iters": recs[-1][0]["coarsest_iters_total"],
+                "shifted_outer_iters": recs[-1][1]["outer_iters"], "shifted_cycles": recs[-1][1]["cycles"],
+                "shifted_true_rel_resid": max(r[1]["true_rel_resid"] for r in recs),
+                "shifted_level1_steps": recs[-1][1]["l2_iters_total"],
+                "shifted_coarsest_iters": recs[-1][1]["coarsest_iters_total"]}, recs[-1]
+
+    p = solver_params(tm, w, tm.MIXED, args.graph)
+    p.restart = 12
+    mixed = tm.Solver(w.dims, p, stream=stream)
+    tuned = None
+    if args.tune:
+        mixed.setup(U, kappa, w.csw, w.mu)
+        tuned = autotune(tm, mixed, [1, npt, nsh] + list(w.nv), args)
+    m, last = run(mixed, args.warmup, args.steps, "mixed")
+    log(f"[bench] mixed: {m}")
+
+    # kernels against their roofline (HIP events on the library stream)
+    sap = sap_roofline(tm, mixed, V, npt, 10)
+    log(f"[bench] fine SAP roofline (12 RHS): {sap}")
+    sap_other = {n: round(mixed.time_kernel(tm.K_SAP0, n, 5), 4) for n in (1, nsh, w.nv[0])}
+    sten = stencil_roofline(tm, mixed, V, 20)
+    sten12 = stencil_roofline(tm, mixed, V, 5, npt)
+    log(f"[bench] stencil: {sten} / 12 RHS {sten12}")
+    kern = {}
+    for nm, kid in (("restrict_fine", tm.K_RESTRICT0), ("prolong_fine", tm.K_PROLONG0),
+                    ("coarse_op_l1", tm.K_DC1), ("coarse_op_l2", tm.K_DC2), ("sap_coarse_sweep", tm.K_SAP1)):
+        kern[nm + "_12rhs"] = round(mixed.time_kernel(kid, npt, 5), 4)
+    mfma = batched_coarse(tm, mixed, 20)
+    mixed.close()
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not args.no_fp64:
+        p64 = solver_params(tm, w, tm.FP64)
+        p64.restart = 12
+        plain = tm.Solver(w.dims, p64, stream=stream)
+        fp64, _ = run(plain, 1, min(args.steps, 2), "fp64")
+        log(f"[bench] fp64: {fp64}")
+        plain.close()
         torch.cuda.empty_cache()
-    tuned = res.pop("autotuned_variants", None)
-    m = res["mixed"]
-    out = {"metric": "batched solve time (s) @1e-10 rel. resid: 12 point sources + 8 shifted systems",
-           "value": m["total_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
-           "ms_per_step": m["total_s"] * 1e3, "higher_is_better": False, "scaling": "strong",
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle: unit costs on a 16^3 x 32 sample")
+        unit = oracle_unit_costs(w, m0)
+        cnt = job_unit_counts(w, last)
+        est = sum(cnt[k] * unit[k] for k in cnt)
+        cpu = {"value": est, "unit": "s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": (f"oracle time per unit measured at {'x'.join(map(str, unit['sample_dims']))} with the "
+                          f"workload's parameters and hierarchy shape (D {unit['sample_units_s']['D']:.2f} s, SAP "
+                          f"{unit['sample_units_s']['SAP']:.2f} s, B_MG {unit['sample_units_s']['B']:.2f} s; "
+                          f"{unit['sample_s']:.0f} s in all), scaled by the site ratio {unit['scale']:.0f} and "
+                          f"multiplied by the units one job uses ({cnt}) from the library's iteration counts"),
+               "units_s_at_workload_volume": {k: unit[k] for k in ("D", "SAP", "B")}, "unit_counts": cnt,
+               "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count()}
+        log(f"[bench] cpu baseline: {cpu}")
+
+    out = {"metric": "solve time (s) @1e-10 rel. resid & stencil HBM GB/s; mixed+batched vs FP64 AMG",
+           "value": m["s_per_step"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": m["s_per_step"] * 1e3, "higher_is_better": False, "scaling": "strong",
            "vs_baseline": None, "dtype": "fp32+bf16 (fp64 outer)", "data": "synthetic",
-           "config": {"workload": "c3: 32x32x32x64, 3-level DD-alpha-AMG, 12 point sources + 8 shifts, restart 12",
-                      "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "shifts": sig,
-                      "hip_graph_level1_solve": bool(args.graph)},
-           "mixed": m, "fp64_amg": res.get("fp64"),
-           "speedup_vs_fp64": (res["fp64"]["total_s"] / m["total_s"]) if "fp64" in res else None,
-           "per_rhs_s": m["total_s"] / (npt + nsh), "autotuned_variants": tuned}
+           "config": {"workload": "c3: 32x32x32x64 twisted-mass clover, 3-level DD-alpha-AMG, mixed precision; "
+                                  "one step = setup + 12 point sources (one batch) + 8 shifted systems "
+                                  "(D D^dag + sigma) (one batch of two-step solves), all to 1e-10",
+                      "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "m0": m0, "nv": list(w.nv),
+                      "shifts": sig, "restart": 12, "tol": w.tol, "hip_graph_level1_solve": bool(args.graph),
+                      "parallelism": "1 GPU"},
+           "mixed": m, "fp64_amg": fp64,
+           "speedup_vs_fp64": (fp64["s_per_step"] / m["s_per_step"]) if fp64 else None,
+           "per_rhs_s": m["s_per_step"] / (npt + nsh),
+           "roofline": sap,
+           "stencil_roofline": {"1rhs": sten, "12rhs": sten12},
+           "sap_fine_ms_by_rhs": sap_other, "kernel_ms": kern,
+           "mfma_batched_coarse": mfma, "autotuned_variants": tuned, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -292,12 +478,37 @@ def bench_force(args):
     return 0
 
 
+def kernels_only(args):
+    """Timing loops for profiler and counter passes: a context with links
+    and clover but no multigrid (so no setup kernels run), then the FP32
+    stencil (1 RHS), the fine SAP for one colour at 12 right-hand sides and
+    the 512 MiB copy kernel, 10 timed launches each after one warm launch."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, load_m0
+    w = workload(args.workload)
+    m0 = load_m0()[w.name]
+    dev = torch.device("cuda:0")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    p = tm.default_params(nlevels=1, agg=w.agg, precision=tm.MIXED, storage=tm.STORE_BF16, setup_iters=0,
+                          init_smooth=0, mr_steps=w.mr_steps)
+    s = tm.Solver(w.dims, p, stream=torch.cuda.Stream(device=dev))
+    s.setup(U, 1.0 / (2 * m0 + 8), w.csw, w.mu)
+    n = w.extra.get("n_point", 12)
+    out = {"workload": w.name, "sites": w.volume, "dslash_fp32_ms": s.time_kernel(tm.K_DSLASH32, 1, 10),
+           "sap_fine_rhs": n, "sap_fine_ms": s.time_kernel(tm.K_SAP0, n, 10),
+           "copy_512MiB_ms": s.time_kernel(tm.K_COPY, 1, 10)}
+    print(json.dumps(out), flush=True)
+    s.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--graph", type=int, choices=(0, 1), default=None,
@@ -308,7 +519,8 @@ def main():
                     help="autotune the kernel variants on the workload's hierarchy before timing")
     ap.add_argument("--tune-cache", default=None, help="variant table JSON to load if present, else to write")
     ap.add_argument("--kernels-only", action="store_true",
-                    help="only the stencil and copy timing loops (for hardware-counter passes)")
+                    help="only the timing loops of the fine stencil, the fine SAP (12 right-hand sides) and "
+                         "the copy kernel on a context without a multigrid setup (for profiler passes)")
     args = ap.parse_args()
     if args.graph is None:
         args.graph = 1 if args.workload == "c3" else 0
@@ -321,6 +533,8 @@ def main():
     import paper_1710_06198_amd as tm
     from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
 
+    if args.kernels_only:
+        return kernels_only(args)
     if args.workload == "c3":
         return bench_batched(args)
     if args.workload == "c4":
@@ -341,15 +555,6 @@ def main():
         return solver.solve(b, x, tol=w.tol)
 
     mixed = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED, args.graph), stream=stream)
-    if args.kernels_only:
-        mixed.setup(U, kappa, w.csw, w.mu)
-        d_ms = mixed.time_kernel(tm.K_DSLASH32, 1, 10)
-        c_ms = mixed.time_kernel(tm.K_COPY, 1, 10)
-        mf = batched_coarse(tm, mixed, 10)
-        print(json.dumps({"dslash_fp32_ms": d_ms, "copy_512MiB_ms": c_ms, "sites": w.volume, "mfma": mf}),
-              flush=True)
-        mixed.close()
-        return 0
     tuned = None
     if args.tune:
         mixed.setup(U, kappa, w.csw, w.mu)
@@ -428,13 +633,16 @@ def main():
     if not args.no_fp64:
         log("[bench] plain FP64 DD-alpha-AMG")
         plain = tm.Solver(w.dims, solver_params(tm, w, tm.FP64), stream=stream)
+        job(plain)   # warm-up: first-call allocations, as the mixed solver had
+        nf = min(args.steps, 3)
         torch.cuda.synchronize()
         f0 = time.perf_counter()
-        fi = job(plain).as_dict()
+        for _ in range(nf):
+            fi = job(plain).as_dict()
         torch.cuda.synchronize()
         f1 = time.perf_counter()
-        fp64 = {"total_s": f1 - f0, "setup_s": fi["t_setup_s"], "solve_s": fi["t_solve_s"],
-                "outer_iters": fi["outer_iters"], "true_rel_resid": fi["true_rel_resid"]}
+        fp64 = {"total_s": (f1 - f0) / nf, "steps": nf, "warmup": 1, "setup_s": fi["t_setup_s"],
+                "solve_s": fi["t_solve_s"], "outer_iters": fi["outer_iters"], "true_rel_resid": fi["true_rel_resid"]}
         log(f"[bench]   {fp64}")
         upd["fp64"] = update_job(plain)
         upd["speedup_vs_fp64"] = upd["fp64"]["total_s"] / upd["mixed"]["total_s"]

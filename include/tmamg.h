@@ -37,6 +37,8 @@
 #ifndef TMAMG_H
 #define TMAMG_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -84,26 +86,55 @@ typedef struct {
                            every fine cycle is captured once per right-hand-side
                            count as a HIP graph and replayed (same kernels, same
                            order, identical results); 0: plain launches */
+  int nd_coarse_coupling;  /* doublet solves (Sec. 1.1, Eq. (2)): 1 (default) the coarse
+                              levels solve D_ND,c = P_ND^dag D_ND P_ND, i.e. each flavour's
+                              D_c(+-mubar) coupled by -epsbar; 0: each flavour's own cycle */
 } tmamg_params;
 
 typedef struct {
   int status;              /* tmamg_status of the call */
   int outer_iters;         /* FGMRES iterations summed over cycles */
   int cycles;              /* restart cycles / reliable updates */
-  double true_rel_resid;   /* max over right-hand sides of ||b - D x|| / ||b|| (FP64) */
+  double true_rel_resid;   /* max over right-hand sides of ||b - D x|| / ||b|| (FP64);
+                              tmamg_solve_shifted: of ||b - (D D^dag + sigma) x|| / ||b|| */
   double t_setup_s;        /* last setup */
   double t_solve_s;        /* this call */
+  long long l2_iters_total;       /* intermediate-level FGMRES steps in this call, summed over
+                                     its calls (a batch's step counts once) */
+  long long coarsest_iters_total; /* coarsest-level GMRES iterations in this call, summed over
+                                     calls and right-hand sides */
 } tmamg_info;
 
+/* Device memory for a context's internal buffers (optional, see
+ * tmamg_create).  alloc returns `bytes` of device memory usable on
+ * hip_stream, or NULL when it cannot (the call then fails with
+ * TMAMG_ENOMEM); free releases a pointer alloc returned.  `user` is passed
+ * through.  Both are called only from inside the library's own calls on
+ * that context, on the calling thread. */
+typedef void* (*tmamg_alloc_fn)(size_t bytes, void* hip_stream, void* user);
+typedef void (*tmamg_free_fn)(void* ptr, void* hip_stream, void* user);
+typedef struct {
+  tmamg_alloc_fn alloc;
+  tmamg_free_fn free;
+  void* user;
+} tmamg_allocator;
+
 /* Fill *p with the defaults (2 levels, 4^4 aggregates, N_v = 12, 3 setup
- * iterations, SAP k = 4 with 4 MR steps, FGMRES(30), FP64). */
+ * iterations, SAP k = 4 with 4 MR steps, FGMRES(30), FP64): the method's
+ * parameters of Sec. 1.1, which the paper does not print (plumbing). */
 tmamg_status tmamg_default_params(tmamg_params* p);
 
-/* Create a context for one lattice.  hip_stream: a hipStream_t (NULL = the
- * null stream).  Lattice extents must be multiples of agg[0] (and agg[1]
- * on the coarse lattice); SAP needs an even number of blocks (or one) per
- * dimension on every smoothed level.  *ctx is NULL on error. */
-tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream);
+/* Create a context for one lattice (the lattice and multigrid parameters
+ * of Sec. 1.1; the paper's runs use three levels, Sec. 1.2).  hip_stream: a
+ * hipStream_t (NULL = the null stream).  allocator: host, may be NULL
+ * (hipMalloc/hipFree); when given, every internal device buffer of the
+ * context comes from allocator->alloc and goes back through
+ * allocator->free, at the latest in tmamg_destroy; the struct is copied.
+ * Lattice extents must be multiples of agg[0] (and agg[1] on the coarse
+ * lattice); SAP needs an even number of blocks (or one) per dimension on
+ * every smoothed level.  *ctx is NULL on error. */
+tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream,
+                          const tmamg_allocator* allocator);
 
 /* Setup (Sec. 1.1 adaptive setup): copy the links U (device, canonical
  * complex128), build the clover term for c_sw and m0 = 1/(2 kappa) - 4,
@@ -113,23 +144,46 @@ tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg
  * D_c.  Links must be SU(3) within 1e-6 (TMAMG_ENUMERIC otherwise). */
 tmamg_status tmamg_setup(tmamg_ctx* ctx, const void* U, double kappa, double csw, double mu);
 
-/* Setup update on new links U (same kappa, c_sw, mu): the existing test
- * vectors are improved by `iters` further setup iterations (the paper
- * updates with one iteration per physical-mass inversion). */
+/* Setup update on new links U (same kappa, c_sw, mu), Sec. 2 (setup
+ * updates along the molecular-dynamics trajectory, one setup iteration per
+ * update): P and D_c are rebuilt on U from the kept test vectors, which
+ * then take `iters` further setup iterations.  U: device, canonical; the
+ * same SU(3) check and errors as tmamg_setup; TMAMG_ESTATE before a
+ * setup. */
 tmamg_status tmamg_setup_update(tmamg_ctx* ctx, const void* U, int iters);
 
-/* Solve D(mu_r) x_r = b_r for r < nrhs, in one batch.  b, x: device,
- * canonical spinors [nrhs].  mu_rhs: host [nrhs] signed twisted masses, or
- * NULL for the setup mu on every right-hand side.  Stops when every
- * ||b_r - D x_r|| / ||b_r|| <= tol (FP64 true residual). */
+/* Solve D(mu_r) x_r = b_r for r < nrhs, in one batch: FGMRES
+ * right-preconditioned by the multigrid cycle of Sec. 1.1, Eq. (1), with
+ * D(-mu) through the same P (Sec. 1.1, D_c(+-mu) = D_c +- i mu Gamma5,c).
+ * b, x: device, canonical spinors [nrhs] (may not alias).  mu_rhs: host
+ * [nrhs] signed twisted masses, or NULL for the setup mu on every
+ * right-hand side.  Stops when every ||b_r - D x_r|| / ||b_r|| <= tol (FP64
+ * true residual), 0 < tol < 1.  A zero b_r gives x_r = 0.  TMAMG_ESTATE
+ * before a setup; TMAMG_ENUMERIC for NaN/Inf in b; TMAMG_EHIP also when a
+ * persistent coarse kernel's bounded barrier wait gave up (x still holds
+ * the iterate the FP64 residual in info describes; the context then stops
+ * using those kernels). */
 tmamg_status tmamg_solve(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
                          tmamg_info* info);
 
+/* tmamg_solve from an initial guess: on entry x holds x0_r (device,
+ * canonical [nrhs]); the first FP64 residual is b - D x0.  A right-hand side
+ * whose initial residual exceeds ||b_r|| starts from zero instead.  Used for
+ * the first-order initial guesses of shifted systems (Sec. 3, Eq. (6): an
+ * expansion of the shifted inverse in the shift). */
+tmamg_status tmamg_solve_guess(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                               tmamg_info* info);
+
 /* Squared / shifted systems (D D^dag + sigma_r) x_r = b_r with one
- * hierarchy: since D D^dag + sigma = D(mu') D(mu')^dag with
+ * hierarchy (the two-step solves of Sec. 1.1 for D^dag D, and the shifted
+ * systems of the Hasenbusch monomials, Eq. (3), and of the rational
+ * approximation, Eq. (5)): since D D^dag + sigma = D(mu') D(mu')^dag with
  * mu' = sqrt(mu^2 + sigma), solve D(mu') w = b, then
- * x = Gamma5 D(-mu')^-1 Gamma5 w (the two-step solve of Sec. 1.1).
- * sigma: host [nrhs] (>= 0; sigma = 0 gives D D^dag). */
+ * x = Gamma5 D(-mu')^-1 Gamma5 w, each step to tol; the FP64 residual of
+ * the shifted system itself is then checked and, while above tol, the pair
+ * of solves is repeated on it (defect correction, at most three passes).
+ * sigma: host [nrhs] (>= 0; sigma = 0 gives D D^dag).  b, x: device
+ * canonical [nrhs]; info.true_rel_resid is the shifted system's residual. */
 tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
                                  tmamg_info* info);
 
@@ -146,12 +200,16 @@ tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar
 
 /* Pseudofermion action S_f = phi^dag (D D^dag)^-1 phi at the setup mu and
  * its force F_mu(x) = sum_a (dS/dw^a) T^a for U -> exp(w) U, T^a = i lambda^a/2
- * (dS/dt = -2 sum tr(F w)); F is traceless anti-Hermitian.
+ * (dS/dt = -2 sum tr(F w)); F is traceless anti-Hermitian.  The HMC force
+ * of Sec. 1.2 (its solves use the DD-alpha-AMG of Sec. 1.1 to tol; the
+ * paper's MD forces use 1e-9) and Sec. 2: Y = D^-1 phi, X = (D^dag)^-1 Y,
+ * then the adjoint of the hopping and clover terms on (X, Y).
  * phi: device spinor [1]; F: device [4][T][Z][Y][X][3][3]; S: host. */
 tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info);
 
-/* The force for given X = (D D^dag)^-1 phi and Y = D^dag X (device spinors),
- * without solves: F from the hopping and clover derivatives. */
+/* The force of tmamg_force (Sec. 1.2) for given X = (D D^dag)^-1 phi and
+ * Y = D^dag X (device canonical spinors), without solves: F from the
+ * hopping and clover derivatives.  F: device [4][T][Z][Y][X][3][3]. */
 tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F);
 
 /* Link gradient of S_f for automatic differentiation (Sec. 1.2 force, as
@@ -164,9 +222,11 @@ tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* 
  * [4][T][Z][Y][X][3][3] complex128 (may not alias); scale: host. */
 tmamg_status tmamg_force_link_gradient(tmamg_ctx* ctx, const void* F, void* G, double scale);
 
-/* Operator hook for tests.  op: one of TMAMG_OP_*; level: 0 fine, 1, 2.
- * in/out: device, canonical fields of that level, nrhs of them; mu_rhs host
- * [nrhs] or NULL (setup mu). */
+/* Operator hook for tests: the single steps of the method of Sec. 1.1
+ * (operator, transfers P and P^dag, Galerkin D_c, SAP, the cycle of
+ * Eq. (1), the coarsest solve).  op: one of TMAMG_OP_*; level: 0 fine, 1,
+ * 2.  in/out: device, canonical fields of that level, nrhs of them (may not
+ * alias); mu_rhs host [nrhs] or NULL (setup mu). */
 enum {
   TMAMG_OP_D64 = 0,       /* fine D(mu) in FP64 */
   TMAMG_OP_D32 = 1,       /* fine D(mu) in FP32 (rounded in/out) */
@@ -183,12 +243,24 @@ enum {
                              entries of out are 0.  Level 0.  Assumes the Hermitian part
                              of the site-diagonal term is positive definite (m0 + 4 above
                              the clover term's spectral radius) */
-  TMAMG_OP_SCHUR32 = 9    /* the same in FP32 (rounded in/out) */
+  TMAMG_OP_SCHUR32 = 9,   /* the same in FP32 (rounded in/out) */
+  TMAMG_OP_DDAG64 = 10,   /* fine D(mu)^dag = Gamma5 D(-mu) Gamma5 in FP64 (Sec. 1.1) */
+  TMAMG_OP_DDAG32 = 11,   /* the same in FP32 (rounded in/out) */
+  TMAMG_OP_DCND = 12      /* doublet coarse operator D_ND,c = P_ND^dag D_ND P_ND (Sec. 1.1,
+                             Eq. (2), P_ND = P x I_2) on level 1 or 2: nrhs = 2 (the two
+                             flavours' coarse fields), mu_rhs = {mubar, epsbar} (required) */
 };
 tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
                          const double* mu_rhs);
 
-/* Parity hooks.  set_test_vectors: the next setup starts from these N_v
+/* Test hook for failure paths (no passage of the paper): what = 0 marks a timed-out barrier wait in the
+ * persistent coarse kernels' status word, as a real timeout would; the next
+ * solve then returns TMAMG_EHIP and the context falls back to the generic
+ * coarse kernels.  Needs a setup with two or more levels. */
+tmamg_status tmamg_debug_inject(tmamg_ctx* ctx, int what);
+
+/* Test hooks for parity of the setup's P and D_c (Sec. 1.1: P from the
+ * test vectors, D_c = P^dag D P).  set_test_vectors: the next setup starts from these N_v
  * vectors of level `level` (device, canonical level fields) instead of noise.
  * export: what = 0 copies P of coarsening `level` (N_v canonical fields of
  * the finer level, complex128) to out; what = 1 copies D_c of level
@@ -197,7 +269,7 @@ tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void
 tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void* v);
 tmamg_status tmamg_debug_export(tmamg_ctx* ctx, int what, int level, void* out);
 
-/* Kernel timing for measurements: launches kernel `kernel` `reps` times on
+/* Measurement (no passage of the paper): kernel timing; launches kernel `kernel` `reps` times on
  * internal buffers of nrhs right-hand sides (random contents) between two
  * HIP events on the context's stream and stores the mean milliseconds per
  * launch in *avg_ms (host).  Kernels: TMAMG_K_*. Needs a completed setup
@@ -228,7 +300,10 @@ tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, d
  *   TMAMG_TUNE_RESTRICT0,
  *   TMAMG_TUNE_PROLONG0      a = N_v, b = fine sites; 0 vector ALU, 1 matrix cores
  *   TMAMG_TUNE_SAP0          fine SAP, a = block sites, b = fine sites;
- *                            register budget for 0 one / 1 three workgroups per CU
+ *                            register budget for 0 one / 1 three workgroups per CU,
+ *                            one right-hand side per workgroup; 2: two right-hand
+ *                            sides per workgroup (lane pairs on one site share every
+ *                            link and clover load)
  * A variant a launcher cannot run for its precision, storage or shape is
  * ignored (the rule applies).  Every variant computes the same operation;
  * results differ only by rounding (SAP0 variants not at all).  The table
@@ -241,31 +316,36 @@ enum {
   TMAMG_TUNE_PROLONG0 = 3,
   TMAMG_TUNE_SAP0 = 4
 };
-/* Autotuner: for every right-hand-side count nrhs_list[0..n) (host, each
- * 1..64) and every family with two variants for this context's hierarchy,
- * times each variant over `reps` launches (HIP events, as
- * tmamg_time_kernel) and stores the faster in the table.  json_path: if
- * not NULL, the whole table is written there as JSON (entries with the
- * measured milliseconds of each variant).  Needs a completed setup. */
+/* Measurement and plumbing: the autotuner.  For every right-hand-side
+ * count nrhs_list[0..n) (host, each 1..64) and every family with two
+ * variants for this context's hierarchy, times each variant over `reps`
+ * launches (HIP events, as tmamg_time_kernel) and stores the faster in the
+ * table.  json_path: if not NULL, the whole table is written there as JSON
+ * (entries with the measured milliseconds of each variant).  Needs a
+ * completed setup. */
 tmamg_status tmamg_autotune(tmamg_ctx* ctx, const int* nrhs_list, int n, int reps, const char* json_path);
-/* Add the entries of a file written by tmamg_autotune or tmamg_tune_save
- * (same keys are replaced); *n_entries (may be NULL) = entries read.
+/* Plumbing: add the entries of a file written by tmamg_autotune or
+ * tmamg_tune_save (same keys are replaced); *n_entries (may be NULL) =
+ * entries read.
  * TMAMG_EINVAL if the file is unreadable or malformed (nothing is added). */
 tmamg_status tmamg_tune_load(const char* json_path, int* n_entries);
 tmamg_status tmamg_tune_save(const char* json_path);
-/* Set one entry (variant -1 removes it; TMAMG_EINVAL beyond the family's
- * variants); read one (-1: none). */
+/* Plumbing: set one entry (variant -1 removes it; TMAMG_EINVAL beyond the
+ * family's variants); read one (-1: none). */
 tmamg_status tmamg_tune_set(int family, long a, long b, long nrhs, int variant);
 int tmamg_tune_get(int family, long a, long b, long nrhs);
 int tmamg_tune_entries(void);
 void tmamg_tune_clear(void);
 
-/* Sizes of level `level`: sites and dof per site (fine: 12). */
+/* Plumbing: sizes of level `level`: sites and dof per site (fine: 12;
+ * coarse: 2 N_v, Sec. 1.1). */
 tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int* dof);
 
+/* Plumbing: release the context and every buffer it owns (through the
+ * allocator given at creation).  NULL is ignored. */
 void tmamg_destroy(tmamg_ctx* ctx);
 
-/* Message for the last non-OK status of the calling thread. */
+/* Plumbing: message for the last non-OK status of the calling thread. */
 const char* tmamg_last_error(void);
 
 #ifdef __cplusplus

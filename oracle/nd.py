@@ -7,7 +7,9 @@ Sec. 1.1, Eq. 2: for the heavy (strange-charm) doublet
                         = [[D(mubar), -epsbar], [-epsbar, D(-mubar)]]
 
 with D(+-mubar) the twisted-mass clover operator of the light sector, and
-Q_ND = (Gamma5 x tau_1) D_ND its Hermitian form (Sec. 2.1).  Fields carry the
+Q_ND = (Gamma5 x tau_1) D_ND its Hermitian form (Sec. 3).  The coarse
+doublet operator is the Galerkin product with P_ND = P x I_2 (Sec. 1.1,
+after Eq. 2), written out below as prolong, apply, restrict per flavour.  Fields carry the
 flavour as their leading axis: [2, T, Z, Y, X, 12].
 
 The unit-link closed form below is the same operator in momentum space: one
@@ -74,3 +76,14 @@ def free_field_nd_solve(b: torch.Tensor, m0: float, mubar: float, epsbar: float)
     xf = xf.reshape(lt, lz, ly, lx, 2, 4, 3).permute(4, 0, 1, 2, 3, 5, 6).reshape(2, lt, lz, ly, lx, 12)
     x = torch.fft.ifftn(xf, dim=(1, 2, 3, 4))
     return x / ph
+
+
+def coarse_nd_apply(op: WilsonClover, P, mubar: float, epsbar: float, e: torch.Tensor) -> torch.Tensor:
+    """D_ND,c e = P_ND^dag D_ND P_ND e with P_ND = P x I_2 (P an oracle
+    Prolongation of the light sector): each flavour's coarse field is
+    prolonged with P, D_ND acts on the doublet, and each flavour is
+    restricted with P^dag.  e: [2, Tc, Zc, Yc, Xc, d]."""
+    nd = NDOperator(op, mubar, epsbar)
+    w = torch.stack([P.prolong(e[0]), P.prolong(e[1])])
+    y = nd.apply(w)
+    return torch.stack([P.restrict(y[0]), P.restrict(y[1])])

@@ -6,8 +6,10 @@ the HIP library.  Loading fails loudly when the library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # TMAMG_LIB selects another build of the library (same ABI)
@@ -16,7 +18,8 @@ LIB_PATH = os.environ.get("TMAMG_LIB", os.path.join(HERE, "libtmamg.so"))
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16 = 0, 1, 2, 3
-OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST, OP_SCHUR64, OP_SCHUR32 = range(10)
+(OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST, OP_SCHUR64, OP_SCHUR32, OP_DDAG64,
+ OP_DDAG32, OP_DCND) = range(13)
 
 EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",
@@ -24,7 +27,7 @@ EXPORTS = [
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
     "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
-    "tmamg_solve_nd",
+    "tmamg_solve_nd", "tmamg_solve_guess", "tmamg_debug_inject",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY, K_SCHUR32 = range(10)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
@@ -55,6 +58,7 @@ class Params(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("seed", ctypes.c_ulonglong),
         ("use_graph", ctypes.c_int),
+        ("nd_coarse_coupling", ctypes.c_int),
     ]
 
 
@@ -66,10 +70,20 @@ class Info(ctypes.Structure):
         ("true_rel_resid", ctypes.c_double),
         ("t_setup_s", ctypes.c_double),
         ("t_solve_s", ctypes.c_double),
+        ("l2_iters_total", ctypes.c_longlong),
+        ("coarsest_iters_total", ctypes.c_longlong),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
 
 
 _lib = None
@@ -86,11 +100,13 @@ def load(path: str = LIB_PATH):
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     P = ctypes.POINTER
     lib.tmamg_default_params.argtypes = [P(Params)]
-    lib.tmamg_create.argtypes = [P(vp), P(Lattice), P(Params), vp]
+    lib.tmamg_create.argtypes = [P(vp), P(Lattice), P(Params), vp, P(Allocator)]
     lib.tmamg_setup.argtypes = [vp, vp, d, d, d]
     lib.tmamg_setup_update.argtypes = [vp, vp, i]
     lib.tmamg_solve.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
+    lib.tmamg_solve_guess.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_solve_shifted.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
+    lib.tmamg_debug_inject.argtypes = [vp, i]
     lib.tmamg_force.argtypes = [vp, vp, vp, P(d), d, P(Info)]
     lib.tmamg_solve_nd.argtypes = [vp, vp, vp, d, d, d, P(Info)]
     lib.tmamg_force_from_fields.argtypes = [vp, vp, vp, vp]
@@ -159,14 +175,82 @@ def _dvec(vals):
     return arr
 
 
-class Solver:
-    """One context of the library.  Buffers are torch complex128 CUDA tensors."""
+def check_field(name, t, count, device):
+    """Validate a buffer handed to the library: a complex128, contiguous
+    tensor of `count` elements on `device`.  The C ABI takes raw pointers, so
+    a wrong dtype or size would be read or written out of bounds there."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name}: dtype must be complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() != count:
+        raise ValueError(f"{name}: expected {count} complex elements, got {t.numel()} (shape {tuple(t.shape)})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: must be on {device}, found {t.device}")
 
-    def __init__(self, dims, params: Params = None, antiperiodic: bool = True, stream=None):
+
+def check_values(name, vals, n):
+    if vals is None:
+        return
+    if len(vals) != n:
+        raise ValueError(f"{name}: expected {n} values (one per right-hand side), got {len(vals)}")
+
+
+# live contexts, closed at interpreter exit before any module is torn down:
+# the library's buffers may belong to torch's caching allocator, and no
+# device memory is released after the runtimes start finalising
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
+def torch_allocator(device, stream):
+    """A tmamg_allocator backed by torch's caching allocator on `device`,
+    stream-ordered on `stream` (device memory then shows up in
+    torch.cuda.memory_allocated and is reused by torch after close)."""
+    import torch
+    dev_index = torch.device(device).index or 0
+
+    def _alloc(nbytes, hip_stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev_index, stream=int(hip_stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, hip_stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    a = Allocator()
+    a.alloc = ALLOC_FN(_alloc)
+    a.free = FREE_FN(_free)
+    a.user = None
+    return a
+
+
+class Solver:
+    """One context of the library.  Buffers are torch complex128 CUDA tensors.
+
+    allocator: "torch" (default) lets torch's caching allocator back every
+    internal device buffer; None uses hipMalloc/hipFree inside the library."""
+
+    def __init__(self, dims, params: Params = None, antiperiodic: bool = True, stream=None, allocator="torch"):
         import torch
         lib = load()
         self.lib = lib
-        self.dims = tuple(dims)
+        self.dims = tuple(int(d) for d in dims)
         self.params = params if params is not None else default_params()
         lat = Lattice()
         for m in range(4):
@@ -174,10 +258,36 @@ class Solver:
         lat.t_antiperiodic = 1 if antiperiodic else 0
         s = stream if stream is not None else torch.cuda.current_stream()
         self._stream = s
+        self.device = torch.device("cuda", s.device.index if s.device.index is not None else 0)
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = torch_allocator(self.device, s)
+        elif allocator is not None:
+            raise ValueError('allocator must be "torch" or None')
         h = ctypes.c_void_p()
         _check(lib.tmamg_create(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(self.params),
-                                ctypes.c_void_p(s.cuda_stream)))
+                                ctypes.c_void_p(s.cuda_stream),
+                                ctypes.byref(self._alloc) if self._alloc is not None else None))
         self.h = h
+        _live.add(self)
+
+    @property
+    def volume(self):
+        v = 1
+        for d in self.dims:
+            v *= d
+        return v
+
+    def _spinors(self, name, t, n=None):
+        if n is None:
+            n = t.shape[0] if hasattr(t, "shape") and len(t.shape) > 0 else 0
+        if n < 1:
+            raise ValueError(f"{name}: needs a leading right-hand-side axis")
+        check_field(name, t, n * self.volume * 12, getattr(self, "device", None))
+        return n
+
+    def _links(self, name, t):
+        check_field(name, t, 4 * self.volume * 9, getattr(self, "device", None))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -195,24 +305,34 @@ class Solver:
     links_version = 0
 
     def setup(self, U, kappa, csw, mu):
+        self._links("U", U)
         _check(self.lib.tmamg_setup(self.h, _ptr(U), float(kappa), float(csw), float(mu)))
         self.links_version += 1
 
     def setup_update(self, U, iters=1):
+        self._links("U", U)
         _check(self.lib.tmamg_setup_update(self.h, _ptr(U), int(iters)))
         self.links_version += 1
 
-    def solve(self, b, x, mu_rhs=None, tol=1e-10):
+    def solve(self, b, x, mu_rhs=None, tol=1e-10, guess=False):
+        """D(mu_r) x_r = b_r; guess=True starts from the x passed in."""
+        n = self._spinors("b", b)
+        self._spinors("x", x, n)
+        check_values("mu_rhs", mu_rhs, n)
         info = Info()
-        n = b.shape[0]
-        st = self.lib.tmamg_solve(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol), ctypes.byref(info))
+        fn = self.lib.tmamg_solve_guess if guess else self.lib.tmamg_solve
+        st = fn(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol), ctypes.byref(info))
         _check(st)
         return info
 
     def solve_shifted(self, b, x, sigma, tol=1e-10):
+        n = self._spinors("b", b)
+        self._spinors("x", x, n)
+        if sigma is None:
+            raise ValueError("sigma: one shift per right-hand side is required")
+        check_values("sigma", sigma, n)
         info = Info()
-        st = self.lib.tmamg_solve_shifted(self.h, _ptr(b), _ptr(x), b.shape[0], _dvec(sigma), float(tol),
-                                          ctypes.byref(info))
+        st = self.lib.tmamg_solve_shifted(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol), ctypes.byref(info))
         _check(st)
         return info
 
@@ -220,6 +340,8 @@ class Solver:
         """Doublet D_ND(mubar, epsbar) x = b (Eq. 2); b, x: complex128 [2][T][Z][Y][X][4][3]."""
         if b.shape[0] != 2 or x.shape[0] != 2:
             raise ValueError("a doublet has two flavours: b and x need a leading axis of 2")
+        self._spinors("b", b, 2)
+        self._spinors("x", x, 2)
         info = Info()
         st = self.lib.tmamg_solve_nd(self.h, _ptr(b), _ptr(x), float(mubar), float(epsbar), float(tol),
                                      ctypes.byref(info))
@@ -227,26 +349,62 @@ class Solver:
         return info
 
     def force(self, phi, F, tol=1e-12):
+        self._spinors("phi", phi, 1)
+        self._links("F", F)
         info = Info()
         S = ctypes.c_double()
         _check(self.lib.tmamg_force(self.h, _ptr(phi), _ptr(F), ctypes.byref(S), float(tol), ctypes.byref(info)))
         return S.value, info
 
     def force_from_fields(self, X, Y, F):
+        self._spinors("X", X, 1)
+        self._spinors("Y", Y, 1)
+        self._links("F", F)
         _check(self.lib.tmamg_force_from_fields(self.h, _ptr(X), _ptr(Y), _ptr(F)))
 
     def force_link_gradient(self, F, G, scale=1.0):
+        self._links("F", F)
+        self._links("G", G)
         _check(self.lib.tmamg_force_link_gradient(self.h, _ptr(F), _ptr(G), float(scale)))
 
     def apply(self, op, level, inp, out, mu_rhs=None):
-        _check(self.lib.tmamg_apply(self.h, int(op), int(level), _ptr(inp), _ptr(out), inp.shape[0],
-                                    _dvec(mu_rhs)))
+        n = inp.shape[0]
+        lin = lout = int(level)
+        if op == OP_PROLONG:
+            lout = lin - 1
+        elif op == OP_RESTRICT:
+            lout = lin + 1
+        sin, din = self.level_info(lin)
+        sout, dout = self.level_info(lout)
+        check_field("in", inp, n * sin * din, self.device)
+        check_field("out", out, n * sout * dout, self.device)
+        if op != OP_DCND:
+            check_values("mu_rhs", mu_rhs, n)
+        elif mu_rhs is None or len(mu_rhs) != 2 or n != 2:
+            raise ValueError("OP_DCND: two flavours and mu_rhs = (mubar, epsbar)")
+        _check(self.lib.tmamg_apply(self.h, int(op), int(level), _ptr(inp), _ptr(out), n, _dvec(mu_rhs)))
 
     def set_test_vectors(self, level, v):
+        if level == 0:
+            check_field("v", v, self.params.nv[0] * self.volume * 12, self.device)
+        else:
+            s1, d1 = self.level_info(1)
+            check_field("v", v, self.params.nv[1] * s1 * d1, self.device)
         _check(self.lib.tmamg_debug_set_test_vectors(self.h, int(level), _ptr(v)))
 
     def export(self, what, level, out):
+        if what == 0:
+            sf, df = self.level_info(level)
+            check_field("out", out, self.params.nv[level] * sf * df, self.device)
+        else:
+            sc, dc = self.level_info(level)
+            check_field("out", out, sc * 9 * dc * dc, self.device)
         _check(self.lib.tmamg_debug_export(self.h, int(what), int(level), _ptr(out)))
+
+    def inject_barrier_timeout(self):
+        """Failure-path hook: the next solve reports TMAMG_EHIP and the
+        context falls back to the generic coarse kernels."""
+        _check(self.lib.tmamg_debug_inject(self.h, 0))
 
     def time_kernel(self, kernel, nrhs=1, reps=20):
         ms = ctypes.c_double()

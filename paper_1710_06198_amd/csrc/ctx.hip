@@ -71,6 +71,13 @@ void Hier<T, S>::test_op(int op, int level, const void* in_, void* out_, int nrh
       need(level >= 1 && level == nlev - 1);
       coarse_solve(level, in, out, nrhs, mu);
       break;
+    case TMAMG_OP_DCND: {
+      need(level >= 1 && level < nlev && nrhs == 2);
+      const long n = level == 1 ? g1.V * d1 : g2.V * d2;
+      dc_apply(level, in, out, 2, mu);
+      launch_flavour_couple<T>(in, out, -nd_eps, n, st);
+      break;
+    }
     default:
       throw TmError{TMAMG_EINVAL, "unknown operator"};
   }
@@ -167,13 +174,22 @@ static void check(bool ok, const std::string& msg) {
 
 static bool even_or_one(int n) { return n == 1 || n % 2 == 0; }
 
-Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s) : lat(l), par(p), st(s) {
+Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s, const tmamg_allocator* a)
+    : lat(l), par(p), st(s) {
+  if (a) {
+    check(a->alloc != nullptr && a->free != nullptr, "an allocator needs both alloc and free");
+    dalloc.alloc = a->alloc;
+    dalloc.free = a->free;
+    dalloc.user = a->user;
+    dalloc.st = s;
+  }
   check(p.nlevels >= 0 && p.nlevels <= 3, "nlevels must be 0..3");
   check(p.restart >= 1 && p.restart <= 127, "restart must be 1..127");
   check(p.max_iter >= 1, "max_iter must be positive");
   check(p.mr_steps >= 0 && p.sap_sweeps[0] >= 0 && p.sap_sweeps[1] >= 0, "negative smoother counts");
   check(p.precision == TMAMG_FP64 || p.precision == TMAMG_MIXED, "precision");
   check(p.use_graph == 0 || p.use_graph == 1, "use_graph must be 0 or 1");
+  check(p.nd_coarse_coupling == 0 || p.nd_coarse_coupling == 1, "nd_coarse_coupling must be 0 or 1");
   if (p.precision == TMAMG_MIXED)
     check(p.storage == TMAMG_STORE_FP32 || p.storage == TMAMG_STORE_BF16 || p.storage == TMAMG_STORE_FP16,
           "mixed precision stores P and D_c in fp32, bf16 or fp16");
@@ -324,6 +340,19 @@ void Ctx::load_links(const cplx<double>* U) {
   have_links = true;
 }
 
+// Counters of work outside a solve (setup, operator hooks): dropped, but a
+// timed-out barrier wait still fails the call and retires the persistent
+// coarse kernels.
+HierBase::Counters Ctx::drain_counters() {
+  const HierBase::Counters k = hier->take_counters();
+  if (k.timeouts > 0) {
+    hier->disable_persistent();
+    throw TmError{TMAMG_EHIP, "a persistent coarse kernel's barrier wait timed out; the coarsest level uses the "
+                              "generic kernels from now on"};
+  }
+  return k;
+}
+
 void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
   check(kappa_ > 0 && std::isfinite(kappa_), "kappa must be positive");
   check(std::isfinite(csw_) && std::isfinite(mu_), "csw and mu must be finite");
@@ -340,7 +369,13 @@ void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
   hier->setup(mu);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  timer.report("setup", st, timer.on ? hier->stats_line() : std::string());
+  {
+    // the setup's own coarse iterations are not a solve's
+    const HierBase::Counters k = drain_counters();
+    if (timer.on)
+      timer.report("setup", st, " level1_iters=" + std::to_string(k.l2) + " coarsest_iters=" +
+                                  std::to_string(k.coarsest) + " coarsest_calls=" + std::to_string(k.coarsest_calls));
+  }
   have_setup = true;
   t_setup = std::chrono::duration<double>(clk::now() - t0).count();
 }
@@ -353,6 +388,7 @@ void Ctx::setup_update(const cplx<double>* U, int iters) {
   hier->rebuild();
   for (int i = 0; i < iters; ++i) hier->setup_iteration();
   HIPCHK(hipStreamSynchronize(st));
+  (void)drain_counters();
   t_setup = std::chrono::duration<double>(clk::now() - t0).count();
 }
 
@@ -412,7 +448,8 @@ void Ctx::upload_mu(int nrhs, const double* mu_host) {
 // coupling -epsbar; one Krylov space spans both flavours, and the
 // preconditioner is the multigrid cycle of each flavour's own D(+-mubar)
 // (the coupling is left to the flexible outer iteration).
-tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info, const double* eps_nd) {
+tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info, const double* eps_nd,
+                             bool guess) {
   const long n = 12 * fg.V;
   const bool nd = eps_nd != nullptr;
   const double eps = nd ? *eps_nd : 0.0;
@@ -424,8 +461,6 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     return h;
   };
   upload_mu(nrhs, mu_host);
-  launch_fill_zero(x64.p, (size_t)nrhs * n * sizeof(cplx<double>), st);
-  HIPCHK(hipMemcpyAsync(r64.p, b64.p, (size_t)nrhs * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   std::vector<double> bn = sys_norms(b64.p);
   for (double v : bn)
     if (!std::isfinite(v)) throw TmError{TMAMG_ENUMERIC, "right-hand side holds NaN/Inf"};
@@ -433,6 +468,25 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
   FineOp<double> o64 = op64();
   FineOp<float> o32 = mixed ? op32() : FineOp<float>{};
   const double* mu_d = mu_dev.p;
+  if (guess && !nd) {
+    // x64 holds the initial guess: r = b - D x0; a right-hand side whose
+    // guess is worse than zero starts from zero
+    launch_dslash<double>(o64, x64.p, t64.p, nrhs, mu_d, st);
+    launch_xmy<double>(b64.p, t64.p, (long)nrhs * n, st);
+    std::vector<double> rn0 = norms(t64.p, nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rn0[r])) throw TmError{TMAMG_ENUMERIC, "initial guess holds NaN/Inf"};
+      if (rn0[r] > bn[r]) {
+        launch_fill_zero(x64.p + (size_t)r * n, n * sizeof(cplx<double>), st);
+        HIPCHK(hipMemcpyAsync(t64.p + (size_t)r * n, b64.p + (size_t)r * n, n * sizeof(cplx<double>),
+                              hipMemcpyDeviceToDevice, st));
+      }
+    }
+    std::swap(r64.p, t64.p);
+  } else {
+    launch_fill_zero(x64.p, (size_t)nrhs * n * sizeof(cplx<double>), st);
+    HIPCHK(hipMemcpyAsync(r64.p, b64.p, (size_t)nrhs * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  }
   OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) {
     hipEvent_t e0 = timer.begin(st);
     launch_dslash<double>(o64, in, out, nrhs, mu_d, st);
@@ -449,6 +503,12 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
   OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, nrhs, mu_d); };
   Krylov<double>& k64 = nd ? KN64 : K64;
   Krylov<float>& k32 = nd ? KN32 : K32;
+  // the coarse levels of a doublet's cycle carry the flavour coupling
+  struct NdScope {
+    HierBase* h;
+    NdScope(HierBase* h_, double e) : h(h_) { h->nd_eps = e; }
+    ~NdScope() { h->nd_eps = 0.0; }
+  } nd_scope(hier.get(), (nd && par.nd_coarse_coupling) ? eps : 0.0);
   const bool use_m = par.nlevels >= 1;
   int iters = 0, cycles = 0;
   tmamg_status status = TMAMG_NOT_CONVERGED;
@@ -500,8 +560,29 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
   return status;
 }
 
+// End of a solve: the coarse-level counters go into info; a persistent
+// kernel's barrier wait that gave up turns the status into TMAMG_EHIP (the
+// FP64 residual in info still describes x) and retires those kernels for
+// the rest of the context.
+tmamg_status Ctx::finish(tmamg_info& loc, tmamg_status s) {
+  const HierBase::Counters k = hier->take_counters();
+  loc.l2_iters_total += k.l2;
+  loc.coarsest_iters_total += k.coarsest;
+  if (timer.on)
+    timer.report("solve", st, " level1_iters=" + std::to_string(k.l2) + " coarsest_iters=" +
+                                  std::to_string(k.coarsest) + " coarsest_calls=" + std::to_string(k.coarsest_calls) +
+                                  " coarsest_reorth=" + std::to_string(k.reorth));
+  if (k.timeouts > 0) {
+    hier->disable_persistent();
+    g_last_error = "a persistent coarse kernel's barrier wait timed out (" + std::to_string(k.timeouts) +
+                   "); the coarsest level uses the generic kernels from now on";
+    return TMAMG_EHIP;
+  }
+  return s;
+}
+
 tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
-                        tmamg_info* info) {
+                        tmamg_info* info, bool guess) {
   if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
   check(b && x && nrhs >= 1, "bad solve arguments");
   check(tol > 0 && tol < 1, "tol must be in (0, 1)");
@@ -509,10 +590,11 @@ tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const 
   ensure(nrhs);
   tmamg_info loc{};
   launch_spinor_to_internal<double>(fg, b, b64.p, nrhs, st);
-  tmamg_status s = solve_core(nrhs, mu_host, tol, &loc);
+  if (guess) launch_spinor_to_internal<double>(fg, x, x64.p, nrhs, st);
+  tmamg_status s = solve_core(nrhs, mu_host, tol, &loc, nullptr, guess);
   launch_spinor_to_canonical<double>(fg, x64.p, x, nrhs, st);
   HIPCHK(hipStreamSynchronize(st));
-  timer.report("solve", st, timer.on ? hier->stats_line() : std::string());
+  s = finish(loc, s);
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   loc.status = s;
@@ -520,6 +602,11 @@ tmamg_status Ctx::solve(const cplx<double>* b, cplx<double>* x, int nrhs, const 
   return s;
 }
 
+// (D D^dag + sigma) x = b as D(mu') w = b, then x = Gamma5 D(-mu')^-1 Gamma5 w
+// (mu' = sqrt(mu^2 + sigma)).  Each solve meets tol on its own system; the
+// residual of the product system can still exceed tol by up to
+// ||D|| / mu', so it is computed in FP64 and, while above tol, the pair of
+// solves is repeated on it and the correction added.
 tmamg_status Ctx::solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,
                                 tmamg_info* info) {
   if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
@@ -527,24 +614,55 @@ tmamg_status Ctx::solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs
   check(tol > 0 && tol < 1, "tol must be in (0, 1)");
   auto t0 = clk::now();
   ensure(nrhs);
+  const long n = 12 * fg.V;
+  const size_t cnt = (size_t)nrhs * n;
   std::vector<double> mup(nrhs), mum(nrhs);
   for (int r = 0; r < nrhs; ++r) {
     check(std::isfinite(sigma[r]) && sigma[r] >= 0, "sigma must be finite and >= 0");
     mup[r] = std::sqrt(mu * mu + sigma[r]);
     mum[r] = -mup[r];
   }
+  sh_b.alloc(std::max(sh_b.n, cnt));
+  sh_x.alloc(std::max(sh_x.n, cnt));
   tmamg_info loc{};
-  launch_spinor_to_internal<double>(fg, b, b64.p, nrhs, st);
-  tmamg_status s1 = solve_core(nrhs, mup.data(), tol, &loc);
-  // x = Gamma5 D(-mu')^-1 Gamma5 w
-  launch_gamma5_fine<double>(fg, x64.p, b64.p, nrhs, st);
-  tmamg_status s2 = solve_core(nrhs, mum.data(), tol, &loc);
-  launch_gamma5_fine<double>(fg, x64.p, t64.p, nrhs, st);
-  launch_spinor_to_canonical<double>(fg, t64.p, x, nrhs, st);
+  launch_spinor_to_internal<double>(fg, b, sh_b.p, nrhs, st);
+  std::vector<double> bn = norms(sh_b.p, nrhs);
+  launch_fill_zero(sh_x.p, cnt * sizeof(cplx<double>), st);
+  HIPCHK(hipMemcpyAsync(b64.p, sh_b.p, cnt * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  const FineOp<double> o64 = op64();
+  tmamg_status s = TMAMG_OK;
+  double worst = 0;
+  for (int pass = 0;; ++pass) {
+    // b64 holds the right-hand side of this pass (b, then the product residual)
+    tmamg_status s1 = solve_core(nrhs, mup.data(), tol, &loc);
+    launch_gamma5_fine<double>(fg, x64.p, b64.p, nrhs, st);
+    tmamg_status s2 = solve_core(nrhs, mum.data(), tol, &loc);
+    launch_gamma5_fine<double>(fg, x64.p, t64.p, nrhs, st);
+    launch_axpby<double>(t64.p, sh_x.p, 1.0, 1.0, (long)cnt, st);
+    if (s1 != TMAMG_OK || s2 != TMAMG_OK) s = TMAMG_NOT_CONVERGED;
+    // r = b - D(mu') Gamma5 D(-mu') Gamma5 x
+    upload_mu(nrhs, mum.data());
+    launch_gamma5_fine<double>(fg, sh_x.p, t64.p, nrhs, st);
+    launch_dslash<double>(o64, t64.p, r64.p, nrhs, mu_dev.p, st);
+    launch_gamma5_fine<double>(fg, r64.p, t64.p, nrhs, st);
+    upload_mu(nrhs, mup.data());
+    launch_dslash<double>(o64, t64.p, b64.p, nrhs, mu_dev.p, st);
+    launch_xmy<double>(sh_b.p, b64.p, (long)cnt, st);
+    std::vector<double> rn = norms(b64.p, nrhs);
+    worst = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rn[r])) throw TmError{TMAMG_ENUMERIC, "residual became NaN/Inf"};
+      worst = std::max(worst, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+    }
+    if (worst <= tol || s != TMAMG_OK || pass == 2) break;
+  }
+  if (worst > tol) s = TMAMG_NOT_CONVERGED;
+  launch_spinor_to_canonical<double>(fg, sh_x.p, x, nrhs, st);
   HIPCHK(hipStreamSynchronize(st));
+  s = finish(loc, s);
+  loc.true_rel_resid = worst;
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
-  tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
   loc.status = s;
   if (info) *info = loc;
   return s;
@@ -570,6 +688,7 @@ tmamg_status Ctx::solve_nd(const cplx<double>* b, cplx<double>* x, double mubar,
   tmamg_status s = solve_core(2, mus, tol, &loc, &epsbar);
   launch_spinor_to_canonical<double>(fg, x64.p, x, 2, st);
   HIPCHK(hipStreamSynchronize(st));
+  s = finish(loc, s);
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
   loc.status = s;
@@ -608,9 +727,10 @@ tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, dou
   launch_force(op64(), csw, X.p, Y.p, F, st);
   HIPCHK(hipStreamSynchronize(st));
   *S = sv[0];
+  tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
+  s = finish(loc, s);
   loc.t_setup_s = t_setup;
   loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
-  tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
   loc.status = s;
   if (info) *info = loc;
   return s;
@@ -644,6 +764,31 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
   ensure(nrhs);
   upload_mu(nrhs, mu_host);
   const long n0 = 12 * fg.V;
+  if (op == TMAMG_OP_DDAG64 || op == TMAMG_OP_DDAG32) {
+    // D(mu)^dag = Gamma5 D(-mu) Gamma5
+    check(level == 0, "D^dag acts on level 0");
+    std::vector<double> neg(nrhs);
+    for (int r = 0; r < nrhs; ++r) neg[r] = -(mu_host ? mu_host[r] : mu);
+    upload_mu(nrhs, neg.data());
+    launch_spinor_to_internal<double>(fg, in, b64.p, nrhs, st);
+    launch_gamma5_fine<double>(fg, b64.p, r64.p, nrhs, st);
+    if (op == TMAMG_OP_DDAG64) {
+      launch_dslash<double>(op64(), r64.p, t64.p, nrhs, mu_dev.p, st);
+    } else {
+      if (!links32.p) throw TmError{TMAMG_EINVAL, "FP32 operator needs mixed precision"};
+      DevArr<cplx<float>> a, b;
+      a.alloc((size_t)nrhs * n0);
+      b.alloc((size_t)nrhs * n0);
+      launch_convert<double, float>(r64.p, a.p, (long)nrhs * n0, st);
+      launch_dslash<float>(op32(), a.p, b.p, nrhs, mu_dev.p, st);
+      launch_convert<float, double>(b.p, t64.p, (long)nrhs * n0, st);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    launch_gamma5_fine<double>(fg, t64.p, b64.p, nrhs, st);
+    launch_spinor_to_canonical<double>(fg, b64.p, out, nrhs, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
   if (op == TMAMG_OP_D64 || op == TMAMG_OP_D32 || op == TMAMG_OP_SCHUR64 || op == TMAMG_OP_SCHUR32) {
     check(level == 0, "D acts on level 0");
     launch_spinor_to_internal<double>(fg, in, b64.p, nrhs, st);
@@ -676,6 +821,19 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
     return;
   }
   if (!have_setup) throw TmError{TMAMG_ESTATE, "hierarchy not set up"};
+  double dc_eps = 0.0;
+  if (op == TMAMG_OP_DCND) {
+    check(nrhs == 2 && mu_host != nullptr, "the doublet coarse operator takes two flavours and {mubar, epsbar}");
+    check(std::isfinite(mu_host[0]) && std::isfinite(mu_host[1]), "non-finite doublet masses");
+    const double m2[2] = {mu_host[0], -mu_host[0]};
+    upload_mu(2, m2);
+    dc_eps = mu_host[1];
+  }
+  struct EpsScope {
+    HierBase* h;
+    EpsScope(HierBase* h_, double e) : h(h_) { h->nd_eps = e; }
+    ~EpsScope() { h->nd_eps = 0.0; }
+  } eps_scope(hier.get(), dc_eps);
   long sites_in, sites_out;
   int dof_in, dof_out;
   int lin = level, lout = level;
@@ -705,6 +863,7 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
   if (lout == 0) launch_spinor_to_canonical<double>(fg, o64.p, out, nrhs, st);
   else HIPCHK(hipMemcpyAsync(out, o64.p, nout * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+  (void)drain_counters();
 }
 
 double Ctx::time_kernel(int kernel, int nrhs, int reps) {
@@ -780,7 +939,7 @@ void Hier<T, S>::autotune(int nrhs, int reps) {
     jobs.push_back({TUNE_SAP1, TMAMG_K_SAP1, d1, g1.V});
   }
   for (const Job& j : jobs) {
-    double ms[3] = {-1.0, -1.0, -1.0};
+    double ms[TUNE_MAX_VARIANTS] = {-1.0, -1.0, -1.0, -1.0};
     const int nvar = tune_variants(j.fam);
     int best = -1;
     for (int v = 0; v < nvar; ++v) {
@@ -820,6 +979,18 @@ static tmamg_status guarded(F&& f) {
 static Ctx* C(tmamg_ctx* c) { return reinterpret_cast<Ctx*>(c); }
 static const Ctx* C(const tmamg_ctx* c) { return reinterpret_cast<const Ctx*>(c); }
 
+// An entry point on a context: errors become statuses, and every device
+// buffer the call allocates comes from the context's allocator.
+template <typename F>
+static tmamg_status with_ctx(tmamg_ctx* ctx, F&& f) {
+  return guarded([&]() -> tmamg_status {
+    check(ctx != nullptr, "null context");
+    Ctx* c = C(ctx);
+    AllocScope scope(&c->dalloc);
+    return f(c);
+  });
+}
+
 extern "C" {
 
 tmamg_status tmamg_default_params(tmamg_params* p) {
@@ -844,81 +1015,92 @@ tmamg_status tmamg_default_params(tmamg_params* p) {
   p->storage = TMAMG_STORE_BF16;
   p->inner_tol = 1e-3;
   p->seed = 4001;
+  p->nd_coarse_coupling = 1;
   return TMAMG_OK;
 }
 
-tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream) {
+tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg_params* par, void* hip_stream,
+                          const tmamg_allocator* allocator) {
   return guarded([&]() {
     check(ctx && lat && par, "null argument");
     *ctx = nullptr;
-    Ctx* c = new Ctx(*lat, *par, reinterpret_cast<hipStream_t>(hip_stream));
+    Ctx* c = new Ctx(*lat, *par, reinterpret_cast<hipStream_t>(hip_stream), allocator);
     *ctx = reinterpret_cast<tmamg_ctx*>(c);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_setup(tmamg_ctx* ctx, const void* U, double kappa, double csw, double mu) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->setup(static_cast<const cplx<double>*>(U), kappa, csw, mu);
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->setup(static_cast<const cplx<double>*>(U), kappa, csw, mu);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_setup_update(tmamg_ctx* ctx, const void* U, int iters) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->setup_update(static_cast<const cplx<double>*>(U), iters);
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->setup_update(static_cast<const cplx<double>*>(U), iters);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_solve(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
                          tmamg_info* info) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    return C(ctx)->solve(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, mu_rhs, tol,
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, mu_rhs, tol,
                          info);
+  });
+}
+
+tmamg_status tmamg_solve_guess(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                               tmamg_info* info) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, mu_rhs, tol, info,
+                    true);
+  });
+}
+
+tmamg_status tmamg_debug_inject(tmamg_ctx* ctx, int what) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(what == 0, "what must be 0 (barrier timeout)");
+    if (!c->have_setup || c->par.nlevels < 2) throw TmError{TMAMG_ESTATE, "needs a multigrid setup"};
+    c->hier->flag_barrier_timeout();
+    return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
                                  tmamg_info* info) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    return C(ctx)->solve_shifted(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, sigma,
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve_shifted(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, sigma,
                                  tol, info);
   });
 }
 
 tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar, double epsbar, double tol,
                             tmamg_info* info) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    return C(ctx)->solve_nd(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), mubar, epsbar, tol,
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve_nd(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), mubar, epsbar, tol,
                             info);
   });
 }
 
 tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    return C(ctx)->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info);
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info);
   });
 }
 
 tmamg_status tmamg_force_link_gradient(tmamg_ctx* ctx, const void* F, void* G, double scale) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->force_link_gradient(static_cast<const cplx<double>*>(F), static_cast<cplx<double>*>(G), scale);
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->force_link_gradient(static_cast<const cplx<double>*>(F), static_cast<cplx<double>*>(G), scale);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->force_from_fields(static_cast<const cplx<double>*>(X), static_cast<const cplx<double>*>(Y),
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->force_from_fields(static_cast<const cplx<double>*>(X), static_cast<const cplx<double>*>(Y),
                               static_cast<cplx<double>*>(F));
     return TMAMG_OK;
   });
@@ -926,17 +1108,15 @@ tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* 
 
 tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
                          const double* mu_rhs) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->apply(op, level, static_cast<const cplx<double>*>(in), static_cast<cplx<double>*>(out), nrhs, mu_rhs);
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->apply(op, level, static_cast<const cplx<double>*>(in), static_cast<cplx<double>*>(out), nrhs, mu_rhs);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void* v) {
-  return guarded([&]() {
-    check(ctx != nullptr && v != nullptr, "null argument");
-    Ctx* c = C(ctx);
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(v != nullptr, "null argument");
     check(level == 0 || level == 1, "test vectors live on level 0 or 1");
     check(c->par.nlevels >= level + 2, "no such coarsening");
     if (level == 0) {
@@ -954,9 +1134,8 @@ tmamg_status tmamg_debug_set_test_vectors(tmamg_ctx* ctx, int level, const void*
 }
 
 tmamg_status tmamg_debug_export(tmamg_ctx* ctx, int what, int level, void* out) {
-  return guarded([&]() {
-    check(ctx != nullptr && out != nullptr, "null argument");
-    Ctx* c = C(ctx);
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(out != nullptr, "null argument");
     if (!c->have_setup) throw TmError{TMAMG_ESTATE, "export before setup"};
     if (what == 0) c->hier->export_P(level, static_cast<cplx<double>*>(out));
     else if (what == 1) c->hier->export_Dc(level, static_cast<cplx<double>*>(out));
@@ -985,17 +1164,16 @@ tmamg_status tmamg_level_info(const tmamg_ctx* ctx, int level, long* sites, int*
 }
 
 tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, double* avg_ms) {
-  return guarded([&]() {
-    check(ctx != nullptr && avg_ms != nullptr, "null argument");
-    *avg_ms = C(ctx)->time_kernel(kernel, nrhs, reps);
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(avg_ms != nullptr, "null argument");
+    *avg_ms = c->time_kernel(kernel, nrhs, reps);
     return TMAMG_OK;
   });
 }
 
 tmamg_status tmamg_autotune(tmamg_ctx* ctx, const int* nrhs_list, int n, int reps, const char* json_path) {
-  return guarded([&]() {
-    check(ctx != nullptr, "null context");
-    C(ctx)->autotune(nrhs_list, n, reps);
+  return with_ctx(ctx, [&](Ctx* c) {
+    c->autotune(nrhs_list, n, reps);
     if (json_path) {
       int dev = 0;
       hipDeviceProp_t prop;

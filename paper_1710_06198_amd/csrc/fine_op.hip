@@ -4,8 +4,7 @@
 // D(mu) psi(x) = A(x) psi(x) + i mu g5 psi(x)
 //   - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)]
 // (twisted-mass term of Sec. 1.1 on the clover-improved Wilson operator).
-#include "kernels.h"
-#include "su3.h"
+#include "fine_site.h"
 
 // ------------------------------------------------------------------ conversion
 __global__ void k_convert_links(FineGeom g, const cplx<double>* __restrict__ canon, cplx<double>* out64,
@@ -175,66 +174,6 @@ void launch_clover_build(const FineGeom& g, const cplx<double>* links64, const C
 
 
 // ------------------------------------------------------------------ stencil
-// Every access goes through a wave-uniform base (field + component * V) and
-// the lane's 32-bit site index.
-template <typename T>
-TM_D void load_spinor(const cplx<T>* __restrict__ f, unsigned s, long V, cplx<T>* p) {
-  const cplx<T>* q = f + tsite(s, 12);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) p[k] = q[k * FT];
-}
-
-// acc = (A + i mu g5) psi
-template <typename T, bool STREAM = false>
-TM_D void site_diag(const FineOp<T>& op, unsigned s, T mu, const cplx<T>* psi, cplx<T>* acc) {
-  const long V = op.g.V;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
-  clover_block_mv<T, STREAM>(op.clover, s, V, psi, acc);
-  clover_block_mv<T, STREAM>(op.clover + 36 * V, s, V, psi + 6, acc + 6);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    acc[k] += mu * times_i(psi[k]);
-    acc[6 + k] -= mu * times_i(psi[6 + k]);
-  }
-}
-
-template <int MU, typename T>
-TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
-                        cplx<T>* acc) {
-  const long V = op.g.V;
-  cplx<T> pn[12];
-  const unsigned sf = (unsigned)fine_neighbour(op.g, s, c, MU, +1);
-  load_spinor(in, sf, V, pn);
-  M3<T> u = load_link_u<MU>(op.links, s, V);
-  hop_fwd<MU>(u, pn, acc);
-  compiler_fence(acc);
-  const unsigned sb = (unsigned)fine_neighbour(op.g, s, c, MU, -1);
-  load_spinor(in, sb, V, pn);
-  M3<T> ub = load_link_u<MU>(op.links, sb, V);
-  hop_bwd<MU>(ub, pn, acc);
-}
-
-// (D(mu) in)(s) for one right-hand side
-template <typename T>
-TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc) {
-  int c[4];
-  fine_coords(op.g, s, c);
-  cplx<T> psi[12];
-  load_spinor(in, s, op.g.V, psi);
-  site_diag(op, s, mu, psi, acc);
-  // one direction at a time: without these compiler fences every
-  // neighbour's loads are hoisted to the top (> 256 live VGPRs, occupancy 1)
-  compiler_fence(acc);
-  site_hops_dir<0>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<1>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<2>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<3>(op, in, s, c, acc);
-}
-
 // One workgroup per block (one thread per site).  The block's spinors are
 // staged in LDS once; hops that stay in the block read them there.  The
 // backward hop is formed by its source: site y computes
@@ -450,142 +389,28 @@ template void launch_gamma5_fine<double>(const FineGeom&, const cplx<double>*, c
 template void launch_gamma5_fine<float>(const FineGeom&, const cplx<float>*, cplx<float>*, int, hipStream_t);
 
 // ------------------------------------------------------------------ SAP (K3)
-// One workgroup per SAP block (one thread per site).  For every block B of
-// the given colour: r_B = eta_B - (D z)_B, then mr_steps of minimal residual
-// on the block-restricted operator D_B (hops leaving B dropped) from e = 0,
-// then z_B += e.  Blocks of one colour only neighbour blocks of the other
-// colour, so blocks of one launch never read what another writes.
-template <int MU, typename T>
-TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, int loc, const int c[4], cplx<T>* acc) {
-  const FineGeom& g = op.g;
-  const int bv = g.bvol;
-  const int lc = c[MU] % g.B[MU];
-  const bool whole = g.NB[MU] == 1;    // block spans the periodic direction
-  cplx<T> pn[12];
-  // forward neighbour
-  int nl = -1;
-  if (lc < g.B[MU] - 1) nl = loc + g.lstride[MU];
-  else if (whole) nl = loc - (g.B[MU] - 1) * g.lstride[MU];
-  if (nl >= 0) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
-    M3<T> u = load_link_u<MU>(op.links, (unsigned)s, g.V);
-    hop_fwd<MU>(u, pn, acc);
-  }
-  compiler_fence(acc);
-  nl = -1;
-  if (lc > 0) nl = loc - g.lstride[MU];
-  else if (whole) nl = loc + (g.B[MU] - 1) * g.lstride[MU];
-  if (nl >= 0) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
-    const unsigned sb = (unsigned)(s - loc + nl);
-    M3<T> ub = load_link_u<MU>(op.links, sb, g.V);
-    hop_bwd<MU>(ub, pn, acc);
-  }
-}
-
-template <typename T>
-TM_D void block_reduce3(T& a, T& b, T& c, T* red) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  if (lane == 0) { red[w * 3] = a; red[w * 3 + 1] = b; red[w * 3 + 2] = c; }
-  __syncthreads();
-  a = 0; b = 0; c = 0;
-  for (int i = 0; i < nw; ++i) { a += red[i * 3]; b += red[i * 3 + 1]; c += red[i * 3 + 2]; }
-  __syncthreads();
-}
-
-// MINB: workgroups per CU the register allocation aims for (3 for
-// batches, where more resident blocks hide more of the L2 latency)
 template <typename T, int MINB>
 __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                                                   const double* __restrict__ mu_dev, const int* __restrict__ blist,
                                                   int nblk, int nrhs, int mr_steps) {
-  extern __shared__ unsigned char smem_raw[];
-  const FineGeom& g = op.g;
-  const long V = g.V;
-  const int bv = g.bvol;
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  // batches (MINB 3): the block solution e lives in LDS next to the MR
-  // vector, each thread touching only its own site (no barrier), which
-  // frees the 24 registers that otherwise spill at three workgroups per CU
-  constexpr bool ELDS = MINB == 3;
-  cplx<T>* el = lds + 12 * bv;
-  T* red = reinterpret_cast<T*>(lds + (ELDS ? 24 : 12) * bv);
-  // workgroup -> (block, rhs): the right-hand sides of one block run on one
-  // XCD one after the other, so its links and clover come from that L2
-  // after the first; with one right-hand side this is the identity
-  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
-  const int r = rest % nrhs, bi = (rest / nrhs) * 8 + x8;
-  if (bi >= nblk) return;
-  const T mu = (T)mu_dev[r];
-  const int loc = threadIdx.x;
-  const unsigned s = (unsigned)blist[bi] * bv + loc;
-  const cplx<T>* zr = z + (long)r * 12 * V;
-  int c[4];
-  fine_coords(g, s, c);
-  cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
-  {
-    cplx<T> dz[12];
-    site_dslash(op, zr, s, mu, dz);
-    const cplx<T>* er = eta + (long)r * 12 * V + tsite(s, 12);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      rho[k] = er[k * FT] - dz[k];
-      if constexpr (ELDS) el[k * bv + loc] = mk<T>(0, 0);
-      else e[k] = mk<T>(0, 0);
-    }
-  }
-  for (int it = 0; it < mr_steps; ++it) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) lds[k * bv + loc] = rho[k];
-    __syncthreads();
-    site_diag(op, s, mu, rho, q);
-    compiler_fence(q);
-    block_hops_dir<0>(op, lds, s, loc, c, q);
-    compiler_fence(q);
-    block_hops_dir<1>(op, lds, s, loc, c, q);
-    compiler_fence(q);
-    block_hops_dir<2>(op, lds, s, loc, c, q);
-    compiler_fence(q);
-    block_hops_dir<3>(op, lds, s, loc, c, q);
-    T qq = 0, qr_re = 0, qr_im = 0;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      qq += norm2(q[k]);
-      cplx<T> t = cmulc(q[k], rho[k]);
-      qr_re += t.re;
-      qr_im += t.im;
-    }
-    block_reduce3(qq, qr_re, qr_im, red);
-    cplx<T> alpha = qq > (T)0 ? mk(qr_re / qq, qr_im / qq) : mk<T>(0, 0);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      if constexpr (ELDS) {
-        cplx<T> ek = el[k * bv + loc];
-        cfma(ek, alpha, rho[k]);
-        el[k * bv + loc] = ek;
-      } else {
-        cfma(e[k], alpha, rho[k]);
-      }
-      rho[k] -= alpha * q[k];
-    }
-  }
-  cplx<T>* zo = z + (long)r * 12 * V + tsite(s, 12);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) zo[k * FT] += ELDS ? el[k * bv + loc] : e[k];
+  sap_block_solve<T, MINB, false>(op, eta, z, mu_dev, blist, nblk, nrhs, mr_steps);
 }
 
 template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
                      const int* block_list, int nblk, int mr_steps, hipStream_t st) {
-  const size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + 3 * 16 * sizeof(T);
+  const size_t red_bytes = 2 * 6 * 8 * sizeof(T);   // two slots of [waves <= 8][halves][3]
+  const size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + red_bytes;
   const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
   if constexpr (sizeof(T) == 4) {
     const int tv = tune_get(TUNE_SAP0, op.g.bvol, op.g.V, nrhs);
+    if (tv == 2 && op.g.bvol % 32 == 0) {
+      // two right-hand sides per workgroup, the MR vectors of both in LDS
+      const size_t sh2 = sh + (size_t)12 * op.g.bvol * sizeof(cplx<T>);
+      launch_sap_fine_pair(op, eta, z, nrhs, mu_dev, block_list, nblk, mr_steps, sh2, n8, st);
+      tune_used(TUNE_SAP0, 2);
+      return;
+    }
     if (tv >= 0 ? tv == 1 : nrhs > 1) {
       const size_t sh3 = sh + (size_t)12 * op.g.bvol * sizeof(cplx<T>);   // and e
       hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh3, st, op, eta, z, mu_dev,
@@ -595,8 +420,8 @@ void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nr
     }
   }
   tune_used(TUNE_SAP0, 0);
-  hipLaunchKernelGGL((k_sap_fine<T, 1>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev, block_list,
-                     nblk, nrhs, mr_steps);
+  hipLaunchKernelGGL((k_sap_fine<T, 1>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
+                     block_list, nblk, nrhs, mr_steps);
 }
 template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                       const int*, int, int, hipStream_t);

@@ -1,0 +1,240 @@
+// Per-site pieces of the fine operator and the SAP block solve, shared by
+// the translation units that instantiate the stencil and SAP kernels (the
+// two-right-hand-side SAP kernel is compiled on its own: in one unit with
+// the others the compiler's register allocation of those degraded).
+#pragma once
+
+#include "kernels.h"
+#include "su3.h"
+
+// ------------------------------------------------------------------ stencil
+// Every access goes through a wave-uniform base (field + component * V) and
+// the lane's 32-bit site index.
+template <typename T>
+TM_D void load_spinor(const cplx<T>* __restrict__ f, unsigned s, long V, cplx<T>* p) {
+  const cplx<T>* q = f + tsite(s, 12);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k] = q[k * FT];
+}
+
+// acc = (A + i mu g5) psi
+template <typename T, bool STREAM = false>
+TM_D void site_diag(const FineOp<T>& op, unsigned s, T mu, const cplx<T>* psi, cplx<T>* acc) {
+  const long V = op.g.V;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
+  clover_block_mv<T, STREAM>(op.clover, s, V, psi, acc);
+  clover_block_mv<T, STREAM>(op.clover + 36 * V, s, V, psi + 6, acc + 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    acc[k] += mu * times_i(psi[k]);
+    acc[6 + k] -= mu * times_i(psi[6 + k]);
+  }
+}
+
+template <int MU, typename T>
+TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
+                        cplx<T>* acc) {
+  const long V = op.g.V;
+  cplx<T> pn[12];
+  const unsigned sf = (unsigned)fine_neighbour(op.g, s, c, MU, +1);
+  load_spinor(in, sf, V, pn);
+  M3<T> u = load_link_u<MU>(op.links, s, V);
+  hop_fwd<MU>(u, pn, acc);
+  compiler_fence(acc);
+  const unsigned sb = (unsigned)fine_neighbour(op.g, s, c, MU, -1);
+  load_spinor(in, sb, V, pn);
+  M3<T> ub = load_link_u<MU>(op.links, sb, V);
+  hop_bwd<MU>(ub, pn, acc);
+}
+
+// (D(mu) in)(s) for one right-hand side
+template <typename T>
+TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc) {
+  int c[4];
+  fine_coords(op.g, s, c);
+  cplx<T> psi[12];
+  load_spinor(in, s, op.g.V, psi);
+  site_diag(op, s, mu, psi, acc);
+  // one direction at a time: without these compiler fences every
+  // neighbour's loads are hoisted to the top (> 256 live VGPRs, occupancy 1)
+  compiler_fence(acc);
+  site_hops_dir<0>(op, in, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<1>(op, in, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<2>(op, in, s, c, acc);
+  compiler_fence(acc);
+  site_hops_dir<3>(op, in, s, c, acc);
+}
+
+// ------------------------------------------------------------------ SAP (K3)
+// One workgroup per SAP block (one thread per site).  For every block B of
+// the given colour: r_B = eta_B - (D z)_B, then mr_steps of minimal residual
+// on the block-restricted operator D_B (hops leaving B dropped) from e = 0,
+// then z_B += e.  Blocks of one colour only neighbour blocks of the other
+// colour, so blocks of one launch never read what another writes.
+template <int MU, typename T>
+TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, int loc, const int c[4], cplx<T>* acc) {
+  const FineGeom& g = op.g;
+  const int bv = g.bvol;
+  const int lc = c[MU] % g.B[MU];
+  const bool whole = g.NB[MU] == 1;    // block spans the periodic direction
+  cplx<T> pn[12];
+  // forward neighbour
+  int nl = -1;
+  if (lc < g.B[MU] - 1) nl = loc + g.lstride[MU];
+  else if (whole) nl = loc - (g.B[MU] - 1) * g.lstride[MU];
+  if (nl >= 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
+    M3<T> u = load_link_u<MU>(op.links, (unsigned)s, g.V);
+    hop_fwd<MU>(u, pn, acc);
+  }
+  compiler_fence(acc);
+  nl = -1;
+  if (lc > 0) nl = loc - g.lstride[MU];
+  else if (whole) nl = loc + (g.B[MU] - 1) * g.lstride[MU];
+  if (nl >= 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pn[k] = lds[k * bv + nl];
+    const unsigned sb = (unsigned)(s - loc + nl);
+    M3<T> ub = load_link_u<MU>(op.links, sb, g.V);
+    hop_bwd<MU>(ub, pn, acc);
+  }
+}
+
+// Workgroup sums of three values, one barrier: the wave sums go to slot
+// `slot` of red (two slots of 3 x 4 values).  Alternate the slot between
+// calls: a slot is written again only two calls later, after every wave
+// has passed the barrier that follows its reads of it.
+template <typename T>
+TM_D void block_reduce3(T& a, T& b, T& c, T* red, int slot) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  T* r = red + slot * 12;
+  if (lane == 0) { r[w * 3] = a; r[w * 3 + 1] = b; r[w * 3 + 2] = c; }
+  __syncthreads();
+  a = 0; b = 0; c = 0;
+  for (int i = 0; i < nw; ++i) { a += r[i * 3]; b += r[i * 3 + 1]; c += r[i * 3 + 2]; }
+}
+
+// Sums of three values over each half-wave (lanes 0-31, 32-63), one barrier;
+// red holds two slots of [waves][2 halves][3] (see block_reduce3).
+template <typename T>
+TM_D void block_reduce3_halves(T& a, T& b, T& c, T* red, int slot) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, nw = blockDim.x >> 6;
+  T* r = red + slot * 6 * nw;
+  if ((lane & 31) == 0) { r[(w * 2 + half) * 3] = a; r[(w * 2 + half) * 3 + 1] = b; r[(w * 2 + half) * 3 + 2] = c; }
+  __syncthreads();
+  a = 0; b = 0; c = 0;
+  for (int i = 0; i < nw; ++i) {
+    a += r[(i * 2 + half) * 3];
+    b += r[(i * 2 + half) * 3 + 1];
+    c += r[(i * 2 + half) * 3 + 2];
+  }
+}
+
+// MINB: workgroups per CU the register allocation aims for (3 for
+// batches, where more resident blocks hide more of the L2 latency).
+// PAIR: two right-hand sides per workgroup, 2 x bvol threads: each wave
+// holds 32 sites (one layout tile) for both, lanes l and l + 32 on the
+// same site, so every link and clover load of the wave covers both
+// right-hand sides with the cache lines of one.
+template <typename T, int MINB, bool PAIR>
+TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, cplx<T>* z,
+                          const double* __restrict__ mu_dev, const int* __restrict__ blist, int nblk, int nrhs,
+                          int mr_steps) {
+  extern __shared__ unsigned char smem_raw[];
+  const FineGeom& g = op.g;
+  const long V = g.V;
+  const int bv = g.bvol;
+  // batches (MINB 3): the block solution e lives in LDS next to the MR
+  // vector, each thread touching only its own site (no barrier), which
+  // frees the 24 registers that otherwise spill at three workgroups per CU
+  constexpr bool ELDS = MINB == 3 && !PAIR;
+  const int half = PAIR ? (threadIdx.x >> 5) & 1 : 0;
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw) + half * 12 * bv;
+  cplx<T>* el = lds + 12 * bv;
+  T* red = reinterpret_cast<T*>(reinterpret_cast<cplx<T>*>(smem_raw) + (ELDS || PAIR ? 24 : 12) * bv);
+  // workgroup -> (block, rhs or pair): the right-hand sides of one block
+  // run on one XCD one after the other, so its links and clover come from
+  // that L2 after the first; with one right-hand side this is the identity
+  const int nunit = PAIR ? (nrhs + 1) / 2 : nrhs;
+  const int x8 = blockIdx.x & 7, rest = blockIdx.x >> 3;
+  const int ru = rest % nunit, bi = (rest / nunit) * 8 + x8;
+  if (bi >= nblk) return;
+  // a lone last right-hand side of a pair is computed by both halves and
+  // written by the first
+  const bool writes = !PAIR || 2 * ru + half < nrhs;
+  const int r = PAIR ? (writes ? 2 * ru + half : 2 * ru) : ru;
+  const T mu = (T)mu_dev[r];
+  const int loc = PAIR ? ((threadIdx.x >> 6) << 5) | (threadIdx.x & 31) : threadIdx.x;
+  const unsigned s = (unsigned)blist[bi] * bv + loc;
+  const cplx<T>* zr = z + (long)r * 12 * V;
+  int c[4];
+  fine_coords(g, s, c);
+  cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
+  {
+    cplx<T> dz[12];
+    site_dslash(op, zr, s, mu, dz);
+    const cplx<T>* er = eta + (long)r * 12 * V + tsite(s, 12);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      rho[k] = er[k * FT] - dz[k];
+      if constexpr (ELDS) el[k * bv + loc] = mk<T>(0, 0);
+      else e[k] = mk<T>(0, 0);
+    }
+  }
+  for (int it = 0; it < mr_steps; ++it) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lds[k * bv + loc] = rho[k];
+    __syncthreads();
+    site_diag(op, s, mu, rho, q);
+    compiler_fence(q);
+    block_hops_dir<0>(op, lds, s, loc, c, q);
+    compiler_fence(q);
+    block_hops_dir<1>(op, lds, s, loc, c, q);
+    compiler_fence(q);
+    block_hops_dir<2>(op, lds, s, loc, c, q);
+    compiler_fence(q);
+    block_hops_dir<3>(op, lds, s, loc, c, q);
+    T qq = 0, qr_re = 0, qr_im = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      qq += norm2(q[k]);
+      cplx<T> t = cmulc(q[k], rho[k]);
+      qr_re += t.re;
+      qr_im += t.im;
+    }
+    // the next step overwrites the staged rho only after this barrier,
+    // which every wave reaches after its last neighbour read
+    if constexpr (PAIR) block_reduce3_halves(qq, qr_re, qr_im, red, it & 1);
+    else block_reduce3(qq, qr_re, qr_im, red, it & 1);
+    cplx<T> alpha = qq > (T)0 ? mk(qr_re / qq, qr_im / qq) : mk<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      if constexpr (ELDS) {
+        cplx<T> ek = el[k * bv + loc];
+        cfma(ek, alpha, rho[k]);
+        el[k * bv + loc] = ek;
+      } else {
+        cfma(e[k], alpha, rho[k]);
+      }
+      rho[k] -= alpha * q[k];
+    }
+  }
+  if (!writes) return;
+  cplx<T>* zo = z + (long)r * 12 * V + tsite(s, 12);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) zo[k * FT] += ELDS ? el[k * bv + loc] : e[k];
+}
+

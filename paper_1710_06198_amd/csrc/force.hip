@@ -239,18 +239,22 @@ __global__ void k_force_links(FineOp<double> op, const cplx<double>* __restrict_
 void sigma_blocks(double re[6][2][2][2], double im[6][2][2][2]);
 
 void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, const cplx<double>* Y,
-                  cplx<double>* F_canon, hipStream_t st) {
+                  cplx<double>* F_canon, hipStream_t st, cplx<double>* xi_ws) {
   SigmaTab sg;
   sigma_blocks(sg.re, sg.im);
   DevArr<cplx<double>> Xi;
   const bool clover = csw != 0.0;
+  cplx<double>* xi = xi_ws;
   if (clover) {
-    Xi.alloc((size_t)6 * 9 * op.g.V);
+    if (!xi) {
+      Xi.alloc((size_t)6 * 9 * op.g.V);
+      xi = Xi.p;
+    }
     hipLaunchKernelGGL(k_force_xi, dim3((unsigned)((op.g.V + 127) / 128)), dim3(128), 0, st, op.g, sg, csw, X, Y,
-                       Xi.p);
+                       xi);
   }
   hipLaunchKernelGGL(k_force_links, dim3((unsigned)((op.g.V + 127) / 128), 4), dim3(128), 0, st, op, X, Y,
-                     clover ? Xi.p : nullptr, clover ? 1 : 0, F_canon);
+                     clover ? xi : nullptr, clover ? 1 : 0, F_canon);
   HIPCHK(hipStreamSynchronize(st));
 }
 

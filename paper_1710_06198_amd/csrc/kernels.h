@@ -53,6 +53,12 @@ template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
                      const int* block_list, int nblk, int mr_steps, hipStream_t st);
 
+// the same with two right-hand sides per workgroup (2 x bvol threads);
+// lds_bytes: both MR vectors and the reduction slots; n8: blocks rounded up to 8
+void launch_sap_fine_pair(const FineOp<float>& op, const cplx<float>* eta, cplx<float>* z, int nrhs,
+                          const double* mu_dev, const int* block_list, int nblk, int mr_steps, size_t lds_bytes,
+                          unsigned n8, hipStream_t st);
+
 // ---- BLAS-1 and Krylov scalars (K9, K10)
 struct Reducer {
   double* partial = nullptr;   // [nrhs][nvec][NB] complex as 2 doubles
@@ -209,12 +215,13 @@ void launch_store_from64(const cplx<double>* in, typename Store<S>::pair* out, l
 //   TUNE_SAP1         (d, coarse sites, nrhs): 0 vector ALU, 1 matrix cores,
 //                     2 matrix cores with a register budget for four workgroups per CU
 //   TUNE_RESTRICT0 / TUNE_PROLONG0 (nv, fine sites, nrhs): 0 vector ALU, 1 matrix cores
-//   TUNE_SAP0         (block sites, fine sites, nrhs): register budget for 0 one, 1 three workgroups per CU
+//   TUNE_SAP0         (block sites, fine sites, nrhs): register budget for 0 one, 1 three workgroups per CU;
+//                     2: two right-hand sides per workgroup (lane pairs share every link and clover load)
 // tune_get returns -1 without an entry; the launcher then applies its own
 // rule, and records the variant it ran with tune_used.
 enum { TUNE_COARSE_APPLY = 0, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0, TUNE_NFAM };
 constexpr int TUNE_MAX_VARIANTS = 4;
-inline int tune_variants(int family) { return family == TUNE_SAP1 ? 3 : 2; }
+inline int tune_variants(int family) { return family == TUNE_SAP1 || family == TUNE_SAP0 ? 3 : 2; }
 int tune_get(int family, long a, long b, long c);
 void tune_put(int family, long a, long b, long c, int variant, const double* ms, int nms);
 void tune_used(int family, int variant);

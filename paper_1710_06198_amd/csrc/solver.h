@@ -24,11 +24,30 @@ struct TmError {
 
 extern thread_local std::string g_last_error;
 
+// Where a context's device buffers come from: hipMalloc/hipFree, or the
+// pair of callbacks the caller installed at creation (for example a
+// framework's caching allocator).  g_alloc names the allocator of the API
+// call in progress on this thread (null outside calls: hipMalloc); every
+// buffer remembers the allocator that produced it and is released with it.
+struct DevAlloc {
+  tmamg_alloc_fn alloc = nullptr;
+  tmamg_free_fn free = nullptr;
+  void* user = nullptr;
+  hipStream_t st = nullptr;
+};
+extern thread_local const DevAlloc* g_alloc;
+struct AllocScope {
+  const DevAlloc* saved;
+  explicit AllocScope(const DevAlloc* a) : saved(g_alloc) { g_alloc = a; }
+  ~AllocScope() { g_alloc = saved; }
+};
+
 template <typename X>
 struct DevArr {
   X* p = nullptr;
   size_t n = 0;
   int count = 0;   // optional element count used by callers (e.g. block lists)
+  DevAlloc from{};
   DevArr() = default;
   DevArr(const DevArr&) = delete;
   DevArr& operator=(const DevArr&) = delete;
@@ -37,18 +56,33 @@ struct DevArr {
     if (cnt == n && p) return;
     release();
     if (cnt == 0) return;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), cnt * sizeof(X));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw TmError{TMAMG_ENOMEM, "hipMalloc of " + std::to_string(cnt * sizeof(X)) + " bytes failed"};
+    const size_t bytes = cnt * sizeof(X);
+    if (g_alloc && g_alloc->alloc) {
+      from = *g_alloc;
+      p = static_cast<X*>(from.alloc(bytes, from.st, from.user));
+      if (!p) {
+        from = DevAlloc{};
+        throw TmError{TMAMG_ENOMEM, "the caller's allocator refused " + std::to_string(bytes) + " bytes"};
+      }
+    } else {
+      from = DevAlloc{};
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        throw TmError{TMAMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+      }
     }
     n = cnt;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (from.free) from.free(p, from.st, from.user);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
+    from = DevAlloc{};
   }
   size_t bytes() const { return n * sizeof(X); }
 };
@@ -126,10 +160,21 @@ struct HierBase {
   virtual void export_Dc(int level, cplx<double>* out) = 0;
   virtual double time_kernel(int kernel, int nrhs, int reps) = 0;
   virtual void autotune(int nrhs, int reps) = 0;
-  // counters of the coarse solves since the last call, for the timing line
-  virtual std::string stats_line() { return ""; }
+  // counters of the coarse solves since the last call (and reset them)
+  struct Counters {
+    long l2 = 0, coarsest = 0;
+    int coarsest_calls = 0, reorth = 0, timeouts = 0;
+  };
+  virtual Counters take_counters() { return Counters{}; }
+  // persistent coarse kernels: mark a barrier timeout as if one had
+  // happened (failure-path tests), and stop using them after one
+  virtual void flag_barrier_timeout() {}
+  virtual void disable_persistent() {}
   long stats_l2 = 0, stats_coarsest = 0;
   PhaseTimer* timer = nullptr;
+  // non-zero while a doublet (two flavours as a pair of right-hand sides)
+  // is solved: the coarse operators carry the flavour coupling -epsbar
+  double nd_eps = 0.0;
 };
 
 template <typename T, typename S>
@@ -147,6 +192,7 @@ struct Hier : HierBase {
   DevArr<cplx<double>> P64;
   DevArr<cplx<T>> rc1, ec1, rc2, ec2;
   Krylov<T> K1, K2;
+  Krylov<T> KN1, KN2;   // doublet: one Krylov space over both flavours per coarse level
   DevArr<double> red_partial, red_out, red_inv, mu_setup;
   // fused coarse SAP: residual/product vectors and per-site partial sums,
   // two slots each; coarsest-GMRES scalars, flags and barrier counters
@@ -157,7 +203,7 @@ struct Hier : HierBase {
   bool use_coop = true;
   // captured intermediate-level solves (rc1 -> ec1), one per right-hand-side
   // count and twisted-mass array; `calls` counts eager uses before capture
-  struct GraphEntry { int nrhs; const double* mu; int calls; hipGraphExec_t exec; };
+  struct GraphEntry { int nrhs; const double* mu; int calls; hipGraphExec_t exec; long l2_steps, coarsest_steps; };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_st = nullptr;
   bool capturing = false;
@@ -168,12 +214,15 @@ struct Hier : HierBase {
   bool coarse_solve_graph(int nrhs, const double* mu);
   void build_colours(const int nb[4], DevArr<int> out[2]);
   void ensure(int nrhs) override;
-  std::string stats_line() override;
+  Counters take_counters() override;
+  void flag_barrier_timeout() override;
+  void disable_persistent() override { use_coop = false; drop_graphs(); }
   void dc_apply(int level, const cplx<T>* in, cplx<T>* out, int nrhs, const double* mu);
   void sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
   void sap_level1(const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu, int sweeps);
   void precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, const double* mu);
   void coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu);
+  void coarse_solve_nd(int level, const cplx<T>* rhs, cplx<T>* sol, const double* mu);
   void normalize(cplx<T>* v, long n, int nrhs);
   void build(int l);
   void build_inner(int l);
@@ -218,7 +267,11 @@ struct Ctx {
   double t_setup = 0;
   int cap = 0;
 
-  Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s);
+  DevAlloc dalloc{};   // where the context's device buffers come from
+  // shifted systems: the original right-hand sides, the accumulated solution
+  DevArr<cplx<double>> sh_b, sh_x;
+
+  Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s, const tmamg_allocator* a);
   ~Ctx();
   FineOp<double> op64() const { FineOp<double> o; o.g = fg; o.links = links64.p; o.clover = clov64.p; return o; }
   FineOp<float> op32() const { FineOp<float> o; o.g = fg; o.links = links32.p; o.clover = clov32.p; return o; }
@@ -228,11 +281,13 @@ struct Ctx {
   void ensure(int nrhs);
   std::vector<double> norms(const cplx<double>* v, int nrhs);
   tmamg_status solve_core(int nrhs, const double* mu_host, double tol, tmamg_info* info,
-                          const double* eps_nd = nullptr);
+                          const double* eps_nd = nullptr, bool guess = false);
+  tmamg_status finish(tmamg_info& loc, tmamg_status s);
+  HierBase::Counters drain_counters();
   tmamg_status solve_nd(const cplx<double>* b, cplx<double>* x, double mubar, double epsbar, double tol,
                         tmamg_info* info);
   tmamg_status solve(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
-                     tmamg_info* info);
+                     tmamg_info* info, bool guess = false);
   tmamg_status solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,
                              tmamg_info* info);
   tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info);
@@ -263,7 +318,9 @@ double time_launches(hipStream_t st, int reps, F&& f) {
 }
 
 // force kernels (K13-K15)
+// xi_ws: workspace of 54 complex doubles per site for the clover part, or
+// null (then it is allocated for the call)
 void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, const cplx<double>* Y,
-                  cplx<double>* F_canon, hipStream_t st);
+                  cplx<double>* F_canon, hipStream_t st, cplx<double>* xi_ws = nullptr);
 void launch_link_gradient(const FineOp<double>& op, int antiperiodic, const cplx<double>* F_canon,
                           cplx<double>* G_canon, double scale, hipStream_t st);

@@ -11,6 +11,7 @@
 #include <cstring>
 
 thread_local std::string g_last_error;
+thread_local const DevAlloc* g_alloc = nullptr;
 
 // ------------------------------------------------------------------ small kernels
 __global__ void k_rsqrt(const double* in, double* out, int n) {
@@ -204,9 +205,12 @@ template <typename T, typename S>
 bool Hier<T, S>::coarse_solve_graph(int nrhs, const double* mu) {
   size_t k = 0;
   while (k < graphs.size() && !(graphs[k].nrhs == nrhs && graphs[k].mu == mu)) ++k;
-  if (k == graphs.size()) graphs.push_back({nrhs, mu, 0, nullptr});
+  if (k == graphs.size()) graphs.push_back({nrhs, mu, 0, nullptr, 0, 0});
   if (!graphs[k].exec) {
     if (++graphs[k].calls < 2) return false;
+    // capture runs no kernels: the host-side step counts it adds are the
+    // counts of one replay
+    const long l2_0 = stats_l2, cs_0 = stats_coarsest;
     if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
     const hipStream_t saved = c->st;
     hipGraph_t gr = nullptr;
@@ -231,8 +235,14 @@ bool Hier<T, S>::coarse_solve_graph(int nrhs, const double* mu) {
     (void)hipGraphDestroy(gr);
     HIPCHK(e);
     graphs[k].exec = ex;
+    graphs[k].l2_steps = stats_l2 - l2_0;
+    graphs[k].coarsest_steps = stats_coarsest - cs_0;
+    stats_l2 = l2_0;
+    stats_coarsest = cs_0;
   }
   HIPCHK(hipGraphLaunch(graphs[k].exec, c->st));
+  stats_l2 += graphs[k].l2_steps;
+  stats_coarsest += graphs[k].coarsest_steps;
   return true;
 }
 
@@ -295,21 +305,38 @@ void Hier<T, S>::ensure(int nrhs) {
   }
 }
 
+// Counters since the last call: host-side step counts of the generic
+// Krylov cycles (and of graph replays) plus the persistent coarsest
+// kernels' device counters (iterations summed over right-hand sides,
+// launches, second Gram-Schmidt passes, barrier waits that gave up).
 template <typename T, typename S>
-std::string Hier<T, S>::stats_line() {
-  std::string out = " level1_iters=" + std::to_string(stats_l2) + " coarsest_iters(generic)=" +
-                    std::to_string(stats_coarsest);
+HierBase::Counters Hier<T, S>::take_counters() {
+  Counters k;
+  k.l2 = stats_l2;
+  k.coarsest = stats_coarsest;
   stats_l2 = stats_coarsest = 0;
   if (cg_iws.p) {
     int h[6] = {0, 0, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, cg_iws.p + 2, sizeof(h), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    HIPCHK(hipMemcpy(h, cg_iws.p + 2, sizeof(h), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemsetAsync(cg_iws.p + 2, 0, 3 * sizeof(int), c->st));
-    HIPCHK(hipMemsetAsync(cg_iws.p + 7, 0, sizeof(int), c->st));
-    out += " coarsest_calls=" + std::to_string(h[2]) + " coarsest_iters=" + std::to_string(h[1]) +
-           " coarsest_reorth=" + std::to_string(h[5]) + " barrier_flags=" + std::to_string(h[0]);
+    if (h[0] | h[1] | h[2] | h[5]) {
+      HIPCHK(hipMemsetAsync(cg_iws.p + 2, 0, 3 * sizeof(int), c->st));
+      HIPCHK(hipMemsetAsync(cg_iws.p + 7, 0, sizeof(int), c->st));
+    }
+    k.timeouts = h[0];
+    k.coarsest += h[1];
+    k.coarsest_calls = h[2];
+    k.reorth = h[5];
   }
-  return out;
+  return k;
+}
+
+template <typename T, typename S>
+void Hier<T, S>::flag_barrier_timeout() {
+  ensure(1);
+  const int one = 1;
+  HIPCHK(hipMemcpyAsync(cg_iws.p + 2, &one, sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
 }
 
 template <typename T, typename S>
@@ -385,9 +412,41 @@ void Hier<T, S>::precond(int level, const cplx<T>* v, cplx<T>* z, int nrhs, cons
   }
 }
 
+// Doublet (Sec. 1.1, Eq. (2)): with P_ND = P x I_2 and P^dag P = I the
+// coarse operator is D_ND,c = P_ND^dag D_ND P_ND = [[D_c(mubar), -epsbar],
+// [-epsbar, D_c(-mubar)]]: the two flavours' coarse fields (a pair of
+// right-hand sides) are solved as one system whose operator is the
+// flavour's own D_c plus -epsbar times the other flavour's field.
+template <typename T, typename S>
+void Hier<T, S>::coarse_solve_nd(int level, const cplx<T>* rhs, cplx<T>* sol, const double* mu) {
+  const tmamg_params& p = c->par;
+  hipStream_t st = c->st;
+  const long n = level == 1 ? g1.V * d1 : g2.V * d2;
+  const double eps = nd_eps;
+  const bool coarsest = level == nlev - 1;
+  Krylov<T>& K = level == 1 ? KN1 : KN2;
+  K.ensure(2 * n, coarsest ? p.coarsest_iters : p.l2_iters, 1, !coarsest, st);
+  launch_fill_zero(sol, (size_t)2 * n * sizeof(cplx<T>), st);
+  OpFn<T> A = [this, level, mu, n, eps](const cplx<T>* in, cplx<T>* out) {
+    dc_apply(level, in, out, 2, mu);
+    launch_flavour_couple<T>(in, out, -eps, n, c->st);
+  };
+  if (coarsest) {
+    stats_coarsest += krylov_cycle<T>(K, A, nullptr, rhs, sol, 1, p.coarsest_iters, p.coarsest_tol, nullptr, false,
+                                      nullptr, st);
+  } else {
+    OpFn<T> M = [this, mu](const cplx<T>* in, cplx<T>* out) { precond(1, in, out, 2, mu); };
+    stats_l2 += krylov_cycle<T>(K, A, &M, rhs, sol, 1, p.l2_iters, p.l2_tol, nullptr, false, nullptr, st);
+  }
+}
+
 template <typename T, typename S>
 void Hier<T, S>::coarse_solve(int level, const cplx<T>* rhs, cplx<T>* sol, int nrhs, const double* mu) {
   const tmamg_params& p = c->par;
+  if (nd_eps != 0.0 && nrhs == 2) {
+    coarse_solve_nd(level, rhs, sol, mu);
+    return;
+  }
   if (level == 1 && nlev >= 3 && p.use_graph && !capturing && !c->timer.on && rhs == rc1.p && sol == ec1.p &&
       coarse_solve_graph(nrhs, mu))
     return;

@@ -36,3 +36,12 @@ def field(x):
     """canonical spinor(s) [..., 4, 3] -> oracle field [..., 12] (cpu)."""
     t = torch.as_tensor(x).cpu()
     return t.reshape(*t.shape[:-2], 12)
+
+
+def maxabs_rel(a, b):
+    """Largest elementwise deviation relative to the largest entry of the
+    reference: catches a wrong value at a few sites that an l2 ratio over
+    the whole field would average away."""
+    a = torch.as_tensor(a).to(torch.complex128).cpu()
+    b = torch.as_tensor(b).to(torch.complex128).cpu()
+    return float((a - b).abs().max() / b.abs().max())

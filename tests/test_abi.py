@@ -30,6 +30,47 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(tmamg_[a-z_0-9]+)\s*\(", text)))
 
 
+def declarations_with_comments():
+    """(function name, the comment block that documents it): the nearest
+    block comment that starts a line above the declaration, skipping other
+    declarations of the same group and enum bodies."""
+    lines = open(HEADER).read().splitlines()
+    out = []
+    for i, ln in enumerate(lines):
+        m = re.match(r"^(?:const char\*|void|int|tmamg_status)\s+(tmamg_\w+)\s*\(", ln)
+        if not m:
+            continue
+        j = i - 1
+        while j >= 0:
+            t = lines[j].strip()
+            if t == "};":
+                while j >= 0 and not lines[j].startswith(("enum", "typedef")):
+                    j -= 1
+            elif t.endswith("*/") and t.startswith(("/*", "*")):
+                break
+            j -= 1
+        k = j
+        while k >= 0 and not lines[k].startswith("/*"):
+            k -= 1
+        out.append((m.group(1), "\n".join(lines[k:j + 1])))
+    return out
+
+
+def test_every_call_cites_its_passage_or_says_what_it_is():
+    """Each call's comment names the passage of the paper it implements
+    (Sec./Eq.) or says it is plumbing, measurement or a test hook."""
+    decl = declarations_with_comments()
+    assert {n for n, _ in decl} == set(declared_functions())
+    for name, comment in decl:
+        ok = re.search(r"Sec\. \d|Eq\. \(?\d", comment) or re.search(
+            r"plumbing|Plumbing|Measurement|measurement|Test hook|test hook", comment)
+        assert ok, (name, comment)
+    solve = dict(decl)
+    assert "Sec. 1.1, Eq. (1)" in solve["tmamg_solve"]
+    assert "Sec. 1.2" in solve["tmamg_force"]
+    assert "Sec. 2" in solve["tmamg_setup_update"]
+
+
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve", "tmamg_solve_shifted",
@@ -55,21 +96,26 @@ int main(void) {
   printf("tmamg_lattice size %zu\n", sizeof(tmamg_lattice));
   printf("tmamg_params size %zu\n", sizeof(tmamg_params));
   printf("tmamg_info size %zu\n", sizeof(tmamg_info));
+  printf("tmamg_allocator size %zu\n", sizeof(tmamg_allocator));
+  F(tmamg_allocator, alloc) F(tmamg_allocator, free) F(tmamg_allocator, user)
   F(tmamg_lattice, dims) F(tmamg_lattice, t_antiperiodic)
   F(tmamg_params, nlevels) F(tmamg_params, agg) F(tmamg_params, nv) F(tmamg_params, setup_iters)
   F(tmamg_params, init_smooth) F(tmamg_params, sap_block1) F(tmamg_params, sap_sweeps) F(tmamg_params, mr_steps)
   F(tmamg_params, l2_iters) F(tmamg_params, l2_tol) F(tmamg_params, coarsest_iters) F(tmamg_params, coarsest_tol)
   F(tmamg_params, restart) F(tmamg_params, max_iter) F(tmamg_params, precision) F(tmamg_params, storage)
   F(tmamg_params, inner_tol) F(tmamg_params, seed) F(tmamg_params, use_graph)
+  F(tmamg_params, nd_coarse_coupling)
   F(tmamg_info, status) F(tmamg_info, outer_iters) F(tmamg_info, cycles) F(tmamg_info, true_rel_resid)
-  F(tmamg_info, t_setup_s) F(tmamg_info, t_solve_s)
+  F(tmamg_info, t_setup_s) F(tmamg_info, t_solve_s) F(tmamg_info, l2_iters_total)
+  F(tmamg_info, coarsest_iters_total)
   printf("enum %d %d %d %d %d %d %d\n", TMAMG_OK, TMAMG_NOT_CONVERGED, TMAMG_EINVAL, TMAMG_ENOMEM, TMAMG_EHIP,
          TMAMG_ENUMERIC, TMAMG_ESTATE);
   printf("prec %d %d store %d %d %d %d\n", TMAMG_FP64, TMAMG_MIXED, TMAMG_STORE_FP64, TMAMG_STORE_FP32,
          TMAMG_STORE_BF16, TMAMG_STORE_FP16);
   printf("ops %d %d %d %d %d %d %d %d\n", TMAMG_OP_D64, TMAMG_OP_D32, TMAMG_OP_PROLONG, TMAMG_OP_RESTRICT,
          TMAMG_OP_DC, TMAMG_OP_SAP, TMAMG_OP_PREC, TMAMG_OP_COARSEST);
-  printf("eo %d %d\n", TMAMG_OP_SCHUR64, TMAMG_OP_SCHUR32);
+  printf("eo %d %d %d %d %d\n", TMAMG_OP_SCHUR64, TMAMG_OP_SCHUR32, TMAMG_OP_DDAG64, TMAMG_OP_DDAG32,
+         TMAMG_OP_DCND);
   printf("tune %d %d %d %d %d\n", TMAMG_TUNE_COARSE_APPLY, TMAMG_TUNE_SAP1, TMAMG_TUNE_RESTRICT0,
          TMAMG_TUNE_PROLONG0, TMAMG_TUNE_SAP0);
   return 0;
@@ -84,7 +130,8 @@ def test_struct_layout_matches_c_compiler(tm, tmp_path):
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines()
     b = tm.binding
-    classes = {"tmamg_lattice": b.Lattice, "tmamg_params": b.Params, "tmamg_info": b.Info}
+    classes = {"tmamg_lattice": b.Lattice, "tmamg_params": b.Params, "tmamg_info": b.Info,
+               "tmamg_allocator": b.Allocator}
     for ln in lines:
         parts = ln.split()
         if parts[0] in classes and parts[1] == "size":
@@ -100,7 +147,8 @@ def test_struct_layout_matches_c_compiler(tm, tmp_path):
             assert [int(v) for v in parts[1:]] == [b.OP_D64, b.OP_D32, b.OP_PROLONG, b.OP_RESTRICT, b.OP_DC,
                                                    b.OP_SAP, b.OP_PREC, b.OP_COARSEST]
         elif parts[0] == "eo":
-            assert [int(v) for v in parts[1:]] == [b.OP_SCHUR64, b.OP_SCHUR32]
+            assert [int(v) for v in parts[1:]] == [b.OP_SCHUR64, b.OP_SCHUR32, b.OP_DDAG64, b.OP_DDAG32,
+                                                   b.OP_DCND]
         elif parts[0] == "tune":
             assert [int(v) for v in parts[1:]] == [b.TUNE_COARSE_APPLY, b.TUNE_SAP1, b.TUNE_RESTRICT0,
                                                    b.TUNE_PROLONG0, b.TUNE_SAP0]
@@ -124,7 +172,7 @@ def _create(tm, dims, **kw):
     lat.t_antiperiodic = 1
     p = tm.default_params(**kw)
     h = ctypes.c_void_p()
-    st = b.load().tmamg_create(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(p), None)
+    st = b.load().tmamg_create(ctypes.byref(h), ctypes.byref(lat), ctypes.byref(p), None, None)
     msg = b.load().tmamg_last_error()
     return st, h, msg.decode() if isinstance(msg, bytes) else str(msg)
 
@@ -147,7 +195,7 @@ def test_create_rejects_bad_parameters(tm, dims, kw, needle):
 
 def test_null_arguments(tm):
     lib = tm.binding.load()
-    assert lib.tmamg_create(None, None, None, None) == -1
+    assert lib.tmamg_create(None, None, None, None, None) == -1
     assert lib.tmamg_default_params(None) == -1
     assert lib.tmamg_solve(None, None, None, 1, None, 1e-10, None) == -1
     lib.tmamg_destroy(None)   # no-op
@@ -263,3 +311,36 @@ def test_autograd_function_wiring(tm):
     s.setup(None, 0, 0, 0)   # links move before the gradient is taken
     with pytest.raises(RuntimeError, match="links changed"):
         S2.backward()
+
+
+def test_binding_rejects_mismatched_buffers(tm):
+    """The binding checks every buffer before the C ABI sees its pointer:
+    dtype, contiguity, element count and one twisted mass or shift per
+    right-hand side (a short list would be read past its end on the host)."""
+    import torch
+    b = tm.binding
+    s = b.Solver.__new__(b.Solver)   # no context: the checks come first
+    s.dims = (4, 4, 4, 4)
+    s.device = None
+    s.params = tm.default_params()
+    V = 256
+    good = torch.zeros((2, 4, 4, 4, 4, 4, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="complex128"):
+        s.solve(good.to(torch.complex64), good)
+    with pytest.raises(ValueError, match="elements"):
+        s.solve(good, torch.zeros((1, 4, 4, 4, 4, 4, 3), dtype=torch.complex128))
+    with pytest.raises(ValueError, match="contiguous"):
+        s.solve(good, good.transpose(-1, -2))
+    with pytest.raises(ValueError, match="one per right-hand side"):
+        s.solve(good, good.clone(), mu_rhs=[0.1])
+    with pytest.raises(ValueError, match="one per right-hand side"):
+        s.solve_shifted(good, good.clone(), [0.1, 0.2, 0.3])
+    with pytest.raises(ValueError, match="two flavours"):
+        s.solve_nd(good[:1], good[:1], 0.1, 0.05)
+    with pytest.raises(ValueError, match="elements"):
+        s.setup(torch.zeros((4, V, 9), dtype=torch.complex128)[:, :-1].contiguous(), 0.13, 1.0, 0.01)
+    with pytest.raises(ValueError, match="torch tensor"):
+        s.force(good[:1].numpy(), torch.zeros((4, V, 9), dtype=torch.complex128))
+    with pytest.raises(ValueError, match="must be on cuda"):
+        b.check_field("x", good, good.numel(), torch.device("cuda", 0))
+    b.check_field("x", good, good.numel(), None)   # a matching buffer passes
