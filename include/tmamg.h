@@ -187,6 +187,32 @@ tmamg_status tmamg_solve_guess(tmamg_ctx* ctx, const void* b, void* x, int nrhs,
 tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* sigma, double tol,
                                  tmamg_info* info);
 
+/* The even-odd reduced system D_hat(mu_r) x_r = b_r on the even sites
+ * (x + y + z + t even), D_hat = D_ee - D_eo D_oo^-1 D_oe: the operator the
+ * paper's simulations use (Sec. 1.2).  Solved through the full operator
+ * (D [x_e; x_o] = [b_e; 0] gives D_hat x_e = b_e) with the FP64 residual of
+ * the reduced system checked by the Schur operator and corrected while
+ * above tol.  b, x: device canonical spinors [nrhs]; odd entries of b are
+ * ignored, odd entries of x are set to 0; mu_rhs as for tmamg_solve;
+ * info.true_rel_resid is the reduced system's ||b_e - D_hat x_e|| / ||b_e||.
+ * Assumes the site-diagonal term's Hermitian part is positive definite (as
+ * TMAMG_OP_SCHUR64). */
+tmamg_status tmamg_solve_eo(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                            tmamg_info* info);
+
+/* Shifted systems of one source, (D D^dag + sigma_k) x_k = b for k < nshift,
+ * with the first-order initial guesses of Sec. 3, Eq. (6): the shifted
+ * inverse expanded in the shift, (Q +- i delta)^-1 ~ Q^-1 -+ i delta Q^-2,
+ * with Q = Gamma5 D(0) + i mu_b around the smallest shift's twisted mass
+ * mu_b = sqrt(mu^2 + sigma_min), applied to both solves of each shift (the
+ * base shift takes four solves, the others start from the guesses; a guess
+ * worse than zero is dropped).  Each shifted system's own FP64 residual is
+ * then corrected as in tmamg_solve_shifted.  b: device canonical spinor [1];
+ * x: device canonical [nshift]; sigma: host [nshift], >= 0.  The guess pays
+ * when the shifts are close (delta small against the low modes). */
+tmamg_status tmamg_solve_multishift(tmamg_ctx* ctx, const void* b, void* x, int nshift, const double* sigma,
+                                    double tol, tmamg_info* info);
+
 /* Non-degenerate doublet (Sec. 1.1, Eq. 2): solve
  *   D_ND(mubar, epsbar) x = b,  D_ND = [[D(mubar), -epsbar], [-epsbar, D(-mubar)]]
  * with the hierarchy built at setup (P_ND = P x I_2: each flavour's
@@ -206,6 +232,25 @@ tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar
  * then the adjoint of the hopping and clover terms on (X, Y).
  * phi: device spinor [1]; F: device [4][T][Z][Y][X][3][3]; S: host. */
 tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info);
+
+/* tmamg_force at twisted mass mu instead of the setup's (the hierarchy
+ * serves every mu, Sec. 1.1): the monomials of Sec. 2, Eq. (3), each at
+ * its own shifted mass. */
+tmamg_status tmamg_force_at(tmamg_ctx* ctx, const void* phi, double mu, void* F, double* S, double tol,
+                            tmamg_info* info);
+
+/* Molecular dynamics of the HMC of Sec. 2 (the nested integrator's
+ * updates; the gauge action on its innermost time scale).  Canonical
+ * complex128 fields [4][T][Z][Y][X][3][3] on the device; the gauge field is
+ * periodic.  gauge_force: S = beta sum_{x, mu<nu} (1 - Re tr P_{mu nu}(x)/3)
+ * (host) and its force F = sum_a (dS/dw^a) T^a for U -> exp(w) U (the
+ * convention of tmamg_force).  md_update_links: U <- exp(eps P) U per link
+ * (P traceless anti-Hermitian).  md_update_momenta: P <- P + coef F.
+ * md_kinetic: K = sum |P_ij|^2 = 1/2 sum_a (p^a)^2 (host). */
+tmamg_status tmamg_gauge_force(tmamg_ctx* ctx, const void* U, double beta, void* F, double* S);
+tmamg_status tmamg_md_update_links(tmamg_ctx* ctx, void* U, const void* P, double eps);
+tmamg_status tmamg_md_update_momenta(tmamg_ctx* ctx, void* P, const void* F, double coef);
+tmamg_status tmamg_md_kinetic(tmamg_ctx* ctx, const void* P, double* K);
 
 /* The force of tmamg_force (Sec. 1.2) for given X = (D D^dag)^-1 phi and
  * Y = D^dag X (device canonical spinors), without solves: F from the
@@ -246,9 +291,13 @@ enum {
   TMAMG_OP_SCHUR32 = 9,   /* the same in FP32 (rounded in/out) */
   TMAMG_OP_DDAG64 = 10,   /* fine D(mu)^dag = Gamma5 D(-mu) Gamma5 in FP64 (Sec. 1.1) */
   TMAMG_OP_DDAG32 = 11,   /* the same in FP32 (rounded in/out) */
-  TMAMG_OP_DCND = 12      /* doublet coarse operator D_ND,c = P_ND^dag D_ND P_ND (Sec. 1.1,
+  TMAMG_OP_DCND = 12,     /* doublet coarse operator D_ND,c = P_ND^dag D_ND P_ND (Sec. 1.1,
                              Eq. (2), P_ND = P x I_2) on level 1 or 2: nrhs = 2 (the two
                              flavours' coarse fields), mu_rhs = {mubar, epsbar} (required) */
+  TMAMG_OP_SAPND = 13     /* the doublet's fine SAP (k sweeps from zero, level 0) on the
+                             coupled block operator D_ND restricted to the blocks: nrhs = 2,
+                             mu_rhs = {mubar, epsbar}.  Mixed precision couples the
+                             flavours in the block solves; FP64 smooths each flavour alone */
 };
 tmamg_status tmamg_apply(tmamg_ctx* ctx, int op, int level, const void* in, void* out, int nrhs,
                          const double* mu_rhs);

@@ -29,6 +29,7 @@ __all__ = [
     "random_gauge_transform",
     "md_step_links",
     "unit_links",
+    "su3_momenta",
 ]
 
 
@@ -156,3 +157,12 @@ def random_gauge_transform(dims, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     g = rng.standard_normal((lt, lz, ly, lx, 8))
     return su3_from_coeffs(g, scale)
+
+
+def su3_momenta(dims, seed: int) -> np.ndarray:
+    """Molecular-dynamics momenta P = sum_a p^a T^a, T^a = i lambda^a / 2,
+    p^a ~ N(0, 1) i.i.d. per link: complex128 [4][T][Z][Y][X][3][3]
+    (traceless anti-Hermitian; the density exp(-sum |P_ij|^2) of the
+    kinetic term K = sum_a (p^a)^2 / 2)."""
+    c = su3_algebra_coeffs(dims, seed)
+    return np.einsum("...a,aij->...ij", c, 0.5j * gell_mann())

@@ -87,3 +87,46 @@ def coarse_nd_apply(op: WilsonClover, P, mubar: float, epsbar: float, e: torch.T
     w = torch.stack([P.prolong(e[0]), P.prolong(e[1])])
     y = nd.apply(w)
     return torch.stack([P.restrict(y[0]), P.restrict(y[1])])
+
+
+def sap_doublet(nd: NDOperator, eta: torch.Tensor, blk, sweeps: int, mr_steps: int, block_solver=None) -> torch.Tensor:
+    """k sweeps of SAP from zero for D_ND z = eta with the coupled block
+    operator: the blocks of one colour (Dirichlet restriction of D_ND, both
+    flavours of a block together) are solved by mr_steps of minimal
+    residual, one alpha per block from sums over both flavours' sites.
+    eta: [2, T, Z, Y, X, 12].  block_solver(r, mask) -> e replaces the MR
+    steps (the exact solves of the pins)."""
+    from .mg import block_colour, check_blocking, to_blocks
+    op = nd.op
+    check_blocking(op.dims, blk)
+    colour = block_colour(op.dims, blk)
+    bx, by, bz, bt = blk
+
+    def bsum(f):   # per-block sums over sites and both flavours
+        return to_blocks(f, blk, False).sum(-1).sum(0)
+
+    def expand(a):
+        a = a.repeat_interleave(bt, dim=-4).repeat_interleave(bz, dim=-3)
+        return a.repeat_interleave(by, dim=-2).repeat_interleave(bx, dim=-1)[..., None]
+
+    z = torch.zeros_like(eta)
+    for _ in range(sweeps):
+        for c in (0, 1):
+            mask = (colour == c).to(torch.float64)[..., None]
+            r = mask * (eta - nd.apply(z))
+            if block_solver is not None:
+                z = z + block_solver(r, mask)
+                continue
+            e = torch.zeros_like(r)
+            rho = r.clone()
+            for _ in range(mr_steps):
+                q = mask * nd.apply(mask * rho)
+                qq = bsum((q.conj() * q).real)
+                qr = bsum(q.conj() * rho)
+                alpha = torch.where(qq > 0, qr / torch.where(qq > 0, qq, torch.ones_like(qq)),
+                                    torch.zeros_like(qr))
+                a = expand(alpha)
+                e = e + a * rho
+                rho = rho - a * q
+            z = z + e
+    return z

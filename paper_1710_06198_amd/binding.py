@@ -19,7 +19,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENUMERIC, ESTATE = 0, 1, -1, -2, -3, -4
 FP64, MIXED = 0, 1
 STORE_FP64, STORE_FP32, STORE_BF16, STORE_FP16 = 0, 1, 2, 3
 (OP_D64, OP_D32, OP_PROLONG, OP_RESTRICT, OP_DC, OP_SAP, OP_PREC, OP_COARSEST, OP_SCHUR64, OP_SCHUR32, OP_DDAG64,
- OP_DDAG32, OP_DCND) = range(13)
+ OP_DDAG32, OP_DCND, OP_SAPND) = range(14)
 
 EXPORTS = [
     "tmamg_default_params", "tmamg_create", "tmamg_setup", "tmamg_setup_update", "tmamg_solve",
@@ -27,7 +27,8 @@ EXPORTS = [
     "tmamg_debug_set_test_vectors", "tmamg_debug_export", "tmamg_level_info", "tmamg_destroy",
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
     "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
-    "tmamg_solve_nd", "tmamg_solve_guess", "tmamg_debug_inject",
+    "tmamg_solve_nd", "tmamg_solve_guess", "tmamg_debug_inject", "tmamg_solve_multishift", "tmamg_force_at",
+    "tmamg_gauge_force", "tmamg_md_update_links", "tmamg_md_update_momenta", "tmamg_md_kinetic", "tmamg_solve_eo",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY, K_SCHUR32 = range(10)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
@@ -106,8 +107,15 @@ def load(path: str = LIB_PATH):
     lib.tmamg_solve.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_solve_guess.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_solve_shifted.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
+    lib.tmamg_solve_multishift.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
+    lib.tmamg_solve_eo.argtypes = [vp, vp, vp, i, P(d), d, P(Info)]
     lib.tmamg_debug_inject.argtypes = [vp, i]
     lib.tmamg_force.argtypes = [vp, vp, vp, P(d), d, P(Info)]
+    lib.tmamg_force_at.argtypes = [vp, vp, d, vp, P(d), d, P(Info)]
+    lib.tmamg_gauge_force.argtypes = [vp, vp, d, vp, P(d)]
+    lib.tmamg_md_update_links.argtypes = [vp, vp, vp, d]
+    lib.tmamg_md_update_momenta.argtypes = [vp, vp, vp, d]
+    lib.tmamg_md_kinetic.argtypes = [vp, vp, P(d)]
     lib.tmamg_solve_nd.argtypes = [vp, vp, vp, d, d, d, P(Info)]
     lib.tmamg_force_from_fields.argtypes = [vp, vp, vp, vp]
     lib.tmamg_force_link_gradient.argtypes = [vp, vp, vp, d]
@@ -325,6 +333,17 @@ class Solver:
         _check(st)
         return info
 
+    def solve_eo(self, b, x, mu_rhs=None, tol=1e-10):
+        """Even-odd reduced D_hat x_e = b_e (even sites; odd entries of b
+        ignored, odd entries of x set to 0)."""
+        n = self._spinors("b", b)
+        self._spinors("x", x, n)
+        check_values("mu_rhs", mu_rhs, n)
+        info = Info()
+        st = self.lib.tmamg_solve_eo(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol), ctypes.byref(info))
+        _check(st)
+        return info
+
     def solve_shifted(self, b, x, sigma, tol=1e-10):
         n = self._spinors("b", b)
         self._spinors("x", x, n)
@@ -333,6 +352,20 @@ class Solver:
         check_values("sigma", sigma, n)
         info = Info()
         st = self.lib.tmamg_solve_shifted(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol), ctypes.byref(info))
+        _check(st)
+        return info
+
+    def solve_multishift(self, b, x, sigma, tol=1e-10):
+        """(D D^dag + sigma_k) x_k = b for one source b [1] and x [len(sigma)],
+        with first-order initial guesses around the smallest shift (Sec. 3)."""
+        self._spinors("b", b, 1)
+        n = self._spinors("x", x)
+        if sigma is None:
+            raise ValueError("sigma: one shift per solution is required")
+        check_values("sigma", sigma, n)
+        info = Info()
+        st = self.lib.tmamg_solve_multishift(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol),
+                                             ctypes.byref(info))
         _check(st)
         return info
 
@@ -356,6 +389,40 @@ class Solver:
         _check(self.lib.tmamg_force(self.h, _ptr(phi), _ptr(F), ctypes.byref(S), float(tol), ctypes.byref(info)))
         return S.value, info
 
+    def force_at(self, phi, mu, F, tol=1e-12):
+        """tmamg_force at twisted mass mu: S_f = phi^dag (D(mu) D(mu)^dag)^-1 phi and its force."""
+        self._spinors("phi", phi, 1)
+        self._links("F", F)
+        info = Info()
+        S = ctypes.c_double()
+        _check(self.lib.tmamg_force_at(self.h, _ptr(phi), float(mu), _ptr(F), ctypes.byref(S), float(tol),
+                                       ctypes.byref(info)))
+        return S.value, info
+
+    def gauge_force(self, U, beta, F):
+        """Wilson plaquette action S_g (returned) and its force into F."""
+        self._links("U", U)
+        self._links("F", F)
+        S = ctypes.c_double()
+        _check(self.lib.tmamg_gauge_force(self.h, _ptr(U), float(beta), _ptr(F), ctypes.byref(S)))
+        return S.value
+
+    def md_update_links(self, U, P, eps):
+        self._links("U", U)
+        self._links("P", P)
+        _check(self.lib.tmamg_md_update_links(self.h, _ptr(U), _ptr(P), float(eps)))
+
+    def md_update_momenta(self, P, F, coef):
+        self._links("P", P)
+        self._links("F", F)
+        _check(self.lib.tmamg_md_update_momenta(self.h, _ptr(P), _ptr(F), float(coef)))
+
+    def md_kinetic(self, P):
+        self._links("P", P)
+        K = ctypes.c_double()
+        _check(self.lib.tmamg_md_kinetic(self.h, _ptr(P), ctypes.byref(K)))
+        return K.value
+
     def force_from_fields(self, X, Y, F):
         self._spinors("X", X, 1)
         self._spinors("Y", Y, 1)
@@ -378,10 +445,10 @@ class Solver:
         sout, dout = self.level_info(lout)
         check_field("in", inp, n * sin * din, self.device)
         check_field("out", out, n * sout * dout, self.device)
-        if op != OP_DCND:
+        if op not in (OP_DCND, OP_SAPND):
             check_values("mu_rhs", mu_rhs, n)
         elif mu_rhs is None or len(mu_rhs) != 2 or n != 2:
-            raise ValueError("OP_DCND: two flavours and mu_rhs = (mubar, epsbar)")
+            raise ValueError("doublet operators: two flavours and mu_rhs = (mubar, epsbar)")
         _check(self.lib.tmamg_apply(self.h, int(op), int(level), _ptr(inp), _ptr(out), n, _dvec(mu_rhs)))
 
     def set_test_vectors(self, level, v):

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtmamg.so")
 SOURCES = ["fine_op.hip", "sap_pair.hip", "fine_mg.hip", "coarse.hip", "coop.hip", "blas.hip", "solver.hip", "ctx.hip",
-           "force.hip", "tune.hip"]
+           "force.hip", "tune.hip", "md.hip"]
 ARCH = os.environ.get("TMAMG_ARCH", "gfx950")
 
 FLAGS = [

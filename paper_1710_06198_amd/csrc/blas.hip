@@ -216,6 +216,20 @@ void launch_flavour_couple(const cplx<T>* x, cplx<T>* y, double a, long n, hipSt
   hipLaunchKernelGGL(k_flavour_couple<T>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st, x, y, a, n);
 }
 
+// out = a + c b for complex fields of n elements, c complex (host scalar)
+__global__ void k_lincomb(const cplx<double>* __restrict__ a, const cplx<double>* __restrict__ b,
+                          cplx<double>* __restrict__ out, double cre, double cim, long n) {
+  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  cplx<double> v = a[k];
+  cfma(v, mk(cre, cim), b[k]);
+  out[k] = v;
+}
+void launch_lincomb(const cplx<double>* a, const cplx<double>* b, cplx<double>* out, double cre, double cim, long n,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, out, cre, cim, n);
+}
+
 // plain streaming copy (16-byte accesses); the reference kernel of known
 // traffic for counter calibration
 __global__ void k_copy16(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {

@@ -71,6 +71,12 @@ void Hier<T, S>::test_op(int op, int level, const void* in_, void* out_, int nrh
       need(level >= 1 && level == nlev - 1);
       coarse_solve(level, in, out, nrhs, mu);
       break;
+    case TMAMG_OP_SAPND: {
+      need(level == 0 && nrhs == 2);
+      launch_fill_zero(out, (size_t)2 * 12 * c->fg.V * sizeof(cplx<T>), st);
+      sap(0, in, out, 2, mu, p.sap_sweeps[0]);
+      break;
+    }
     case TMAMG_OP_DCND: {
       need(level >= 1 && level < nlev && nrhs == 2);
       const long n = level == 1 ? g1.V * d1 : g2.V * d2;
@@ -668,6 +674,202 @@ tmamg_status Ctx::solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs
   return s;
 }
 
+std::vector<double> Ctx::shifted_residual(const cplx<double>* b, const cplx<double>* x, cplx<double>* r, int nrhs,
+                                          const std::vector<double>& mup, const std::vector<double>& bn) {
+  const long n = 12 * fg.V;
+  std::vector<double> mum(nrhs);
+  for (int k = 0; k < nrhs; ++k) mum[k] = -mup[k];
+  const FineOp<double> o64 = op64();
+  // r = b - D(mu') Gamma5 D(-mu') Gamma5 x
+  upload_mu(nrhs, mum.data());
+  launch_gamma5_fine<double>(fg, x, t64.p, nrhs, st);
+  launch_dslash<double>(o64, t64.p, r64.p, nrhs, mu_dev.p, st);
+  launch_gamma5_fine<double>(fg, r64.p, t64.p, nrhs, st);
+  upload_mu(nrhs, mup.data());
+  launch_dslash<double>(o64, t64.p, r, nrhs, mu_dev.p, st);
+  launch_xmy<double>(b, r, (long)nrhs * n, st);
+  std::vector<double> rn = norms(r, nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    if (!std::isfinite(rn[k])) throw TmError{TMAMG_ENUMERIC, "residual became NaN/Inf"};
+    rn[k] = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+  }
+  return rn;
+}
+
+// Shifted systems (D D^dag + sigma_k) x_k = b of one source with a
+// first-order initial guess (Sec. 3, Eq. (6)).  With Q = Gamma5 D(0)
+// Hermitian, D D^dag + sigma = Gamma5 (Q + i mu')(Q - i mu') Gamma5, so the two
+// solves of a shift are w = (Q + i mu')^-1 Gamma5 b = D(mu')^-1 b and
+// u = (Q - i mu')^-1 w = D(-mu')^-1 Gamma5 w, x = Gamma5 u.  Around the base
+// shift (the smallest; A = Q + i mu_b, B = Q - i mu_b, delta = mu' - mu_b):
+//   w ~ w_b - i delta y_b,         y_b = A^-1 w_b = D(mu_b)^-1 Gamma5 w_b,
+//   u ~ u_b + i delta v_b,         v_b = B^-1 (u_b - y_b) = D(-mu_b)^-1 Gamma5 (u_b - y_b),
+// the expansion (Q +- i delta)^-1 ~ Q^-1 -+ i delta Q^-2 applied to each
+// factor.  The base shift costs four solves (w_b; y_b and u_b as one batch;
+// v_b), the others start their two batched solves from these guesses (a
+// right-hand side whose guess is worse than zero starts from zero).  The
+// shifted systems' own FP64 residuals are then corrected as in
+// solve_shifted.
+tmamg_status Ctx::solve_multishift(const cplx<double>* b, cplx<double>* x, int nshift, const double* sigma,
+                                   double tol, tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
+  check(b && x && sigma && nshift >= 1, "bad solve arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  auto t0 = clk::now();
+  ensure(std::max(nshift, 2));
+  const long n = 12 * fg.V;
+  int base = 0;
+  std::vector<double> mup(nshift);
+  for (int k = 0; k < nshift; ++k) {
+    check(std::isfinite(sigma[k]) && sigma[k] >= 0, "sigma must be finite and >= 0");
+    mup[k] = std::sqrt(mu * mu + sigma[k]);
+    if (sigma[k] < sigma[base]) base = k;
+  }
+  const double mb = mup[base];
+  const size_t cnt = (size_t)nshift * n, f = n * sizeof(cplx<double>);
+  sh_b.alloc(std::max(sh_b.n, cnt));
+  sh_x.alloc(std::max(sh_x.n, cnt));
+  ms_base.alloc(std::max(ms_base.n, (size_t)4 * n));
+  cplx<double>* W = ms_base.p;
+  cplx<double>* Y = W + n;
+  cplx<double>* U = W + 2 * n;
+  cplx<double>* Vb = W + 3 * n;
+  tmamg_info loc{};
+  tmamg_status s = TMAMG_OK;
+  auto fold = [&](tmamg_status st_) { if (st_ != TMAMG_OK) s = TMAMG_NOT_CONVERGED; };
+  // the source, in every shift's slot
+  launch_spinor_to_internal<double>(fg, b, sh_b.p, 1, st);
+  for (int k = 1; k < nshift; ++k) HIPCHK(hipMemcpyAsync(sh_b.p + k * n, sh_b.p, f, hipMemcpyDeviceToDevice, st));
+  const std::vector<double> bn(nshift, norms(sh_b.p, 1)[0]);
+  // base: w_b
+  HIPCHK(hipMemcpyAsync(b64.p, sh_b.p, f, hipMemcpyDeviceToDevice, st));
+  fold(solve_core(1, &mb, tol, &loc));
+  HIPCHK(hipMemcpyAsync(W, x64.p, f, hipMemcpyDeviceToDevice, st));
+  // y_b and u_b: one batch on Gamma5 w_b with +mu_b and -mu_b
+  launch_gamma5_fine<double>(fg, W, b64.p, 1, st);
+  HIPCHK(hipMemcpyAsync(b64.p + n, b64.p, f, hipMemcpyDeviceToDevice, st));
+  const double pm[2] = {mb, -mb};
+  fold(solve_core(2, pm, tol, &loc));
+  HIPCHK(hipMemcpyAsync(Y, x64.p, f, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(U, x64.p + n, f, hipMemcpyDeviceToDevice, st));
+  launch_gamma5_fine<double>(fg, U, sh_x.p + base * n, 1, st);   // the base shift's solution
+  if (nshift > 1) {
+    // v_b
+    launch_lincomb(U, Y, t64.p, -1.0, 0.0, n, st);
+    launch_gamma5_fine<double>(fg, t64.p, b64.p, 1, st);
+    const double mm = -mb;
+    fold(solve_core(1, &mm, tol, &loc));
+    HIPCHK(hipMemcpyAsync(Vb, x64.p, f, hipMemcpyDeviceToDevice, st));
+    // the other shifts, batched: step 1 from w_b - i delta y_b
+    std::vector<int> idx;
+    std::vector<double> mk_, mkm;
+    for (int k = 0; k < nshift; ++k)
+      if (k != base) {
+        idx.push_back(k);
+        mk_.push_back(mup[k]);
+        mkm.push_back(-mup[k]);
+      }
+    const int m = (int)idx.size();
+    for (int j = 0; j < m; ++j) {
+      HIPCHK(hipMemcpyAsync(b64.p + j * n, sh_b.p, f, hipMemcpyDeviceToDevice, st));
+      launch_lincomb(W, Y, x64.p + j * n, 0.0, -(mk_[j] - mb), n, st);
+    }
+    fold(solve_core(m, mk_.data(), tol, &loc, nullptr, true));
+    // step 2 from u_b + i delta v_b
+    launch_gamma5_fine<double>(fg, x64.p, b64.p, m, st);
+    for (int j = 0; j < m; ++j) launch_lincomb(U, Vb, x64.p + j * n, 0.0, mk_[j] - mb, n, st);
+    fold(solve_core(m, mkm.data(), tol, &loc, nullptr, true));
+    for (int j = 0; j < m; ++j) launch_gamma5_fine<double>(fg, x64.p + j * n, sh_x.p + idx[j] * n, 1, st);
+  }
+  // the shifted systems' own residuals; defect correction where above tol
+  double worst = 0;
+  for (int pass = 0;; ++pass) {
+    std::vector<double> rel = shifted_residual(sh_b.p, sh_x.p, b64.p, nshift, mup, bn);
+    worst = *std::max_element(rel.begin(), rel.end());
+    if (worst <= tol || s != TMAMG_OK || pass == 2) break;
+    std::vector<double> mm(nshift);
+    for (int k = 0; k < nshift; ++k) mm[k] = -mup[k];
+    fold(solve_core(nshift, mup.data(), tol, &loc));
+    launch_gamma5_fine<double>(fg, x64.p, b64.p, nshift, st);
+    fold(solve_core(nshift, mm.data(), tol, &loc));
+    launch_gamma5_fine<double>(fg, x64.p, t64.p, nshift, st);
+    launch_axpby<double>(t64.p, sh_x.p, 1.0, 1.0, (long)cnt, st);
+  }
+  if (worst > tol) s = TMAMG_NOT_CONVERGED;
+  launch_spinor_to_canonical<double>(fg, sh_x.p, x, nshift, st);
+  HIPCHK(hipStreamSynchronize(st));
+  s = finish(loc, s);
+  loc.true_rel_resid = worst;
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
+// The even-odd reduced system D_hat(mu) x_e = b_e (the operator the
+// paper's simulations work with, Sec. 1.2): with the odd right-hand side
+// zero, the full system D [x_e; x_o] = [b_e; 0] has x_o = -D_oo^-1 D_oe x_e
+// and hence D_hat x_e = b_e, so the multigrid solve of the full operator
+// solves it.  The reduced residual r_hat = b_e - D_hat x_e differs from the
+// full one (r_hat = r_e - D_eo D_oo^-1 r_o), so it is computed in FP64 with
+// the Schur operator and, while above tol, the full solve is repeated on it
+// (defect correction, at most three passes).
+tmamg_status Ctx::solve_eo(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
+                           tmamg_info* info) {
+  if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
+  check(b && x && nrhs >= 1, "bad solve arguments");
+  check(tol > 0 && tol < 1, "tol must be in (0, 1)");
+  auto t0 = clk::now();
+  ensure(nrhs);
+  const long n = 12 * fg.V;
+  const size_t cnt = (size_t)nrhs * n;
+  std::vector<double> m(nrhs, mu);
+  if (mu_host)
+    for (int r = 0; r < nrhs; ++r) {
+      check(std::isfinite(mu_host[r]), "non-finite twisted mass");
+      m[r] = mu_host[r];
+    }
+  sh_b.alloc(std::max(sh_b.n, cnt));
+  sh_x.alloc(std::max(sh_x.n, cnt));
+  tmamg_info loc{};
+  launch_spinor_to_internal<double>(fg, b, sh_b.p, nrhs, st);
+  launch_zero_parity<double>(fg, sh_b.p, nrhs, 1, st);
+  const std::vector<double> bn = norms(sh_b.p, nrhs);
+  launch_fill_zero(sh_x.p, cnt * sizeof(cplx<double>), st);
+  HIPCHK(hipMemcpyAsync(b64.p, sh_b.p, cnt * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  const FineOp<double> o64 = op64();
+  tmamg_status s = TMAMG_OK;
+  double worst = 0;
+  for (int pass = 0;; ++pass) {
+    // b64: the even right-hand side of this pass, odd sites zero
+    if (solve_core(nrhs, m.data(), 0.25 * tol, &loc) != TMAMG_OK) s = TMAMG_NOT_CONVERGED;
+    launch_zero_parity<double>(fg, x64.p, nrhs, 1, st);
+    launch_axpby<double>(x64.p, sh_x.p, 1.0, 1.0, (long)cnt, st);
+    // r_hat = b_e - D_hat x_e
+    upload_mu(nrhs, m.data());
+    launch_schur<double>(o64, sh_x.p, t64.p, b64.p, nrhs, mu_dev.p, st);
+    launch_xmy<double>(sh_b.p, b64.p, (long)cnt, st);
+    std::vector<double> rn = norms(b64.p, nrhs);
+    worst = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rn[r])) throw TmError{TMAMG_ENUMERIC, "residual became NaN/Inf"};
+      worst = std::max(worst, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+    }
+    if (worst <= tol || s != TMAMG_OK || pass == 2) break;
+  }
+  if (worst > tol) s = TMAMG_NOT_CONVERGED;
+  launch_spinor_to_canonical<double>(fg, sh_x.p, x, nrhs, st);
+  HIPCHK(hipStreamSynchronize(st));
+  s = finish(loc, s);
+  loc.true_rel_resid = worst;
+  loc.t_setup_s = t_setup;
+  loc.t_solve_s = std::chrono::duration<double>(clk::now() - t0).count();
+  loc.status = s;
+  if (info) *info = loc;
+  return s;
+}
+
 tmamg_status Ctx::solve_nd(const cplx<double>* b, cplx<double>* x, double mubar, double epsbar, double tol,
                            tmamg_info* info) {
   if (!have_setup) throw TmError{TMAMG_ESTATE, "solve before setup"};
@@ -696,7 +898,8 @@ tmamg_status Ctx::solve_nd(const cplx<double>* b, cplx<double>* x, double mubar,
   return s;
 }
 
-tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info) {
+tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info,
+                        const double* mu_force) {
   if (!have_setup) throw TmError{TMAMG_ESTATE, "force before setup"};
   check(phi && F && S, "bad force arguments");
   check(tol > 0 && tol < 1, "tol must be in (0, 1)");
@@ -711,7 +914,9 @@ tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, dou
   Y.alloc(n);
   X.alloc(n);
   HIPCHK(hipMemcpyAsync(phi64.p, b64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
-  double mp = mu, mm = -mu;
+  const double mf = mu_force ? *mu_force : mu;
+  check(std::isfinite(mf), "non-finite twisted mass");
+  double mp = mf, mm = -mf;
   tmamg_status s1 = solve_core(1, &mp, tol, &loc);
   HIPCHK(hipMemcpyAsync(Y.p, x64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   // X = Gamma5 D(-mu)^-1 Gamma5 Y
@@ -822,8 +1027,8 @@ void Ctx::apply(int op, int level, const cplx<double>* in, cplx<double>* out, in
   }
   if (!have_setup) throw TmError{TMAMG_ESTATE, "hierarchy not set up"};
   double dc_eps = 0.0;
-  if (op == TMAMG_OP_DCND) {
-    check(nrhs == 2 && mu_host != nullptr, "the doublet coarse operator takes two flavours and {mubar, epsbar}");
+  if (op == TMAMG_OP_DCND || op == TMAMG_OP_SAPND) {
+    check(nrhs == 2 && mu_host != nullptr, "the doublet operators take two flavours and {mubar, epsbar}");
     check(std::isfinite(mu_host[0]) && std::isfinite(mu_host[1]), "non-finite doublet masses");
     const double m2[2] = {mu_host[0], -mu_host[0]};
     upload_mu(2, m2);
@@ -1077,6 +1282,21 @@ tmamg_status tmamg_solve_shifted(tmamg_ctx* ctx, const void* b, void* x, int nrh
   });
 }
 
+tmamg_status tmamg_solve_eo(tmamg_ctx* ctx, const void* b, void* x, int nrhs, const double* mu_rhs, double tol,
+                            tmamg_info* info) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve_eo(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nrhs, mu_rhs, tol, info);
+  });
+}
+
+tmamg_status tmamg_solve_multishift(tmamg_ctx* ctx, const void* b, void* x, int nshift, const double* sigma,
+                                    double tol, tmamg_info* info) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->solve_multishift(static_cast<const cplx<double>*>(b), static_cast<cplx<double>*>(x), nshift, sigma,
+                               tol, info);
+  });
+}
+
 tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar, double epsbar, double tol,
                             tmamg_info* info) {
   return with_ctx(ctx, [&](Ctx* c) {
@@ -1088,6 +1308,48 @@ tmamg_status tmamg_solve_nd(tmamg_ctx* ctx, const void* b, void* x, double mubar
 tmamg_status tmamg_force(tmamg_ctx* ctx, const void* phi, void* F, double* S, double tol, tmamg_info* info) {
   return with_ctx(ctx, [&](Ctx* c) {
     return c->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info);
+  });
+}
+
+tmamg_status tmamg_force_at(tmamg_ctx* ctx, const void* phi, double mu, void* F, double* S, double tol,
+                            tmamg_info* info) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    return c->force(static_cast<const cplx<double>*>(phi), static_cast<cplx<double>*>(F), S, tol, info, &mu);
+  });
+}
+
+tmamg_status tmamg_gauge_force(tmamg_ctx* ctx, const void* U, double beta, void* F, double* S) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(U && F && S, "null argument");
+    check(std::isfinite(beta), "beta must be finite");
+    *S = md_gauge_force(c->lat, static_cast<const cplx<double>*>(U), beta, static_cast<cplx<double>*>(F), c->st);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_md_update_links(tmamg_ctx* ctx, void* U, const void* P, double eps) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(U && P, "null argument");
+    check(std::isfinite(eps), "eps must be finite");
+    md_update_links(c->lat, static_cast<cplx<double>*>(U), static_cast<const cplx<double>*>(P), eps, c->st);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_md_update_momenta(tmamg_ctx* ctx, void* P, const void* F, double coef) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(P && F, "null argument");
+    check(std::isfinite(coef), "coef must be finite");
+    md_update_momenta(c->lat, static_cast<cplx<double>*>(P), static_cast<const cplx<double>*>(F), coef, c->st);
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_md_kinetic(tmamg_ctx* ctx, const void* P, double* K) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    check(P && K, "null argument");
+    *K = md_kinetic(c->lat, static_cast<const cplx<double>*>(P), c->st);
+    return TMAMG_OK;
   });
 }
 

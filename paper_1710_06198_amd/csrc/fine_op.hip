@@ -398,16 +398,19 @@ __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx
 
 template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
-                     const int* block_list, int nblk, int mr_steps, hipStream_t st) {
+                     const int* block_list, int nblk, int mr_steps, hipStream_t st, double epsbar) {
   const size_t red_bytes = 2 * 6 * 8 * sizeof(T);   // two slots of [waves <= 8][halves][3]
   const size_t sh = (size_t)12 * op.g.bvol * sizeof(cplx<T>) + red_bytes;
   const unsigned n8 = (unsigned)((nblk + 7) / 8 * 8);
   if constexpr (sizeof(T) == 4) {
     const int tv = tune_get(TUNE_SAP0, op.g.bvol, op.g.V, nrhs);
-    if (tv == 2 && op.g.bvol % 32 == 0) {
+    const bool coupled = epsbar != 0.0 && nrhs == 2 && op.g.bvol % 32 == 0;
+    if (coupled || (tv == 2 && op.g.bvol % 32 == 0)) {
       // two right-hand sides per workgroup, the MR vectors of both in LDS
       const size_t sh2 = sh + (size_t)12 * op.g.bvol * sizeof(cplx<T>);
-      launch_sap_fine_pair(op, eta, z, nrhs, mu_dev, block_list, nblk, mr_steps, sh2, n8, st);
+      launch_sap_fine_pair(op, eta, z, nrhs, mu_dev, block_list, nblk, mr_steps, sh2, n8, st,
+                           coupled ? epsbar : 0.0);
+      if (coupled) return;
       tune_used(TUNE_SAP0, 2);
       return;
     }
@@ -424,11 +427,29 @@ void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nr
                      block_list, nblk, nrhs, mr_steps);
 }
 template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
-                                      const int*, int, int, hipStream_t);
+                                      const int*, int, int, hipStream_t, double);
 template void launch_sap_fine<float>(const FineOp<float>&, const cplx<float>*, cplx<float>*, int, const double*,
-                                     const int*, int, int, hipStream_t);
+                                     const int*, int, int, hipStream_t, double);
 
 // ------------------------------------------------------------------ even-odd reduction
+// v_r = 0 on the sites of parity `par` (x + y + z + t), per right-hand side
+template <typename T>
+__global__ void k_zero_parity(FineGeom g, cplx<T>* v, int par) {
+  const unsigned s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  fine_coords(g, s, c);
+  if (((c[0] + c[1] + c[2] + c[3]) & 1) != par) return;
+  cplx<T>* o = v + (long)blockIdx.y * 12 * g.V + tsite(s, 12);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[k * FT] = mk<T>(0, 0);
+}
+template <typename T>
+void launch_zero_parity(const FineGeom& g, cplx<T>* v, int nrhs, int parity, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_parity<T>, dim3((unsigned)((g.V + 255) / 256), nrhs), dim3(256), 0, st, g, v, parity);
+}
+template void launch_zero_parity<double>(const FineGeom&, cplx<double>*, int, int, hipStream_t);
+
 // D_hat(mu) = D_ee - D_eo D_oo^-1 D_oe on the even sites (x + y + z + t even):
 // the hopping term only joins opposite parities and A + i mu g5 is
 // site-diagonal.  Two gather passes over one parity each: on the odd sites

@@ -105,7 +105,7 @@ TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, in
 }
 
 // Workgroup sums of three values, one barrier: the wave sums go to slot
-// `slot` of red (two slots of 3 x 4 values).  Alternate the slot between
+// `slot` of red (two slots of 3 x 8 values).  Alternate the slot between
 // calls: a slot is written again only two calls later, after every wave
 // has passed the barrier that follows its reads of it.
 template <typename T>
@@ -114,7 +114,7 @@ TM_D void block_reduce3(T& a, T& b, T& c, T* red, int slot) {
   b = wave_sum(b);
   c = wave_sum(c);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  T* r = red + slot * 12;
+  T* r = red + slot * 24;   // up to 8 waves
   if (lane == 0) { r[w * 3] = a; r[w * 3 + 1] = b; r[w * 3 + 2] = c; }
   __syncthreads();
   a = 0; b = 0; c = 0;
@@ -149,10 +149,16 @@ TM_D void block_reduce3_halves(T& a, T& b, T& c, T* red, int slot) {
 // holds 32 sites (one layout tile) for both, lanes l and l + 32 on the
 // same site, so every link and clover load of the wave covers both
 // right-hand sides with the cache lines of one.
-template <typename T, int MINB, bool PAIR>
+// CPL (with PAIR): the pair is the two flavours of a doublet (Sec. 1.1,
+// Eq. (2)) and the block operator carries the flavour coupling: each
+// flavour's D_B(+-mubar) plus -epsbar times the other flavour at the same
+// site, one MR step on both flavours together (one alpha from sums over
+// both halves).
+template <typename T, int MINB, bool PAIR, bool CPL = false>
 TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                           const double* __restrict__ mu_dev, const int* __restrict__ blist, int nblk, int nrhs,
-                          int mr_steps) {
+                          int mr_steps, T epsbar = 0) {
+  static_assert(!CPL || PAIR, "the flavour coupling needs both flavours in the workgroup");
   extern __shared__ unsigned char smem_raw[];
   const FineGeom& g = op.g;
   const long V = g.V;
@@ -186,6 +192,11 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   {
     cplx<T> dz[12];
     site_dslash(op, zr, s, mu, dz);
+    if constexpr (CPL) {
+      const cplx<T>* zo = z + (long)(r ^ 1) * 12 * V + tsite(s, 12);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) dz[k] -= epsbar * zo[k * FT];
+    }
     const cplx<T>* er = eta + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -207,6 +218,12 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
     block_hops_dir<2>(op, lds, s, loc, c, q);
     compiler_fence(q);
     block_hops_dir<3>(op, lds, s, loc, c, q);
+    if constexpr (CPL) {
+      // the other flavour's rho at this site, staged by the other half
+      const cplx<T>* lo = reinterpret_cast<cplx<T>*>(smem_raw) + (half ^ 1) * 12 * bv;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) q[k] -= epsbar * lo[k * bv + loc];
+    }
     T qq = 0, qr_re = 0, qr_im = 0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -217,7 +234,7 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
     }
     // the next step overwrites the staged rho only after this barrier,
     // which every wave reaches after its last neighbour read
-    if constexpr (PAIR) block_reduce3_halves(qq, qr_re, qr_im, red, it & 1);
+    if constexpr (PAIR && !CPL) block_reduce3_halves(qq, qr_re, qr_im, red, it & 1);
     else block_reduce3(qq, qr_re, qr_im, red, it & 1);
     cplx<T> alpha = qq > (T)0 ? mk(qr_re / qq, qr_im / qq) : mk<T>(0, 0);
 #pragma unroll

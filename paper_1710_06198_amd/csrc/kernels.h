@@ -44,20 +44,26 @@ void launch_dslash(const FineOp<T>& op, const cplx<T>* in, cplx<T>* out, int nrh
 template <typename T>
 void launch_schur(const FineOp<T>& op, const cplx<T>* in, cplx<T>* tmp, cplx<T>* out, int nrhs, const double* mu_dev,
                   hipStream_t st);
+// zero the sites of one parity (x + y + z + t even: 0, odd: 1)
+template <typename T>
+void launch_zero_parity(const FineGeom& g, cplx<T>* v, int nrhs, int parity, hipStream_t st);
 // out_r = Gamma5 in_r (any level: d dof per site, sites*d elements, SoA fine or AoS coarse)
 template <typename T>
 void launch_gamma5_fine(const FineGeom& g, const cplx<T>* in, cplx<T>* out, int nrhs, hipStream_t st);
 
 // ---- fine SAP (K3): one colour's block solves, z updated in place
+// epsbar != 0 (FP32, nrhs = 2): the doublet's coupled block operator
 template <typename T>
 void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nrhs, const double* mu_dev,
-                     const int* block_list, int nblk, int mr_steps, hipStream_t st);
+                     const int* block_list, int nblk, int mr_steps, hipStream_t st, double epsbar = 0.0);
 
 // the same with two right-hand sides per workgroup (2 x bvol threads);
-// lds_bytes: both MR vectors and the reduction slots; n8: blocks rounded up to 8
+// lds_bytes: both MR vectors and the reduction slots; n8: blocks rounded up
+// to 8; epsbar != 0: the pair is a doublet's two flavours (nrhs = 2) and the
+// block operator carries the flavour coupling -epsbar
 void launch_sap_fine_pair(const FineOp<float>& op, const cplx<float>* eta, cplx<float>* z, int nrhs,
                           const double* mu_dev, const int* block_list, int nblk, int mr_steps, size_t lds_bytes,
-                          unsigned n8, hipStream_t st);
+                          unsigned n8, hipStream_t st, double epsbar = 0.0);
 
 // ---- BLAS-1 and Krylov scalars (K9, K10)
 struct Reducer {
@@ -96,6 +102,9 @@ void launch_add_to64(const cplx<T>* x, cplx<double>* y, long count, hipStream_t 
 // back; y_f += a x_{1-f} (x and y distinct)
 template <typename T>
 void launch_flavour_couple(const cplx<T>* x, cplx<T>* y, double a, long n, hipStream_t st);
+// out = a + c b (complex c), n complex doubles; out may alias a
+void launch_lincomb(const cplx<double>* a, const cplx<double>* b, cplx<double>* out, double cre, double cim, long n,
+                    hipStream_t st);
 // streaming copy of bytes (a multiple of 16)
 void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);

@@ -290,7 +290,16 @@ struct Ctx {
                      tmamg_info* info, bool guess = false);
   tmamg_status solve_shifted(const cplx<double>* b, cplx<double>* x, int nrhs, const double* sigma, double tol,
                              tmamg_info* info);
-  tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info);
+  tmamg_status solve_multishift(const cplx<double>* b, cplx<double>* x, int nshift, const double* sigma, double tol,
+                                tmamg_info* info);
+  tmamg_status solve_eo(const cplx<double>* b, cplx<double>* x, int nrhs, const double* mu_host, double tol,
+                        tmamg_info* info);
+  // FP64 residuals r_k = b_k - (D D^dag + sigma_k) x_k (internal layout) and their relative norms
+  std::vector<double> shifted_residual(const cplx<double>* b, const cplx<double>* x, cplx<double>* r, int nrhs,
+                                       const std::vector<double>& mup, const std::vector<double>& bn);
+  DevArr<cplx<double>> ms_base;   // multishift: the base shift's four fields
+  tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info,
+                     const double* mu_force = nullptr);
   void force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F);
   void force_link_gradient(const cplx<double>* F, cplx<double>* G, double scale);
   void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
@@ -324,3 +333,9 @@ void launch_force(const FineOp<double>& op, double csw, const cplx<double>* X, c
                   cplx<double>* F_canon, hipStream_t st, cplx<double>* xi_ws = nullptr);
 void launch_link_gradient(const FineOp<double>& op, int antiperiodic, const cplx<double>* F_canon,
                           cplx<double>* G_canon, double scale, hipStream_t st);
+
+// molecular-dynamics pieces (md.hip), canonical layouts
+double md_gauge_force(const tmamg_lattice& lat, const cplx<double>* U, double beta, cplx<double>* F, hipStream_t st);
+void md_update_links(const tmamg_lattice& lat, cplx<double>* U, const cplx<double>* P, double eps, hipStream_t st);
+void md_update_momenta(const tmamg_lattice& lat, cplx<double>* P, const cplx<double>* F, double c, hipStream_t st);
+double md_kinetic(const tmamg_lattice& lat, const cplx<double>* P, hipStream_t st);

@@ -352,7 +352,8 @@ void Hier<T, S>::sap(int level, const cplx<T>* eta, cplx<T>* z, int nrhs, const 
     for (int col = 0; col < 2; ++col) {
       if (level == 0) {
         if (blist0[col].count == 0) continue;
-        launch_sap_fine<T>(fop, eta, z, nrhs, mu, blist0[col].p, blist0[col].count, p.mr_steps, c->st);
+        launch_sap_fine<T>(fop, eta, z, nrhs, mu, blist0[col].p, blist0[col].count, p.mr_steps, c->st,
+                           nrhs == 2 ? nd_eps : 0.0);
       } else {
         if (blist1[col].count == 0) continue;
         launch_sap_coarse<T, S>(g1, d1, p.sap_block1, Dc1.p, eta, z, nrhs, mu, blist1[col].p, blist1[col].count,
@@ -425,15 +426,19 @@ void Hier<T, S>::coarse_solve_nd(int level, const cplx<T>* rhs, cplx<T>* sol, co
   const double eps = nd_eps;
   const bool coarsest = level == nlev - 1;
   Krylov<T>& K = level == 1 ? KN1 : KN2;
-  K.ensure(2 * n, coarsest ? p.coarsest_iters : p.l2_iters, 1, !coarsest, st);
+  // the coupled coarsest GMRES takes twice the steps of one flavour's: each
+  // step applies D_c to both flavours, so the operator work equals that of
+  // the two flavours' separate solves
+  const int csteps = std::min(2 * p.coarsest_iters, 127);
+  K.ensure(2 * n, coarsest ? csteps : p.l2_iters, 1, !coarsest, st);
   launch_fill_zero(sol, (size_t)2 * n * sizeof(cplx<T>), st);
   OpFn<T> A = [this, level, mu, n, eps](const cplx<T>* in, cplx<T>* out) {
     dc_apply(level, in, out, 2, mu);
     launch_flavour_couple<T>(in, out, -eps, n, c->st);
   };
   if (coarsest) {
-    stats_coarsest += krylov_cycle<T>(K, A, nullptr, rhs, sol, 1, p.coarsest_iters, p.coarsest_tol, nullptr, false,
-                                      nullptr, st);
+    stats_coarsest += krylov_cycle<T>(K, A, nullptr, rhs, sol, 1, csteps, p.coarsest_tol, nullptr, false, nullptr,
+                                      st);
   } else {
     OpFn<T> M = [this, mu](const cplx<T>* in, cplx<T>* out) { precond(1, in, out, 2, mu); };
     stats_l2 += krylov_cycle<T>(K, A, &M, rhs, sol, 1, p.l2_iters, p.l2_tol, nullptr, false, nullptr, st);

@@ -114,8 +114,8 @@ int main(void) {
          TMAMG_STORE_BF16, TMAMG_STORE_FP16);
   printf("ops %d %d %d %d %d %d %d %d\n", TMAMG_OP_D64, TMAMG_OP_D32, TMAMG_OP_PROLONG, TMAMG_OP_RESTRICT,
          TMAMG_OP_DC, TMAMG_OP_SAP, TMAMG_OP_PREC, TMAMG_OP_COARSEST);
-  printf("eo %d %d %d %d %d\n", TMAMG_OP_SCHUR64, TMAMG_OP_SCHUR32, TMAMG_OP_DDAG64, TMAMG_OP_DDAG32,
-         TMAMG_OP_DCND);
+  printf("eo %d %d %d %d %d %d\n", TMAMG_OP_SCHUR64, TMAMG_OP_SCHUR32, TMAMG_OP_DDAG64, TMAMG_OP_DDAG32,
+         TMAMG_OP_DCND, TMAMG_OP_SAPND);
   printf("tune %d %d %d %d %d\n", TMAMG_TUNE_COARSE_APPLY, TMAMG_TUNE_SAP1, TMAMG_TUNE_RESTRICT0,
          TMAMG_TUNE_PROLONG0, TMAMG_TUNE_SAP0);
   return 0;
@@ -148,7 +148,7 @@ def test_struct_layout_matches_c_compiler(tm, tmp_path):
                                                    b.OP_SAP, b.OP_PREC, b.OP_COARSEST]
         elif parts[0] == "eo":
             assert [int(v) for v in parts[1:]] == [b.OP_SCHUR64, b.OP_SCHUR32, b.OP_DDAG64, b.OP_DDAG32,
-                                                   b.OP_DCND]
+                                                   b.OP_DCND, b.OP_SAPND]
         elif parts[0] == "tune":
             assert [int(v) for v in parts[1:]] == [b.TUNE_COARSE_APPLY, b.TUNE_SAP1, b.TUNE_RESTRICT0,
                                                    b.TUNE_PROLONG0, b.TUNE_SAP0]

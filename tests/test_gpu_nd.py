@@ -10,7 +10,8 @@ import torch
 
 from lattice_inputs import workload, load_m0, unit_links
 from oracle.dirac import WilsonClover, norm
-from oracle.nd import NDOperator, free_field_nd_solve
+from oracle.nd import NDOperator, free_field_nd_solve, coarse_nd_apply, sap_doublet
+from oracle import mg
 from tests.gpu_common import links, spinors, kappa_of, rel, field, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,7 @@ def solver(w, precision, nlevels=2):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("mubar,epsbar", [(0.12, 0.10), (0.15, 0.05)])
+@pytest.mark.parametrize("mubar,epsbar", [(0.12, 0.10), (0.15, 0.05), (0.05, 0.12)])
 def test_doublet_solve_true_residual(c1, precision, mubar, epsbar):
     """Bar: ||b - D_ND x|| / ||b|| <= 1e-10 with D_ND the oracle's (FP64)."""
     w, m0, U, Ud, op = c1
@@ -117,7 +118,7 @@ def test_doublet_three_level_mixed():
     m0 = load_m0()["c4"]
     U, Ud = links(dims, 0.3, 1235)
     op = WilsonClover(U, m0, 1.6)
-    p = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(1, 1, 1, 2),
+    p = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(12, 16), sap_block1=(2, 2, 2, 2),
                           precision=tm.MIXED, storage=tm.STORE_BF16)
     s = tm.Solver(dims, p)
     mubar, epsbar = 0.13, 0.11
@@ -166,3 +167,78 @@ def test_doublet_graph_replay_matches_eager():
         bf = field(b)
         res = norm(bf - NDOperator(op, mubar, epsbar).apply(field(xs[1].cpu()))) / norm(bf)
         assert res <= 1e-10
+
+
+@pytest.mark.parametrize("mubar,epsbar", [(0.12, 0.10), (0.05, 0.12)])
+def test_doublet_coarse_operator_is_galerkin_product(c1, mubar, epsbar):
+    """The library's doublet coarse operator (FP64 hierarchy, level 1)
+    against the oracle's P_ND^dag D_ND P_ND with the library's own P:
+    prolong each flavour, apply D_ND, restrict (Sec. 1.1 after Eq. 2)."""
+    w, m0, U, Ud, op = c1
+    say(f"D_ND,c parity c1 mubar={mubar} epsbar={epsbar}")
+    s = solver(w, tm.FP64)
+    s.setup(Ud, kappa_of(m0), w.csw, mubar)
+    nv = w.nv[0]
+    lx, ly, lz, lt = w.dims
+    Pg = torch.empty((nv, lt, lz, ly, lx, 4, 3), dtype=torch.complex128, device="cuda:0")
+    s.export(0, 0, Pg)
+    Q = mg.to_blocks(field(Pg.cpu()), w.agg[0], True).movedim(0, -1).contiguous()
+    P = mg.Prolongation(Q, w.agg[0], w.dims, 12)
+    Vc, d = s.level_info(1)
+    e = mg.random_test_vectors(P.coarse_dims, d, 2, 6601)
+    out = torch.empty((2, Vc, d), dtype=torch.complex128, device="cuda:0")
+    s.apply(tm.OP_DCND, 1, to_dev(e.reshape(2, Vc, d).numpy()), out, [mubar, epsbar])
+    ref = coarse_nd_apply(op, P, mubar, epsbar, e).reshape(2, Vc, d)
+    err = rel(out.cpu(), ref)
+    say(f"  rel. difference {err:.2e}")
+    assert err < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("mubar,epsbar", [(0.12, 0.10), (0.05, 0.12)])
+def test_doublet_coupled_coarse_levels_converge_faster(mubar, epsbar):
+    """Three levels on 8^3 x 16: the doublet solve with the coarse levels
+    on D_ND,c (default) and with each flavour's own coarse cycle; both meet
+    the oracle's residual bar, the coupled one in fewer outer iterations."""
+    dims = (8, 8, 8, 16)
+    w = workload("c4")
+    m0 = load_m0()["c4"]
+    U, Ud = links(dims, w.eps, 6701)
+    op = WilsonClover(U, m0, w.csw)
+    b, bd = spinors(dims, 6702, 2)
+    its = {}
+    for coupled in (1, 0):
+        p = tm.default_params(nlevels=3, agg=((4, 4, 4, 4), (2, 2, 2, 2)), nv=(24, 32), sap_block1=(2, 2, 2, 2),
+                              setup_iters=3, init_smooth=2, coarsest_iters=10, l2_iters=6, restart=30,
+                              precision=tm.MIXED, storage=tm.STORE_BF16, nd_coarse_coupling=coupled)
+        s = tm.Solver(dims, p)
+        s.setup(Ud, kappa_of(m0), w.csw, mubar)
+        x = torch.empty_like(bd)
+        info = s.solve_nd(bd, x, mubar, epsbar, tol=1e-10)
+        nd = NDOperator(op, mubar, epsbar)
+        res = norm(field(b) - nd.apply(field(x.cpu()))) / norm(field(b))
+        say(f"  coupled coarse levels {coupled}: {info.outer_iters} outer iterations, oracle residual {res:.2e}")
+        assert info.status == 0 and res <= 1e-10
+        its[coupled] = info.outer_iters
+        s.close()
+    assert its[1] <= its[0]
+
+
+def test_doublet_sap_on_coupled_blocks(c1):
+    """The mixed-precision doublet SAP (the two flavours in one workgroup,
+    the block operator with the flavour coupling -epsbar, one MR alpha per
+    block over both flavours) against the oracle's coupled SAP in FP64 at
+    the same sweeps and MR steps.  Bar as for the light-sector FP32 SAP."""
+    w, m0, U, Ud, op = c1
+    mubar, epsbar = 0.05, 0.12
+    say(f"doublet SAP c1 mubar={mubar} epsbar={epsbar}")
+    s = solver(w, tm.MIXED)
+    s.setup(Ud, kappa_of(m0), w.csw, mubar)
+    b, bd = spinors(w.dims, 6801, 2)
+    out = torch.empty_like(bd)
+    s.apply(tm.OP_SAPND, 0, bd, out, [mubar, epsbar])
+    ref = sap_doublet(NDOperator(op, mubar, epsbar), field(b), w.sap_block[0], w.sap_sweeps[0], w.mr_steps)
+    err = rel(field(out.cpu()), ref)
+    say(f"  rel. difference {err:.2e}")
+    assert err < 1e-5
+    s.close()
