@@ -257,6 +257,18 @@ tmamg_status tmamg_md_kinetic(tmamg_ctx* ctx, const void* P, double* K);
  * hopping and clover derivatives.  F: device [4][T][Z][Y][X][3][3]. */
 tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* Y, void* F);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the force
+ * of tmamg_force_from_fields with every intermediate field in a static
+ * device scratch array of 160 MiB per GPU, held from the first context on
+ * that GPU until the process ends.  It needs 78 complex doubles per site
+ * (at most 134,432 sites: a 16^3 x 32 lattice fits; larger lattices get
+ * TMAMG_EINVAL) and allocates nothing.  Every call on one GPU uses that
+ * GPU's single array: calls that overlap on one GPU (several contexts,
+ * threads or streams) race.  Same arguments and result as
+ * tmamg_force_from_fields. */
+tmamg_status tmamg_force_from_fields_noalloc(tmamg_ctx* ctx, const void* X, const void* Y, void* F);
+
 /* Link gradient of S_f for automatic differentiation (Sec. 1.2 force, as
  * a gradient): G_mu(x) = 2 scale F_mu(x) U_mu(x), with F a force from
  * tmamg_force at the context's current links U.  For every perturbation

@@ -28,7 +28,7 @@ EXPORTS = [
     "tmamg_time_kernel", "tmamg_last_error", "tmamg_autotune", "tmamg_tune_load", "tmamg_tune_save",
     "tmamg_tune_set", "tmamg_tune_get", "tmamg_tune_entries", "tmamg_tune_clear", "tmamg_force_link_gradient",
     "tmamg_solve_nd", "tmamg_solve_guess", "tmamg_debug_inject", "tmamg_solve_multishift", "tmamg_force_at",
-    "tmamg_gauge_force", "tmamg_md_update_links", "tmamg_md_update_momenta", "tmamg_md_kinetic", "tmamg_solve_eo",
+    "tmamg_gauge_force", "tmamg_md_update_links", "tmamg_md_update_momenta", "tmamg_md_kinetic", "tmamg_solve_eo", "tmamg_force_from_fields_noalloc",
 ]
 K_DSLASH32, K_DSLASH64, K_SAP0, K_RESTRICT0, K_PROLONG0, K_DC1, K_DC2, K_SAP1, K_COPY, K_SCHUR32 = range(10)
 TUNE_COARSE_APPLY, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0 = range(5)
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH):
     lib.tmamg_md_kinetic.argtypes = [vp, vp, P(d)]
     lib.tmamg_solve_nd.argtypes = [vp, vp, vp, d, d, d, P(Info)]
     lib.tmamg_force_from_fields.argtypes = [vp, vp, vp, vp]
+    lib.tmamg_force_from_fields_noalloc.argtypes = [vp, vp, vp, vp]
     lib.tmamg_force_link_gradient.argtypes = [vp, vp, vp, d]
     lib.tmamg_apply.argtypes = [vp, i, i, vp, vp, i, P(d)]
     lib.tmamg_debug_set_test_vectors.argtypes = [vp, i, vp]
@@ -428,6 +429,15 @@ class Solver:
         self._spinors("Y", Y, 1)
         self._links("F", F)
         _check(self.lib.tmamg_force_from_fields(self.h, _ptr(X), _ptr(Y), _ptr(F)))
+
+    def force_from_fields_noalloc(self, X, Y, F):
+        """force_from_fields without any device allocation: the library's
+        static per-GPU scratch array (at most 134,432 sites; calls that
+        overlap on one GPU race)."""
+        self._spinors("X", X, 1)
+        self._spinors("Y", Y, 1)
+        self._links("F", F)
+        _check(self.lib.tmamg_force_from_fields_noalloc(self.h, _ptr(X), _ptr(Y), _ptr(F)))
 
     def force_link_gradient(self, F, G, scale=1.0):
         self._links("F", F)

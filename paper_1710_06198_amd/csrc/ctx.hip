@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 #include <cstdlib>
+#include <mutex>
 
 using clk = std::chrono::steady_clock;
 
@@ -950,6 +951,21 @@ void Ctx::force_link_gradient(const cplx<double>* F, cplx<double>* G, double sca
   HIPCHK(hipGetLastError());
 }
 
+// The same with every intermediate field in the caller-provided device
+// workspace ws (78 complex doubles per site: X and Y in the internal layout,
+// then the clover part's field); allocates nothing.
+void Ctx::force_from_fields_ws(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F, cplx<double>* ws) {
+  if (!have_links) throw TmError{TMAMG_ESTATE, "force before setup"};
+  check(X && Y && F, "null pointer");
+  const long n = 12 * fg.V;
+  cplx<double>* Xi = ws;
+  cplx<double>* Yi = ws + n;
+  launch_spinor_to_internal<double>(fg, X, Xi, 1, st);
+  launch_spinor_to_internal<double>(fg, Y, Yi, 1, st);
+  launch_force(op64(), csw, Xi, Yi, F, st, ws + 2 * n);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 void Ctx::force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F) {
   if (!have_links) throw TmError{TMAMG_ESTATE, "force before setup"};
   check(X && Y && F, "null pointer");
@@ -1167,6 +1183,36 @@ void Ctx::autotune(const int* nrhs_list, int n, int reps) {
   HIPCHK(hipStreamSynchronize(st));
 }
 
+// ------------------------------------------------------------------ allocation-free scratch
+// Device scratch of tmamg_force_from_fields_noalloc: a file-scope device
+// array (every GPU the library runs on holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: it
+// stands for no device address on the host.  The device address of each
+// GPU's copy is taken once per device, with that device current, when the
+// first context is created on it, and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)160 << 20;
+constexpr size_t NOALLOC_BYTES_PER_SITE = 78 * sizeof(cplx<double>);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[256];
+
+static void* device_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) throw TmError{TMAMG_EHIP, "device index out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      throw TmError{TMAMG_EHIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e)};
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // ------------------------------------------------------------------ C ABI
 template <typename F>
 static tmamg_status guarded(F&& f) {
@@ -1229,8 +1275,9 @@ tmamg_status tmamg_create(tmamg_ctx** ctx, const tmamg_lattice* lat, const tmamg
   return guarded([&]() {
     check(ctx && lat && par, "null argument");
     *ctx = nullptr;
-    Ctx* c = new Ctx(*lat, *par, reinterpret_cast<hipStream_t>(hip_stream), allocator);
-    *ctx = reinterpret_cast<tmamg_ctx*>(c);
+    std::unique_ptr<Ctx> c(new Ctx(*lat, *par, reinterpret_cast<hipStream_t>(hip_stream), allocator));
+    c->scratch = device_scratch();
+    *ctx = reinterpret_cast<tmamg_ctx*>(c.release());
     return TMAMG_OK;
   });
 }
@@ -1364,6 +1411,20 @@ tmamg_status tmamg_force_from_fields(tmamg_ctx* ctx, const void* X, const void* 
   return with_ctx(ctx, [&](Ctx* c) {
     c->force_from_fields(static_cast<const cplx<double>*>(X), static_cast<const cplx<double>*>(Y),
                               static_cast<cplx<double>*>(F));
+    return TMAMG_OK;
+  });
+}
+
+tmamg_status tmamg_force_from_fields_noalloc(tmamg_ctx* ctx, const void* X, const void* Y, void* F) {
+  return with_ctx(ctx, [&](Ctx* c) {
+    const size_t need = (size_t)c->fg.V * NOALLOC_BYTES_PER_SITE;
+    if (need > NOALLOC_SCRATCH_BYTES)
+      throw TmError{TMAMG_EINVAL, "the allocation-free force needs " + std::to_string(need) +
+                                      " bytes of scratch (78 complex doubles per site); its static array holds " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES) + " (at most " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES / NOALLOC_BYTES_PER_SITE) + " sites)"};
+    c->force_from_fields_ws(static_cast<const cplx<double>*>(X), static_cast<const cplx<double>*>(Y),
+                            static_cast<cplx<double>*>(F), static_cast<cplx<double>*>(c->scratch));
     return TMAMG_OK;
   });
 }

@@ -301,6 +301,8 @@ struct Ctx {
   tmamg_status force(const cplx<double>* phi, cplx<double>* F, double* S, double tol, tmamg_info* info,
                      const double* mu_force = nullptr);
   void force_from_fields(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F);
+  void force_from_fields_ws(const cplx<double>* X, const cplx<double>* Y, cplx<double>* F, cplx<double>* ws);
+  void* scratch = nullptr;   // this device's static scratch array (allocation-free entry point)
   void force_link_gradient(const cplx<double>* F, cplx<double>* G, double scale);
   void apply(int op, int level, const cplx<double>* in, cplx<double>* out, int nrhs, const double* mu_host);
   void upload_mu(int nrhs, const double* mu_host);
