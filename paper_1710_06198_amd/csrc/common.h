@@ -36,15 +36,44 @@ template <typename T> TM_HD cplx<T> conj(cplx<T> a) { return mk(a.re, -a.im); }
 template <typename T> TM_HD cplx<T> cmulc(cplx<T> a, cplx<T> b) {
   return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
+// Accumulations are written as explicit chains of fused multiply-adds
+// (four per complex product): written as a += (x*y - u*v) the compiler may
+// only fuse one of the products and then adds, three instructions per real
+// component instead of two.
+TM_HD float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+TM_HD double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // a += b * c
 template <typename T> TM_HD void cfma(cplx<T>& a, cplx<T> b, cplx<T> c) {
-  a.re += b.re * c.re - b.im * c.im;
-  a.im += b.re * c.im + b.im * c.re;
+  a.re = fmaT(b.re, c.re, a.re);
+  a.re = fmaT(-b.im, c.im, a.re);
+  a.im = fmaT(b.re, c.im, a.im);
+  a.im = fmaT(b.im, c.re, a.im);
 }
 // a += conj(b) * c
 template <typename T> TM_HD void cfmac(cplx<T>& a, cplx<T> b, cplx<T> c) {
-  a.re += b.re * c.re + b.im * c.im;
-  a.im += b.re * c.im - b.im * c.re;
+  a.re = fmaT(b.re, c.re, a.re);
+  a.re = fmaT(b.im, c.im, a.re);
+  a.im = fmaT(b.re, c.im, a.im);
+  a.im = fmaT(-b.im, c.re, a.im);
+}
+// a -= b * c
+template <typename T> TM_HD void cfms(cplx<T>& a, cplx<T> b, cplx<T> c) {
+  a.re = fmaT(-b.re, c.re, a.re);
+  a.re = fmaT(b.im, c.im, a.re);
+  a.im = fmaT(-b.re, c.im, a.im);
+  a.im = fmaT(-b.im, c.re, a.im);
+}
+// s += |a|^2
+template <typename T> TM_HD void acc_norm2(T& s, cplx<T> a) {
+  s = fmaT(a.re, a.re, s);
+  s = fmaT(a.im, a.im, s);
+}
+// (sre, sim) += conj(a) * b
+template <typename T> TM_HD void acc_dotc(T& sre, T& sim, cplx<T> a, cplx<T> b) {
+  sre = fmaT(a.re, b.re, sre);
+  sre = fmaT(a.im, b.im, sre);
+  sim = fmaT(a.re, b.im, sim);
+  sim = fmaT(-a.im, b.re, sim);
 }
 template <typename T> TM_HD cplx<T> times_i(cplx<T> a) { return mk(-a.im, a.re); }
 template <typename T> TM_HD T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }

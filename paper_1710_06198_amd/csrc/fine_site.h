@@ -227,10 +227,8 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
     T qq = 0, qr_re = 0, qr_im = 0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      qq += norm2(q[k]);
-      cplx<T> t = cmulc(q[k], rho[k]);
-      qr_re += t.re;
-      qr_im += t.im;
+      acc_norm2(qq, q[k]);
+      acc_dotc(qr_re, qr_im, q[k], rho[k]);
     }
     // the next step overwrites the staged rho only after this barrier,
     // which every wave reaches after its last neighbour read
@@ -246,7 +244,7 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
       } else {
         cfma(e[k], alpha, rho[k]);
       }
-      rho[k] -= alpha * q[k];
+      cfms(rho[k], alpha, q[k]);
     }
   }
   if (!writes) return;

@@ -194,7 +194,9 @@ TM_D void clover_block_mv(const T* __restrict__ cl, unsigned s, long V, const cp
   for (int k = 0; k < 36; ++k) a[k] = STREAM ? __builtin_nontemporal_load(p + k * FT) : p[k * FT];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    cplx<T> row = a[i] * v[i];
+    cplx<T> row = acc[i];
+    row.re = fmaT(a[i], v[i].re, row.re);
+    row.im = fmaT(a[i], v[i].im, row.im);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       if (j == i) continue;
@@ -203,10 +205,10 @@ TM_D void clover_block_mv(const T* __restrict__ cl, unsigned s, long V, const cp
         cfma(row, mk(a[k], a[k + 1]), v[j]);
       } else {
         int k = 6 + 2 * herm_idx(j, i);
-        cfma(row, mk(a[k], -a[k + 1]), v[j]);
+        cfmac(row, mk(a[k], a[k + 1]), v[j]);
       }
     }
-    acc[i] += row;
+    acc[i] = row;
   }
 }
 
