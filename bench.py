@@ -478,6 +478,100 @@ def bench_force(args):
     return 0
 
 
+def paper_volume_params(tm, w):
+    """The 64^3 x 128 memory plan on one GPU: the setup smooths and cycles
+    the test vectors 8 at a time and releases them once P and D_c are built,
+    the outer FGMRES restarts after 8 iterations, and right-hand sides are
+    solved one after the other.  Fine fields are 6.4 GB in FP64 and 3.2 GB in
+    FP32 at this volume: links and clover in both precisions take 58 GB, P
+    in bf16 39 GB, a solve's FP64 vectors and FP32 Krylov space 90 GB."""
+    p = solver_params(tm, w, tm.MIXED)
+    p.restart = 8
+    p.setup_chunk = 8
+    p.keep_test_vectors = 0
+    return p
+
+
+def bench_paper_volume(args):
+    """64^3 x 128, the paper's volume, with all three forms at once on one
+    GPU: setup, 4 Gaussian right-hand sides solved one after the other to
+    1e-10, and S_f with its force for phi = D xi (S_f = |xi|^2 exactly).
+    Mixed precision only: the plain FP64 DD-alpha-AMG does not fit in one
+    GPU's memory at this volume (its FP64 test vectors alone take 155 GB)."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
+    w = workload("c5")
+    m0 = load_m0()[w.name]
+    kappa = 1.0 / (2 * m0 + 8)
+    dev = torch.device("cuda:0")
+    nrhs = w.extra.get("nrhs", 4)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    log(f"[bench] workload c5 dims {w.dims}: generating links ({workers} processes)")
+    t0 = time.perf_counter()
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"], workers=workers))
+    log(f"[bench]   links drawn in {time.perf_counter() - t0:.1f} s")
+    Ud = U.to(dev)
+    del U
+    stream = torch.cuda.Stream(device=dev)
+    s = tm.Solver(w.dims, paper_volume_params(tm, w), stream=stream)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    _, t_setup = _timed(lambda: s.setup(Ud, kappa, w.csw, w.mu))
+    mem_setup = torch.cuda.max_memory_allocated() / 1e9
+    log(f"[bench]   setup {t_setup:.2f} s, peak device memory {mem_setup:.1f} GB")
+    del Ud
+    torch.cuda.empty_cache()
+    b_all = gaussian_spinor(w.dims, w.seeds["source"], n=nrhs)
+    solves = []
+    x = None
+    for r in range(nrhs):
+        b = torch.as_tensor(b_all[r:r + 1]).to(dev)
+        x = torch.empty_like(b) if x is None else x
+        info, t = _timed(lambda: s.solve(b, x, tol=w.tol))
+        solves.append({"s": t, "outer_iters": info.outer_iters, "true_rel_resid": info.true_rel_resid,
+                       "level1_steps": info.l2_iters_total, "coarsest_iters": info.coarsest_iters_total})
+        log(f"[bench]   rhs {r}: {solves[-1]}")
+        del b
+    del b_all
+    xi = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["xi"], n=1)).to(dev)
+    xi2 = float((xi.abs() ** 2).sum())
+    phi = torch.empty_like(xi)
+    s.apply(tm.OP_D64, 0, xi, phi, [w.mu])
+    del xi, x
+    torch.cuda.empty_cache()
+    F = torch.empty((4,) + tuple(reversed(w.dims)) + (3, 3), dtype=torch.complex128, device=dev)
+    (S, finfo), t_force = _timed(lambda: s.force(phi, F, tol=w.tol))
+    log(f"[bench]   force {t_force:.2f} s, S rel. error {abs(S - xi2) / xi2:.2e}")
+    mem_peak = torch.cuda.max_memory_allocated() / 1e9
+    del F, phi
+    torch.cuda.empty_cache()
+    V = w.volume
+    st_ms = s.time_kernel(tm.K_DSLASH32, 1, 10)
+    sap_ms = s.time_kernel(tm.K_SAP0, 1, 5)
+    total = t_setup + sum(v["s"] for v in solves) + t_force
+    out = {"metric": "solve time (s) @1e-10 rel. resid & stencil HBM GB/s; mixed+batched vs FP64 AMG",
+           "value": total, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": total * 1e3,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+           "dtype": "fp32+bf16 (fp64 outer, fp64 force kernels)", "data": "synthetic",
+           "config": {"workload": "c5: 64x64x64x128 (the paper's volume), 3-level DD-alpha-AMG, mixed precision; "
+                                  "one step = setup + 4 Gaussian right-hand sides (solved one after the other) "
+                                  "+ S_f and its force for phi = D xi, all to 1e-10",
+                      "lattice": list(w.dims), "mu": w.mu, "csw": w.csw, "m0": m0, "nv": list(w.nv),
+                      "restart": 8, "setup_chunk": 8, "parallelism": "1 GPU"},
+           "setup_s": t_setup, "solves": solves, "force_s": t_force, "S_rel_err_vs_xi2": abs(S - xi2) / xi2,
+           "force_outer_iters": finfo.outer_iters, "force_true_rel_resid": finfo.true_rel_resid,
+           "peak_device_memory_gb": {"setup": mem_setup, "job": mem_peak},
+           "fp64_amg": None,
+           "stencil_roofline": {"kernel": "k_dslash<float>", "rhs": 1, "ms": st_ms, "bytes_per_launch": 768 * V,
+                                "achieved": 768 * V / (st_ms * 1e-3) / 1e9, "unit": "GB/s",
+                                "frac": 768 * V / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "sap_fine_colour_1rhs_ms": sap_ms}
+    s.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def kernels_only(args):
     """Timing loops for profiler and counter passes: a context with links
     and clover but no multigrid (so no setup kernels run), then the FP32
@@ -539,6 +633,8 @@ def main():
         return bench_batched(args)
     if args.workload == "c4":
         return bench_force(args)
+    if args.workload == "c5":
+        return bench_paper_volume(args)
     w = workload(args.workload)
     m0 = load_m0()[w.name]
     kappa = 1.0 / (2 * m0 + 8)

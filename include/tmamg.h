@@ -89,6 +89,13 @@ typedef struct {
   int nd_coarse_coupling;  /* doublet solves (Sec. 1.1, Eq. (2)): 1 (default) the coarse
                               levels solve D_ND,c = P_ND^dag D_ND P_ND, i.e. each flavour's
                               D_c(+-mubar) coupled by -epsbar; 0: each flavour's own cycle */
+  int setup_chunk;      /* memory plan: test vectors the setup smooths and cycles at once on
+                           each level (0: all of them); the setup's fine work buffer holds
+                           this many vectors.  The result does not depend on it: every test
+                           vector is treated alone */
+  int keep_test_vectors;  /* memory plan: 1 (default) keep the fine test vectors after the setup
+                             for tmamg_setup_update; 0 release them (and the setup's work
+                             buffers), tmamg_setup_update then returns TMAMG_ESTATE */
 } tmamg_params;
 
 typedef struct {
@@ -149,7 +156,8 @@ tmamg_status tmamg_setup(tmamg_ctx* ctx, const void* U, double kappa, double csw
  * update): P and D_c are rebuilt on U from the kept test vectors, which
  * then take `iters` further setup iterations.  U: device, canonical; the
  * same SU(3) check and errors as tmamg_setup; TMAMG_ESTATE before a
- * setup. */
+ * setup or when the setup released its test vectors (keep_test_vectors
+ * = 0). */
 tmamg_status tmamg_setup_update(tmamg_ctx* ctx, const void* U, int iters);
 
 /* Solve D(mu_r) x_r = b_r for r < nrhs, in one batch: FGMRES

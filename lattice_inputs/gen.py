@@ -82,19 +82,38 @@ def su3_from_coeffs(coeffs: np.ndarray, scale: float) -> np.ndarray:
     return _reunitarise(_expi_hermitian(h))
 
 
-def gauge_links(dims, eps: float, seed: int) -> np.ndarray:
+def _links_slice(args):
+    """Links of time slice t: [4][Z][Y][X][3][3] from that slice's stream."""
+    dims, eps, seq, t = args
+    lx, ly, lz, _ = dims
+    g = np.random.Generator(np.random.PCG64(seq)).standard_normal((lz, ly, lx, 4, 8))
+    return t, np.moveaxis(su3_from_coeffs(g, eps), 3, 0)
+
+
+def gauge_links(dims, eps: float, seed: int, t_range=None, workers: int = 1) -> np.ndarray:
     """Random links U = exp(i eps sum_a g_a lambda_a / 2), g_a ~ N(0,1).
 
     dims = (Lx, Ly, Lz, Lt).  Draw order: t-slice major (one stream per
-    slice), then z, y, x, then mu, then a.
-    Returns complex128 [4][T][Z][Y][X][3][3].
+    slice), then z, y, x, then mu, then a.  t_range = (t0, t1) draws only
+    slices t0 <= t < t1 (the same values as in the whole field; t may run
+    past Lt, wrapping); workers > 1 draws slices in that many processes
+    (identical result).
+    Returns complex128 [4][T][Z][Y][X][3][3] (T = t1 - t0 with t_range).
     """
     lx, ly, lz, lt = dims
-    out = np.empty((4, lt, lz, ly, lx, 3, 3), dtype=np.complex128)
-    for t, rng in enumerate(_slice_rngs(seed, lt)):
-        g = rng.standard_normal((lz, ly, lx, 4, 8))
-        u = su3_from_coeffs(g, eps)              # [Z,Y,X,4,3,3]
-        out[:, t] = np.moveaxis(u, 3, 0)
+    t0, t1 = (0, lt) if t_range is None else t_range
+    seqs = np.random.SeedSequence(seed).spawn(lt)
+    jobs = [(dims, eps, seqs[t % lt], t - t0) for t in range(t0, t1)]
+    out = np.empty((4, t1 - t0, lz, ly, lx, 3, 3), dtype=np.complex128)
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            for t, u in pool.imap_unordered(_links_slice, jobs):
+                out[:, t] = u
+    else:
+        for job in jobs:
+            t, u = _links_slice(job)
+            out[:, t] = u
     return out
 
 

@@ -60,6 +60,8 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_ulonglong),
         ("use_graph", ctypes.c_int),
         ("nd_coarse_coupling", ctypes.c_int),
+        ("setup_chunk", ctypes.c_int),
+        ("keep_test_vectors", ctypes.c_int),
     ]
 
 

@@ -161,73 +161,70 @@ void launch_scale_dev(const cplx<T>* x, cplx<T>* y, const double* s, long n, int
 
 template <typename Tin, typename Tout>
 __global__ void k_convert(const cplx<Tin>* __restrict__ x, cplx<Tout>* __restrict__ y, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  cplx<Tin> v = x[k];
-  y[k] = mk<Tout>((Tout)v.re, (Tout)v.im);
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x) {
+    cplx<Tin> v = x[k];
+    y[k] = mk<Tout>((Tout)v.re, (Tout)v.im);
+  }
 }
 template <typename Tin, typename Tout>
 void launch_convert(const cplx<Tin>* x, cplx<Tout>* y, long count, hipStream_t st) {
-  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, count);
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid1d(count)), dim3(256), 0, st, x, y, count);
 }
 
 template <typename T>
 __global__ void k_axpby(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, double a, double b, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  y[k] = (T)a * x[k] + (T)b * y[k];
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x)
+    y[k] = (T)a * x[k] + (T)b * y[k];
 }
 template <typename T>
 void launch_axpby(const cplx<T>* x, cplx<T>* y, double a, double b, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpby<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, a, b, count);
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid1d(count)), dim3(256), 0, st, x, y, a, b, count);
 }
 template <typename T>
 __global__ void k_xmy(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  y[k] = x[k] - y[k];
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x)
+    y[k] = x[k] - y[k];
 }
 template <typename T>
 void launch_xmy(const cplx<T>* x, cplx<T>* y, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_xmy<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, count);
+  hipLaunchKernelGGL(k_xmy<T>, dim3(grid1d(count)), dim3(256), 0, st, x, y, count);
 }
 template <typename T>
 __global__ void k_add_to64(const cplx<T>* __restrict__ x, cplx<double>* __restrict__ y, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  cplx<T> v = x[k];
-  y[k] += mk<double>((double)v.re, (double)v.im);
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x) {
+    cplx<T> v = x[k];
+    y[k] += mk<double>((double)v.re, (double)v.im);
+  }
 }
 template <typename T>
 void launch_add_to64(const cplx<T>* x, cplx<double>* y, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_add_to64<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, x, y, count);
+  hipLaunchKernelGGL(k_add_to64<T>, dim3(grid1d(count)), dim3(256), 0, st, x, y, count);
 }
 
 // Flavour coupling of the doublet operator (Sec. 1.1, Eq. 2): with the two
 // flavours stored back to back (n elements each), y_f += a x_{1-f}.
 template <typename T>
 __global__ void k_flavour_couple(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ y, double a, long n) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= 2 * n) return;
-  y[k] += (T)a * x[k < n ? k + n : k - n];
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < 2 * n; k += (long)gridDim.x * blockDim.x)
+    y[k] += (T)a * x[k < n ? k + n : k - n];
 }
 template <typename T>
 void launch_flavour_couple(const cplx<T>* x, cplx<T>* y, double a, long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_flavour_couple<T>, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, st, x, y, a, n);
+  hipLaunchKernelGGL(k_flavour_couple<T>, dim3(grid1d(2 * n)), dim3(256), 0, st, x, y, a, n);
 }
 
 // out = a + c b for complex fields of n elements, c complex (host scalar)
 __global__ void k_lincomb(const cplx<double>* __restrict__ a, const cplx<double>* __restrict__ b,
                           cplx<double>* __restrict__ out, double cre, double cim, long n) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  cplx<double> v = a[k];
-  cfma(v, mk(cre, cim), b[k]);
-  out[k] = v;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    cplx<double> v = a[k];
+    cfma(v, mk(cre, cim), b[k]);
+    out[k] = v;
+  }
 }
 void launch_lincomb(const cplx<double>* a, const cplx<double>* b, cplx<double>* out, double cre, double cim, long n,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, out, cre, cim, n);
+  hipLaunchKernelGGL(k_lincomb, dim3(grid1d(n)), dim3(256), 0, st, a, b, out, cre, cim, n);
 }
 
 // plain streaming copy (16-byte accesses); the reference kernel of known
@@ -242,14 +239,15 @@ void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st) {
   hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4*)in, (uint4*)out, n);
 }
 
+// 4-byte words; buffers of any size (the grid strides)
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
-  size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0u;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0u;
 }
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   size_t n = bytes / 4;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)p, n);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid1d(n)), dim3(256), 0, st, (uint32_t*)p, n);
 }
 
 // ------------------------------------------------------------------ Krylov scalars

@@ -29,6 +29,7 @@ void Hier<T, S>::precond_f(const cplx<float>* v, cplx<float>* z, int nrhs, const
 template <typename T, typename S>
 void Hier<T, S>::rebuild() {
   if (nlev < 2) return;
+  setup_workspace();
   build(0);
   if (nlev >= 3) build(1);
 }
@@ -197,6 +198,8 @@ Ctx::Ctx(const tmamg_lattice& l, const tmamg_params& p, hipStream_t s, const tma
   check(p.precision == TMAMG_FP64 || p.precision == TMAMG_MIXED, "precision");
   check(p.use_graph == 0 || p.use_graph == 1, "use_graph must be 0 or 1");
   check(p.nd_coarse_coupling == 0 || p.nd_coarse_coupling == 1, "nd_coarse_coupling must be 0 or 1");
+  check(p.setup_chunk >= 0, "setup_chunk must be >= 0");
+  check(p.keep_test_vectors == 0 || p.keep_test_vectors == 1, "keep_test_vectors must be 0 or 1");
   if (p.precision == TMAMG_MIXED)
     check(p.storage == TMAMG_STORE_FP32 || p.storage == TMAMG_STORE_BF16 || p.storage == TMAMG_STORE_FP16,
           "mixed precision stores P and D_c in fp32, bf16 or fp16");
@@ -389,11 +392,14 @@ void Ctx::setup(const cplx<double>* U, double kappa_, double csw_, double mu_) {
 
 void Ctx::setup_update(const cplx<double>* U, int iters) {
   if (!have_setup) throw TmError{TMAMG_ESTATE, "setup_update before setup"};
+  if (!hier->has_test_vectors())
+    throw TmError{TMAMG_ESTATE, "the setup released its test vectors (keep_test_vectors = 0)"};
   check(iters >= 0, "iters must be >= 0");
   auto t0 = clk::now();
   load_links(U);
   hier->rebuild();
   for (int i = 0; i < iters; ++i) hier->setup_iteration();
+  hier->release_setup_workspace();
   HIPCHK(hipStreamSynchronize(st));
   (void)drain_counters();
   t_setup = std::chrono::duration<double>(clk::now() - t0).count();
@@ -908,29 +914,61 @@ tmamg_status Ctx::force(const cplx<double>* phi, cplx<double>* F, double* S, dou
   ensure(1);
   tmamg_info loc{};
   const long n = 12 * fg.V;
-  // Y = D(mu)^-1 phi
-  launch_spinor_to_internal<double>(fg, phi, b64.p, 1, st);
-  DevArr<cplx<double>> phi64, Y, X;
-  phi64.alloc(n);
-  Y.alloc(n);
-  X.alloc(n);
-  HIPCHK(hipMemcpyAsync(phi64.p, b64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   const double mf = mu_force ? *mu_force : mu;
   check(std::isfinite(mf), "non-finite twisted mass");
   double mp = mf, mm = -mf;
+  // Y = D(mu)^-1 phi
+  launch_spinor_to_internal<double>(fg, phi, b64.p, 1, st);
+  DevArr<cplx<double>> Y;
+  Y.alloc(n);
   tmamg_status s1 = solve_core(1, &mp, tol, &loc);
   HIPCHK(hipMemcpyAsync(Y.p, x64.p, n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
-  // X = Gamma5 D(-mu)^-1 Gamma5 Y
+  // X = Gamma5 D(-mu)^-1 Gamma5 Y, in t64 (free once the solves are done)
   launch_gamma5_fine<double>(fg, Y.p, b64.p, 1, st);
   tmamg_status s2 = solve_core(1, &mm, tol, &loc);
-  launch_gamma5_fine<double>(fg, x64.p, X.p, 1, st);
+  cplx<double>* X = t64.p;
+  launch_gamma5_fine<double>(fg, x64.p, X, 1, st);
+  // The Krylov bases hold nothing live after the solves: phi (internal
+  // layout, n values) and the clover part's field of the force kernels
+  // (54 per site) borrow their memory where it is large enough, which keeps
+  // the force within the solver's own footprint at large volumes; the
+  // borrowed bytes are cleared afterwards (the next solve's bases start
+  // from zeros).
+  const size_t phi_b = (size_t)n * sizeof(cplx<double>), xi_b = (size_t)54 * fg.V * sizeof(cplx<double>);
+  struct Pool { char* p; size_t left; };
+  Pool pools[2] = {{nullptr, 0}, {nullptr, 0}};
+  if (par.precision == TMAMG_FP64) {
+    pools[0] = {reinterpret_cast<char*>(K64.V.p), K64.V.bytes()};
+    pools[1] = {reinterpret_cast<char*>(K64.Z.p), K64.Z.bytes()};
+  } else {
+    pools[0] = {reinterpret_cast<char*>(K32.V.p), K32.V.bytes()};
+    pools[1] = {reinterpret_cast<char*>(K32.Z.p), K32.Z.bytes()};
+  }
+  std::vector<std::pair<char*, size_t>> borrowed;
+  DevArr<cplx<double>> own_phi, own_xi;
+  auto take = [&](size_t bytes, DevArr<cplx<double>>& own) -> cplx<double>* {
+    for (Pool& q : pools)
+      if (q.p && q.left >= bytes) {
+        char* r = q.p;
+        q.p += (bytes + 255) / 256 * 256;
+        q.left = q.left > (bytes + 255) / 256 * 256 ? q.left - (bytes + 255) / 256 * 256 : 0;
+        borrowed.emplace_back(r, bytes);
+        return reinterpret_cast<cplx<double>*>(r);
+      }
+    own.alloc(bytes / sizeof(cplx<double>));
+    return own.p;
+  };
+  cplx<double>* xi = csw != 0.0 ? take(xi_b, own_xi) : nullptr;
+  cplx<double>* phi64 = take(phi_b, own_phi);
+  launch_spinor_to_internal<double>(fg, phi, phi64, 1, st);
   // S = Re <phi, X>
   int NB = reduce_blocks(n);
-  launch_multidot<double>(phi64.p, n, 1, X.p, n, 1, red_partial.p, NB, nullptr, st);
+  launch_multidot<double>(phi64, n, 1, X, n, 1, red_partial.p, NB, nullptr, st);
   launch_finalize(red_partial.p, 1, 1, NB, red_out.p, 1, st);
   double sv[2];
   HIPCHK(hipMemcpyAsync(sv, red_out.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  launch_force(op64(), csw, X.p, Y.p, F, st);
+  launch_force(op64(), csw, X, Y.p, F, st, xi);
+  for (auto& b : borrowed) launch_fill_zero(b.first, b.second, st);
   HIPCHK(hipStreamSynchronize(st));
   *S = sv[0];
   tmamg_status s = (s1 == TMAMG_OK && s2 == TMAMG_OK) ? TMAMG_OK : TMAMG_NOT_CONVERGED;
@@ -1267,6 +1305,8 @@ tmamg_status tmamg_default_params(tmamg_params* p) {
   p->inner_tol = 1e-3;
   p->seed = 4001;
   p->nd_coarse_coupling = 1;
+  p->setup_chunk = 0;
+  p->keep_test_vectors = 1;
   return TMAMG_OK;
 }
 

@@ -1077,38 +1077,38 @@ TM_D unsigned long long mix64(unsigned long long z) {
 }
 template <typename T>
 __global__ void k_random(cplx<T>* out, long count, unsigned long long seed) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  unsigned long long h1 = mix64(seed * 0x632BE59BD9B4E019ULL + 2 * (unsigned long long)k);
-  unsigned long long h2 = mix64(h1 ^ (2 * (unsigned long long)k + 1));
-  double u1 = ((double)(h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-  double u2 = ((double)(h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-  double rad = sqrt(-log(u1));
-  double ph = 6.283185307179586 * u2;
-  out[k] = mk<T>((T)(rad * cos(ph)), (T)(rad * sin(ph)));
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x) {
+    unsigned long long h1 = mix64(seed * 0x632BE59BD9B4E019ULL + 2 * (unsigned long long)k);
+    unsigned long long h2 = mix64(h1 ^ (2 * (unsigned long long)k + 1));
+    double u1 = ((double)(h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double u2 = ((double)(h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double rad = sqrt(-log(u1));
+    double ph = 6.283185307179586 * u2;
+    out[k] = mk<T>((T)(rad * cos(ph)), (T)(rad * sin(ph)));
+  }
 }
 template <typename T>
 void launch_random(cplx<T>* out, long count, unsigned long long seed, hipStream_t st) {
-  hipLaunchKernelGGL(k_random<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, out, count, seed);
+  hipLaunchKernelGGL(k_random<T>, dim3(grid1d(count)), dim3(256), 0, st, out, count, seed);
 }
 
 template <typename S>
 __global__ void k_store_to64(const SP<S>* in, cplx<double>* out, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k < count) out[k] = Store<S>::template ld<double>(in + k);
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x)
+    out[k] = Store<S>::template ld<double>(in + k);
 }
 template <typename S>
 __global__ void k_store_from64(const cplx<double>* in, SP<S>* out, long count) {
-  long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k < count) Store<S>::st(out + k, in[k]);
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < count; k += (long)gridDim.x * blockDim.x)
+    Store<S>::st(out + k, in[k]);
 }
 template <typename S>
 void launch_store_to64(const SP<S>* in, cplx<double>* out, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_store_to64<S>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, out, count);
+  hipLaunchKernelGGL(k_store_to64<S>, dim3(grid1d(count)), dim3(256), 0, st, in, out, count);
 }
 template <typename S>
 void launch_store_from64(const cplx<double>* in, SP<S>* out, long count, hipStream_t st) {
-  hipLaunchKernelGGL(k_store_from64<S>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, out, count);
+  hipLaunchKernelGGL(k_store_from64<S>, dim3(grid1d(count)), dim3(256), 0, st, in, out, count);
 }
 
 #define INST_TS(T, S)                                                                                            \

@@ -108,6 +108,13 @@ void launch_lincomb(const cplx<double>* a, const cplx<double>* b, cplx<double>* 
 // streaming copy of bytes (a multiple of 16)
 void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// workgroups of 256 for an elementwise launch over count elements: one
+// element per thread up to 2^28 elements, beyond that the kernels stride
+// by the grid (a launch holds fewer than 2^32 threads)
+inline unsigned grid1d(size_t count) {
+  const size_t g = (count + 255) / 256;
+  return (unsigned)(g == 0 ? 1 : (g > ((size_t)1 << 20) ? ((size_t)1 << 20) : g));
+}
 
 struct KrylovDev {
   int m = 0, nrhs = 0;

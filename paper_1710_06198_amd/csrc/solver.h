@@ -149,6 +149,11 @@ struct HierBase {
   virtual void setup(double mu) = 0;
   virtual void setup_iteration() = 0;
   virtual void rebuild() = 0;
+  // memory plan: drop the setup's work buffers (and the fine test vectors
+  // unless the parameters keep them); has_test_vectors() tells whether
+  // setup updates are still possible
+  virtual void release_setup_workspace() {}
+  virtual bool has_test_vectors() const { return true; }
   virtual void ensure(int nrhs) = 0;
   virtual bool is_double() const = 0;
   // typed entry points; only the matching precision is implemented
@@ -231,6 +236,10 @@ struct Hier : HierBase {
   void smooth_vectors(int l);
   void setup_iteration() override;
   void rebuild() override;
+  void release_setup_workspace() override;
+  bool has_test_vectors() const override { return nlev < 2 || tv0.p != nullptr; }
+  void setup_workspace();
+  int chunk(int l) const;
   bool is_double() const override { return std::is_same<T, double>::value; }
   void precond_d(const cplx<double>* v, cplx<double>* z, int nrhs, const double* mu) override;
   void precond_f(const cplx<float>* v, cplx<float>* z, int nrhs, const double* mu) override;

@@ -268,7 +268,10 @@ template <typename T, typename S>
 void Hier<T, S>::ensure(int nrhs) {
   const tmamg_params& p = c->par;
   hipStream_t st = c->st;
-  int need = std::max(nrhs, std::max(nv0, nv1));
+  // the setup batches chunk(l) test vectors (all of them unless the
+  // memory plan asks for fewer)
+  int need = std::max(nrhs, nlev >= 2 ? chunk(0) : 0);
+  if (nlev >= 3) need = std::max(need, chunk(1));
   if (need <= cap) return;
   drop_graphs();
   cap = need;
@@ -531,17 +534,15 @@ void Hier<T, S>::setup(double mu) {
   tv0.alloc((size_t)nv0 * n0);
   P0.alloc((size_t)nv0 * n0);
   Dc1.alloc((size_t)g1.V * 9 * d1 * d1);
-  // FP64 scratch of the orthonormalisation (the fine level's Cholesky QR needs none)
-  size_t p64 = gs_fine_needs_fp64_copy(nv0) ? (size_t)nv0 * n0 : 0;
+  size_t p64 = 0;
   if (nlev >= 3) {
     tv1.alloc((size_t)nv1 * g1.V * d1);
     P1.alloc((size_t)nv1 * g1.V * d1);
     Dc2.alloc((size_t)g2.V * 9 * d2 * d2);
-    p64 = std::max(p64, (size_t)nv1 * g1.V * d1);
   }
-  P64.alloc(std::max<size_t>(p64, 1));
-  ensure(std::max(nv0, nv1));
-  tvtmp.alloc((size_t)nv0 * n0);
+  (void)p64;
+  ensure(std::max(chunk(0), nlev >= 3 ? chunk(1) : 0));
+  setup_workspace();
   mu_setup.alloc(std::max(nv0, nv1));
   int nmax = std::max(nv0, nv1);
   hipLaunchKernelGGL(k_fill_double, dim3(1), dim3(64), 0, st, mu_setup.p, mu, nmax);
@@ -558,23 +559,58 @@ void Hier<T, S>::setup(double mu) {
     build(1);
   }
   for (int it = 0; it < p.setup_iters; ++it) setup_iteration();
+  release_setup_workspace();
 }
 
-// Initial phase: v <- SAP(v) from zero, normalised, init_smooth times.
+// Test vectors treated at once on level l (the memory plan's setup_chunk).
+template <typename T, typename S>
+int Hier<T, S>::chunk(int l) const {
+  const int nv = l == 0 ? nv0 : nv1;
+  const int ch = c->par.setup_chunk;
+  return ch > 0 && ch < nv ? ch : nv;
+}
+
+// The setup's work buffers: the fine level's batch of smoothed or cycled
+// test vectors and the FP64 scratch of the orthonormalisation (the fine
+// level's Cholesky QR needs none for the vector counts used here).
+template <typename T, typename S>
+void Hier<T, S>::setup_workspace() {
+  const long n0 = 12 * c->fg.V;
+  size_t p64 = gs_fine_needs_fp64_copy(nv0) ? (size_t)nv0 * n0 : 0;
+  if (nlev >= 3) p64 = std::max(p64, (size_t)nv1 * g1.V * d1);
+  if (!P64.p) P64.alloc(std::max<size_t>(p64, 1));
+  if (!tvtmp.p) tvtmp.alloc((size_t)chunk(0) * n0);
+}
+
+template <typename T, typename S>
+void Hier<T, S>::release_setup_workspace() {
+  HIPCHK(hipStreamSynchronize(c->st));
+  tvtmp.release();
+  P64.release();
+  gal_ws.release();
+  if (!c->par.keep_test_vectors) tv0.release();
+}
+
+// Initial phase: v <- SAP(v) from zero, normalised, init_smooth times
+// (test vectors in batches of chunk(l), each treated alone).
 template <typename T, typename S>
 void Hier<T, S>::smooth_vectors(int l) {
   const tmamg_params& p = c->par;
   hipStream_t st = c->st;
-  long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
-  int nv = l == 0 ? nv0 : nv1;
+  const long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
+  const int nv = l == 0 ? nv0 : nv1, ch = chunk(l);
   cplx<T>* v = l == 0 ? tv0.p : tv1.p;
   cplx<T>* w = l == 0 ? tvtmp.p : tmp1.p;
   for (int k = 0; k < p.init_smooth; ++k) {
-    launch_fill_zero(w, (size_t)nv * n * sizeof(cplx<T>), st);
-    if (l == 0) sap(0, v, w, nv, mu_setup.p, p.sap_sweeps[0]);
-    else sap_level1(v, w, nv, mu_setup.p, p.sap_sweeps[1]);
-    HIPCHK(hipMemcpyAsync(v, w, (size_t)nv * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
-    normalize(v, n, nv);
+    for (int i0 = 0; i0 < nv; i0 += ch) {
+      const int nc = std::min(ch, nv - i0);
+      cplx<T>* vc = v + (size_t)i0 * n;
+      launch_fill_zero(w, (size_t)nc * n * sizeof(cplx<T>), st);
+      if (l == 0) sap(0, vc, w, nc, mu_setup.p, p.sap_sweeps[0]);
+      else sap_level1(vc, w, nc, mu_setup.p, p.sap_sweeps[1]);
+      HIPCHK(hipMemcpyAsync(vc, w, (size_t)nc * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+      normalize(vc, n, nc);
+    }
   }
 }
 
@@ -584,14 +620,19 @@ void Hier<T, S>::smooth_vectors(int l) {
 template <typename T, typename S>
 void Hier<T, S>::setup_iteration() {
   hipStream_t st = c->st;
+  setup_workspace();
   for (int l = 0; l < nlev - 1; ++l) {
-    long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
-    int nv = l == 0 ? nv0 : nv1;
+    const long n = l == 0 ? 12 * c->fg.V : g1.V * d1;
+    const int nv = l == 0 ? nv0 : nv1, ch = chunk(l);
     cplx<T>* v = l == 0 ? tv0.p : tv1.p;
     cplx<T>* w = l == 0 ? tvtmp.p : tmp1.p;
-    precond(l, v, w, nv, mu_setup.p);
-    HIPCHK(hipMemcpyAsync(v, w, (size_t)nv * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
-    normalize(v, n, nv);
+    for (int i0 = 0; i0 < nv; i0 += ch) {
+      const int nc = std::min(ch, nv - i0);
+      cplx<T>* vc = v + (size_t)i0 * n;
+      precond(l, vc, w, nc, mu_setup.p);
+      HIPCHK(hipMemcpyAsync(vc, w, (size_t)nc * n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, st));
+      normalize(vc, n, nc);
+    }
     build(l);
     if (l + 2 < nlev) galerkin_only(l + 1);
   }

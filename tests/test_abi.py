@@ -105,6 +105,8 @@ int main(void) {
   F(tmamg_params, restart) F(tmamg_params, max_iter) F(tmamg_params, precision) F(tmamg_params, storage)
   F(tmamg_params, inner_tol) F(tmamg_params, seed) F(tmamg_params, use_graph)
   F(tmamg_params, nd_coarse_coupling)
+  F(tmamg_params, setup_chunk)
+  F(tmamg_params, keep_test_vectors)
   F(tmamg_info, status) F(tmamg_info, outer_iters) F(tmamg_info, cycles) F(tmamg_info, true_rel_resid)
   F(tmamg_info, t_setup_s) F(tmamg_info, t_solve_s) F(tmamg_info, l2_iters_total)
   F(tmamg_info, coarsest_iters_total)

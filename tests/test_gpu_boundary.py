@@ -165,3 +165,42 @@ def test_barrier_timeout_becomes_a_status():
     assert again.status == 0
     assert norm(field(b[0]) - op.apply(field(x.cpu()[0]), 0.01)) / norm(field(b[0])) <= 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_setup_memory_plan(c1, levels):
+    """The memory plan: the setup treating the test vectors in chunks of 5
+    (12 and 16 vectors: chunks of 5, 5, 2 and 5, 5, 5, 1) and releasing them
+    afterwards gives the hierarchy of the all-at-once setup (FP64: the same
+    vectors up to the rounding of differently batched coarse solves), solves
+    to the same tolerance in the same number of outer iterations, and
+    refuses setup updates once the test vectors are gone."""
+    w, m0, U, Ud, op = c1
+    say("memory plan,", levels, "levels")
+    mk = (lambda **kw: params(w, **kw)) if levels == 2 else three_level_params
+    ref = tm.Solver(w.dims, mk())
+    ref.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    s = tm.Solver(w.dims, mk(setup_chunk=5, keep_test_vectors=0))
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    for what, level in ((0, 0), (1, 1)):
+        a = torch.empty(ref.params.nv[0] * ref.volume * 12 if what == 0 else
+                        ref.level_info(1)[0] * 9 * ref.level_info(1)[1] ** 2, dtype=torch.complex128, device=DEV)
+        b = torch.empty_like(a)
+        ref.export(what, level, a)
+        s.export(what, level, b)
+        d = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
+        say(f"  {'P' if what == 0 else 'D_c'} level {level}: rel. difference {d:.2e}")
+        assert d < 1e-8
+    psi, psid = spinors(w.dims, 4401, 1)
+    xr, xs = torch.empty_like(psid), torch.empty_like(psid)
+    ir = ref.solve(psid, xr, tol=1e-10)
+    i_s = s.solve(psid, xs, tol=1e-10)
+    res = norm(field(psi[0]) - op.apply(field(xs.cpu()[0]), w.mu)) / norm(field(psi[0]))
+    say(f"  outer iterations {ir.outer_iters} / {i_s.outer_iters}; oracle residual {res:.2e}")
+    assert i_s.status == 0 and res <= 1e-10 and abs(i_s.outer_iters - ir.outer_iters) <= 1
+    with pytest.raises(tm.TmamgError) as e:
+        s.setup_update(Ud, 1)
+    assert e.value.status == -5   # TMAMG_ESTATE
+    ref.setup_update(Ud, 1)
+    ref.close()
+    s.close()
