@@ -1605,8 +1605,12 @@ bool launch_coarsest_gmres(const CoarseGeom& g, int d, const SP<S>* Dc, const cp
   if (try_site_gmres<T, S>(g, d, Dc, b, x, nrhs, mu_dev, m, reltol, Vbasis, dws, dws_cap, iws, iws_cap, st))
     return true;
   // the shared-site kernel serialises right-hand sides inside a workgroup:
-  // wide batches go to the generic Krylov path
-  if (nrhs > 2) return false;
+  // wide batches go to the generic Krylov path; so do large coarsest
+  // lattices, whose D_c no longer stays in cache between iterations and
+  // which its few resident workgroups would stream at a fraction of the
+  // device's bandwidth (8192 sites at d = 64: 4 ms per iteration with 64
+  // workgroups, against about 0.4 ms for the full-device launches)
+  if (nrhs > 2 || g.V > 2048) return false;
   const int Gmax = coarsest_groups(g.V);
   const size_t coef_bytes = 2 * 2 * sizeof(double) * (size_t)nrhs * (m + 2);
   if (coef_bytes > 65536) return false;
