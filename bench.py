@@ -11,11 +11,14 @@ systems (D D^dag + sigma_k) x = b (sigma_k log-spaced in [1e-5, 1], one
 Gaussian source) as a second batch of two-step solves, every result to
 relative residual 1e-10.  The plain FP64 DD-alpha-AMG on the same GPU runs
 the same job (warmed up and timed the same way) for the speed-up; the fine
-SAP (the kernel with the largest share of the job) and the fine stencil
-are measured against the HBM roofline with HIP events on the library's
-stream; the oracle's cost of the job is estimated from its own timings.
+SAP (the kernel with the largest share of the job, bound by FP32 vector
+issue) is measured against the FP32 vector peak and the fine stencil
+against the HBM roofline, with HIP events on the library's stream; the
+oracle's cost of the job is estimated from its own timings.  Other
+workloads: c2 (24^3 x 48, one right-hand side), c4 (16^3 x 32, force), c5
+(64^3 x 128, the paper's volume: setup, 4 right-hand sides and a force).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c4|c5]
 """
 from __future__ import annotations
 
@@ -30,30 +33,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_fp32_c2_traffic.md")
+STENCIL_TRAFFIC = {"c2": os.path.join(ROOT, "profiles", "dslash_fp32_c2_traffic.md"),
+                   "c3": os.path.join(ROOT, "profiles", "dslash_fp32_c3_traffic.md")}
 STENCIL_SOURCES = ("fine_op.hip", "su3.h", "common.h")
 
 
 def stencil_traffic(workload_name):
-    """HBM bytes per stencil launch from the committed counter record
-    (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel's readings), or
-    None when the record is for another workload or the stencil sources
-    changed since the counters were taken."""
-    import hashlib
-    if workload_name != "c2" or not os.path.exists(TRAFFIC_RECORD):
-        return None
-    rec = None
-    for line in open(TRAFFIC_RECORD):
-        if line.startswith("traffic_record:"):
-            rec = json.loads(line.split(":", 1)[1])
-    if rec is None:
-        return None
-    h = hashlib.sha256()
-    for f in STENCIL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1710_06198_amd", "csrc", f), "rb").read())
-    if h.hexdigest()[:16] != rec["source_sha16"]:
-        return None
-    return rec["bytes_per_launch"]
+    """HBM bytes per FP32 stencil launch (one right-hand side) from the
+    workload's committed counter record, or None (see kernel_traffic)."""
+    rec = STENCIL_TRAFFIC.get(workload_name)
+    return kernel_traffic(rec, STENCIL_SOURCES, workload_name, workload_name) if rec else None
 
 
 MFMA_BF16_PEAK_TFS = 2500.0   # MI355X dense bf16 matrix peak
@@ -267,31 +256,78 @@ def _timed(fn):
 
 
 SAP_BYTES_FIXED, SAP_BYTES_RHS = 576, 384
+FP32_VECTOR_PEAK_TFS = 157.3     # MI355X FP32 vector peak (packed FMA)
+FP32_NONPACKED_PEAK_TFS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz
+# Algorithmic FP32 flops of one SAP launch per site of the colour and right-
+# hand side (FMA = 2 flops; a complex product 6, a complex multiply-add 8):
+#   one hop: spin projection 12, two SU(3) x colour vector products 132,
+#     reconstruction into the accumulator 48 -> 192
+#   clover, two 6x6 Hermitian blocks 528; twisted mass 48
+#   block residual eta - D z: 528 + 48 + 8 x 192 + 24 = 2136
+#   MR step: D_B rho with the hops inside a 4^4 block (6 per site on
+#     average) 1728, (q, q) 48, (q, rho) 96, e += alpha rho and
+#     rho -= alpha q 192 -> 2064
+SAP_FLOPS_RESIDUAL, SAP_FLOPS_MR_STEP = 2136, 2064
+SAP_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sap_fine_fp32_c3_traffic.md")
+SAP_SOURCES = ("fine_op.hip", "fine_site.h", "su3.h", "common.h")
 
 
-def sap_roofline(tm, solver, V, nrhs, reps):
+def kernel_traffic(record, sources, workload_name, want_workload):
+    """HBM bytes per launch from a committed counter record (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy kernel's readings), or None when the record
+    is for another workload or the kernel's sources changed since."""
+    import hashlib
+    if workload_name != want_workload or not os.path.exists(record):
+        return None
+    rec = None
+    for line in open(record):
+        if line.startswith("traffic_record:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_1710_06198_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha16"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def sap_roofline(tm, solver, V, nrhs, reps, mr_steps=4, workload_name="c3"):
     """The fine SAP kernel (one colour of blocks, all MR steps) for nrhs
-    right-hand sides, timed with HIP events on the library's stream.
-    Algorithmic bytes per site of the colour: links and clover once (576 B
-    FP32), and per right-hand side the source, the iterate read and written
-    and the neighbouring iterate for the block residual (4 x 96 B)."""
+    right-hand sides, timed with HIP events on the library's stream.  It is
+    bound by FP32 vector issue, not by HBM (about 24 flops per algorithmic
+    byte, against the chip's 20 at the packed-FMA peak): achieved is the
+    algorithmic flop rate against the FP32 vector peak; the non-packed FMA
+    rate (the instructions this build emits) is given beside it, and so is
+    the HBM view (algorithmic bytes per site of the colour: links and
+    clover once, 576 B, and per right-hand side the source, the iterate
+    read and written and the neighbouring iterate, 4 x 96 B)."""
     ms = solver.time_kernel(tm.K_SAP0, nrhs, reps)
     sites = V // 2
+    flops = sites * nrhs * (SAP_FLOPS_RESIDUAL + mr_steps * SAP_FLOPS_MR_STEP)
+    tfs = flops / (ms * 1e-3) / 1e12
     byts = sites * (SAP_BYTES_FIXED + SAP_BYTES_RHS * nrhs)
     gbs = byts / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_sap_fine<float, 3> (fine SAP, one colour, 4 MR steps per block)",
-            "rhs": nrhs, "sites_per_launch": sites,
-            "bytes_per_launch": byts, "bytes_per_site": f"{SAP_BYTES_FIXED} + {SAP_BYTES_RHS} x rhs",
+    return {"bound": "alu", "achieved": tfs, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": tfs / FP32_VECTOR_PEAK_TFS,
+            "traffic": kernel_traffic(SAP_TRAFFIC_RECORD, SAP_SOURCES, workload_name, "c3"),
+            "kernel": "k_sap_fine<float, 3> (fine SAP, one colour, 4 MR steps per block)",
+            "rhs": nrhs, "sites_per_launch": sites, "flops_per_launch": flops,
+            "flops_per_site_rhs": SAP_FLOPS_RESIDUAL + mr_steps * SAP_FLOPS_MR_STEP,
+            "peak_nonpacked_fp32": FP32_NONPACKED_PEAK_TFS, "frac_nonpacked": tfs / FP32_NONPACKED_PEAK_TFS,
+            "hbm_view": {"bytes_per_launch": byts, "bytes_per_site": f"{SAP_BYTES_FIXED} + {SAP_BYTES_RHS} x rhs",
+                         "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS},
             "ms_per_launch": ms}
 
 
-def stencil_roofline(tm, solver, V, reps, nrhs=1):
+def stencil_roofline(tm, solver, V, reps, nrhs=1, workload_name=None):
     ms = solver.time_kernel(tm.K_DSLASH32, nrhs, reps)
     byts = V * (576 + 192 * nrhs)
     gbs = byts / (ms * 1e-3) / 1e9
     return {"kernel": "k_dslash<float>" + (", true" if nrhs > 1 else ""), "rhs": nrhs, "ms": ms,
-            "bytes_per_launch": byts, "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+            "bytes_per_launch": byts, "achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": stencil_traffic(workload_name) if nrhs == 1 else None}
 
 
 def bench_batched(args):
@@ -368,7 +404,7 @@ def bench_batched(args):
     sap = sap_roofline(tm, mixed, V, npt, 10)
     log(f"[bench] fine SAP roofline (12 RHS): {sap}")
     sap_other = {n: round(mixed.time_kernel(tm.K_SAP0, n, 5), 4) for n in (1, nsh, w.nv[0])}
-    sten = stencil_roofline(tm, mixed, V, 20)
+    sten = stencil_roofline(tm, mixed, V, 20, workload_name="c3")
     sten12 = stencil_roofline(tm, mixed, V, 5, npt)
     log(f"[bench] stencil: {sten} / 12 RHS {sten12}")
     kern = {}
