@@ -316,9 +316,12 @@ TM_D void dslash_block_rhs(const FineOp<T>& op, const cplx<T>* __restrict__ inr,
                        EARLY && !w1 ? fb1 : nullptr);
   stage_dir<2, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
   stage_dir<3, STREAM>(op, inr, psl, hb, s, loc, c, psi, acc);
+  // the output is written non-temporally: its lines would otherwise take
+  // L2 from the neighbouring blocks' face spinors (32^3 x 64: one RHS
+  // 0.375 -> 0.351 ms, 12 RHS 3.16 -> 3.10 ms)
   cplx<T>* o = outr + tsite(s, 12);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) o[k * FT] = acc[k];
+  for (int k = 0; k < 12; ++k) st_stream(o + k * FT, acc[k]);
 }
 
 // A single right-hand side streams links and clover (non-temporal loads).

@@ -90,6 +90,12 @@ template <typename T> TM_D cplx<T> ld_stream(const cplx<T>* p) {
   const typename Vec2<T>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename Vec2<T>::type*>(p));
   return mk<T>(v.x, v.y);
 }
+template <typename T> TM_D void st_stream(cplx<T>* p, cplx<T> v) {
+  typename Vec2<T>::type x;
+  x.x = v.re;
+  x.y = v.im;
+  __builtin_nontemporal_store(x, reinterpret_cast<typename Vec2<T>::type*>(p));
+}
 template <int MU, typename T>
 TM_D M3<T> load_link_stream(const cplx<T>* __restrict__ links, unsigned s, long V) {
   M3<T> u;
