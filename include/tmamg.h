@@ -365,7 +365,9 @@ tmamg_status tmamg_time_kernel(tmamg_ctx* ctx, int kernel, int nrhs, int reps, d
  *                            0 vector ALU, 1 matrix cores (16 RHS tiles)
  *   TMAMG_TUNE_SAP1          level-1 SAP, same key; 0 vector ALU, 1 matrix
  *                            cores, 2 matrix cores with a register budget for
- *                            four workgroups per CU
+ *                            four workgroups per CU, 3 matrix cores with one
+ *                            workgroup per SAP block (blocks of at most 16
+ *                            sites, d <= 48; the colour in one launch)
  *   TMAMG_TUNE_RESTRICT0,
  *   TMAMG_TUNE_PROLONG0      a = N_v, b = fine sites; 0 vector ALU, 1 matrix cores
  *   TMAMG_TUNE_SAP0          fine SAP, a = block sites, b = fine sites;

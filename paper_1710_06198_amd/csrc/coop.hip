@@ -165,9 +165,44 @@ template <typename T, typename S, int D> constexpr bool mf_ok() {
 // vst: [16][stride] staged inputs, block b's D values at slot[b] * D (slot
 // == nullptr: slot b); on return (after a barrier) the partial sums of wave
 // w are at vst[q * stride + (1 + w) D + i] (slots 1..4 must exist)
+// The D_c fragments a wave needs first, loaded ahead of the staging of the
+// inputs so that their latency overlaps it: wave w takes the blocks
+// b = w (mod 4) of the mask, 4 bits each in `blocks`.
 template <int D>
-TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsigned mask, int stride = 9 * D,
-                       const int* slot = nullptr) {
+struct MfPre {
+  static constexpr int MT = D / 16, KS = D / 16;
+  unsigned an[KS][MT][4];
+  int blocks, nb;
+};
+template <int D>
+TM_D void mf_load_block(const unsigned* __restrict__ Du, int b, unsigned (&an)[D / 16][D / 16][4]) {
+  constexpr int MT = D / 16, KS = D / 16;
+  const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  const unsigned* dp = Du + (size_t)(b * D + 4 * lk) * D + lr;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) an[ks][mt][e] = dp[(16 * ks + e) * D + 16 * mt];
+}
+template <int D>
+TM_D void mf_prefetch(const bf16pair* __restrict__ Dm, unsigned mask, MfPre<D>& pre) {
+  const int w = threadIdx.x >> 6;
+  pre.blocks = 0;
+  pre.nb = 0;
+  for (int b = w; b < 9; b += 4)
+    if ((mask >> b) & 1u) pre.blocks |= b << (4 * pre.nb++);
+  if (pre.nb > 0) mf_load_block<D>(reinterpret_cast<const unsigned*>(Dm), pre.blocks & 15, pre.an);
+}
+
+// vst: [16][stride] staged inputs, block b's D values at slot[b] * D (slot
+// == nullptr: slot b); on return (after a barrier) the partial sums of wave
+// w are at vst[q * stride + (1 + w) D + i] (slots 1..4 must exist).  pre
+// holds the wave's first D_c fragments (mf_prefetch).
+template <int D>
+TM_D void site_mv_mfma_pre(const bf16pair* __restrict__ Dm, cplx<float>* vst, MfPre<D>& pre, int stride = 9 * D,
+                           const int* slot = nullptr) {
   constexpr int MT = D / 16, KS = D / 16;
   const int K9 = stride;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
@@ -175,34 +210,18 @@ TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsign
   mf_f4 accr[MT], acci[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = mf_f4{0.f, 0.f, 0.f, 0.f};
-  // this wave's blocks b = w (mod 4) that are in the mask, 4 bits each
-  int blocks = 0, nb = 0;
-  for (int b = w; b < 9; b += 4)
-    if ((mask >> b) & 1u) blocks |= b << (4 * nb++);
   // all D_c fragments of the next block are loaded while the current block
   // runs on the matrix cores
-  unsigned an[KS][MT][4];
-  auto load_a = [&](int ib) {
-    const int b = (blocks >> (4 * ib)) & 15;
-    const unsigned* dp = Du + (size_t)(b * D + 4 * lk) * D + lr;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) an[ks][mt][e] = dp[(16 * ks + e) * D + 16 * mt];
-  };
-  if (nb > 0) load_a(0);
-  for (int ib = 0; ib < nb; ++ib) {
+  for (int ib = 0; ib < pre.nb; ++ib) {
     unsigned ac[KS][MT][4];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ac[ks][mt][e] = an[ks][mt][e];
-    if (ib + 1 < nb) load_a(ib + 1);
-    const int b = (blocks >> (4 * ib)) & 15;
+        for (int e = 0; e < 4; ++e) ac[ks][mt][e] = pre.an[ks][mt][e];
+    if (ib + 1 < pre.nb) mf_load_block<D>(Du, (pre.blocks >> (4 * (ib + 1))) & 15, pre.an);
+    const int b = (pre.blocks >> (4 * ib)) & 15;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int j0 = 16 * ks + 4 * lk;
@@ -238,6 +257,13 @@ TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsign
   __syncthreads();
 }
 template <int D>
+TM_D void site_mv_mfma(const bf16pair* __restrict__ Dm, cplx<float>* vst, unsigned mask, int stride = 9 * D,
+                       const int* slot = nullptr) {
+  MfPre<D> pre;
+  mf_prefetch<D>(Dm, mask, pre);
+  site_mv_mfma_pre<D>(Dm, vst, pre, stride, slot);
+}
+template <int D>
 TM_D cplx<float> site_mv_mfma_row(const cplx<float>* vst, int q, int i, int stride = 9 * D) {
   const cplx<float>* p = vst + q * stride + D + i;
   return (p[0] + p[D]) + (p[2 * D] + p[3 * D]);
@@ -257,6 +283,8 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mf(CoarseGeom g, const bf1
   const long VD = g.V * D;
   const int t = threadIdx.x;
   const C4 c = cc_coords(g, y);
+  MfPre<D> pre;   // first D_c fragments ahead of the staging
+  mf_prefetch<D>(Dc + y * 9L * D * D, 0x1FFu, pre);
   __shared__ long src9[9];
   stage_sources(g, y, c, src9);
   for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
@@ -267,7 +295,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_mf(CoarseGeom g, const bf1
     *reinterpret_cast<float4*>(vst + k) = v;
   }
   __syncthreads();
-  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, 0x1FFu);
+  site_mv_mfma_pre<D>(Dc + y * 9L * D * D, vst, pre);
   for (int e = t; e < MF_NR * D; e += 256) {
     const int q = e / D, i = e - q * D, r = r0 + q;
     if (r >= nrhs) continue;
@@ -556,6 +584,8 @@ __global__ void __launch_bounds__(256, MINB) k_sap1_resid_mf(SapArgs a, const bf
   C4 c, lc;
   cblk_site(a.cb, a.bl[bi], sl, c, lc);
   const long y = cc_index(g, c);
+  MfPre<D> pre;   // first D_c fragments ahead of the staging
+  mf_prefetch<D>(Dc + y * 9L * D * D, 0x1FFu, pre);
   __shared__ long src9[9];
   stage_sources(g, y, c, src9);
   for (int k2 = t; k2 < MF_NR * 9 * D / 2; k2 += 256) {   // two complex values per 16-byte access
@@ -566,7 +596,7 @@ __global__ void __launch_bounds__(256, MINB) k_sap1_resid_mf(SapArgs a, const bf
     *reinterpret_cast<float4*>(vst + k) = v;
   }
   __syncthreads();
-  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, 0x1FFu);
+  site_mv_mfma_pre<D>(Dc + y * 9L * D * D, vst, pre);
   for (int e = t; e < MF_NR * D; e += 256) {
     const int q = e / D, i = e - q * D, r = r0 + q;
     if (r >= a.nrhs) continue;
@@ -602,12 +632,17 @@ __global__ void __launch_bounds__(256, MINB) k_sap1_mr_mf(SapArgs a, const bf16p
   C4 c, lc;
   cblk_site(cb, blk, sl, c, lc);
   const long y = cc_index(g, c);
+  // the blocks inside the SAP block, from the local coordinates (the same
+  // test as stage_block_sources); the first D_c fragments are requested
+  // before anything else so that their latency overlaps the staging
+  unsigned mask = 1u;
+  for (int b = 1; b < 9; ++b)
+    if (cblk_nbr(cb, lc, hop_mu(b), hop_step(b)) >= 0) mask |= 1u << b;
+  MfPre<D> pre;
+  mf_prefetch<D>(Dc + y * 9L * D * D, mask, pre);
   if (!first) block_alpha<float, MF_NR>(part_in, bi, cb.nbs, a.nrhs, r0, alpha_s);
   __shared__ long src9[9];
   stage_block_sources(g, cb, blk, y, lc, src9);
-  unsigned mask = 0u;
-  for (int b = 0; b < 9; ++b)
-    if (src9[b] >= 0) mask |= 1u << b;
   if (t == 0) {
     int ns = 0;
     for (int b = 0; b < 9; ++b) {
@@ -637,7 +672,7 @@ __global__ void __launch_bounds__(256, MINB) k_sap1_mr_mf(SapArgs a, const bf16p
     *reinterpret_cast<float4*>(vst + k) = v;
   }
   __syncthreads();
-  site_mv_mfma<D>(Dc + y * 9L * D * D, vst, mask, stride, slot9);
+  site_mv_mfma_pre<D>(Dc + y * 9L * D * D, vst, pre, stride, slot9);
   // wave q: right-hand sides r0 + q, r0 + q + 4, ...; lanes over rows
   const int wq = t >> 6, lane = t & 63;
   for (int q = wq; q < MF_NR; q += 4) {
@@ -668,6 +703,244 @@ __global__ void __launch_bounds__(256, MINB) k_sap1_mr_mf(SapArgs a, const bf16p
       part_out[3 * u + 2] = qim;
     }
   }
+}
+
+// ------------------------------------------------------------------ level-1 SAP, one workgroup per block
+// The whole colour's block solves in one launch: a workgroup of 8 waves
+// takes one SAP block (at most 16 coarse sites) and 16 right-hand sides,
+// forms the block residual rho = eta - D_c(mu) z on the matrix cores (the
+// inputs of neighbouring blocks straight from memory), keeps rho of all
+// the block's sites in LDS, and runs the MR steps with the step sizes from
+// workgroup reductions (no per-step launches, no per-site partial sums in
+// memory, the neighbours' rho read from LDS instead of being staged per
+// site).  z is updated in place after every step.  Each wave owns up to
+// two sites of the block; its D x 16 products stay in registers.
+constexpr int SB_WAVES = 8;
+constexpr int SB_SITES_PER_WAVE = 2;
+constexpr int SB_MAX_SITES = SB_WAVES * SB_SITES_PER_WAVE;
+
+// accr/acci += sum over the blocks b of mask of D_b(site) x input_b, with
+// input_b(j0 + e) for this lane's right-hand side given by in(b, j0, v4);
+// the D_c fragments of the next block load while the current one runs
+template <int D, typename In>
+TM_D void mf_site_accumulate(const unsigned* __restrict__ Du, unsigned mask, In in, mf_f4 (&accr)[D / 16],
+                             mf_f4 (&acci)[D / 16]) {
+  constexpr int MT = D / 16, KS = D / 16;
+  const int l = threadIdx.x & 63, lk = l >> 4;
+  unsigned an[KS][MT][4];
+  int b = 0;
+  while (b < 9 && !((mask >> b) & 1u)) ++b;
+  if (b < 9) mf_load_block<D>(Du, b, an);
+  while (b < 9) {
+    unsigned ac[KS][MT][4];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ac[ks][mt][e] = an[ks][mt][e];
+    int nb = b + 1;
+    while (nb < 9 && !((mask >> nb) & 1u)) ++nb;
+    if (nb < 9) mf_load_block<D>(Du, nb, an);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      cplx<float> v4[4];
+      in(b, 16 * ks + 4 * lk, v4);
+      const MfSplit bb = mf_split(v4);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        mf_s4 ar, ai;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ar[e] = (short)(ac[ks][mt][e] & 0xffffu);
+          ai[e] = (short)(ac[ks][mt][e] >> 16);
+        }
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr[mt], 0, 0, 0);
+        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci[mt], 0, 0, 0);
+        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci[mt], 0, 0, 0);
+      }
+    }
+    b = nb;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(SB_WAVES * 64, 1) k_sap1_block_mf(SapArgs a, const bf16pair* __restrict__ Dc,
+                                                                      const cplx<float>* __restrict__ eta,
+                                                                      cplx<float>* __restrict__ z,
+                                                                      const double* __restrict__ mu_dev, int mr) {
+  constexpr int MT = D / 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<float>* rho = reinterpret_cast<cplx<float>*>(smem_raw);   // [site of the block][16][D]
+  __shared__ double red[SB_WAVES][MF_NR][3];
+  const CoarseGeom& g = a.g;
+  const CBlk& cb = a.cb;
+  const long VD = g.V * D;
+  const int nbs = cb.nbs;
+  const int ng = (a.nrhs + MF_NR - 1) / MF_NR;
+  const int grp = blockIdx.x % ng, bi = blockIdx.x / ng;
+  const int r0 = grp * MF_NR, blk = a.bl[bi];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+  const int r = r0 + lr;
+  const bool rv = r < a.nrhs;
+  const float mu = rv ? (float)mu_dev[r] : 0.f;
+  // this wave's sites of the block: sl = w + SB_WAVES * k
+  long ys[SB_SITES_PER_WAVE];
+  C4 lcs[SB_SITES_PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < SB_SITES_PER_WAVE; ++k) {
+    const int sl = w + SB_WAVES * k;
+    ys[k] = -1;
+    if (sl < nbs) {
+      C4 c;
+      cblk_site(cb, blk, sl, c, lcs[k]);
+      ys[k] = cc_index(g, c);
+    }
+  }
+  // ---- block residual: rho = eta - D_c(mu) z, all nine blocks
+#pragma unroll
+  for (int k = 0; k < SB_SITES_PER_WAVE; ++k) {
+    if (ys[k] < 0) continue;   // uniform across the wave
+    const long y = ys[k];
+    const C4 c = cc_coords(g, y);
+    long src[9];
+    src[0] = y;
+#pragma unroll
+    for (int b = 1; b < 9; ++b) src[b] = cc_nbr(g, c, hop_mu(b), hop_step(b));
+    mf_f4 accr[MT], acci[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) accr[mt] = acci[mt] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    const unsigned* Du = reinterpret_cast<const unsigned*>(Dc + y * 9L * D * D);
+    mf_site_accumulate<D>(Du, 0x1FFu, [&](int b, int j0, cplx<float>* v4) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v4[e] = rv ? z[r * VD + src[b] * D + j0 + e] : mk(0.f, 0.f);
+    }, accr, acci);
+    const int sl = w + SB_WAVES * k;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * mt + 4 * lk + v;
+        cplx<float> rh = mk(0.f, 0.f);
+        if (rv) {
+          cplx<float> acc = mk(accr[mt][v], acci[mt][v]);
+          acc += (i < D / 2 ? mu : -mu) * times_i(z[r * VD + y * D + i]);
+          rh = eta[r * VD + y * D + i] - acc;
+        }
+        rho[(sl * MF_NR + lr) * D + i] = rh;
+      }
+  }
+  __syncthreads();
+  // ---- MR steps on the block operator D_B
+  for (int it = 0; it < mr; ++it) {
+    mf_f4 qr_[SB_SITES_PER_WAVE][MT], qi_[SB_SITES_PER_WAVE][MT];
+    float sqq = 0.f, sre = 0.f, sim = 0.f;
+#pragma unroll
+    for (int k = 0; k < SB_SITES_PER_WAVE; ++k) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) qr_[k][mt] = qi_[k][mt] = mf_f4{0.f, 0.f, 0.f, 0.f};
+      if (ys[k] < 0) continue;
+      const int sl = w + SB_WAVES * k;
+      int nl[9];
+      unsigned mask = 1u;
+      nl[0] = sl;
+#pragma unroll
+      for (int b = 1; b < 9; ++b) {
+        nl[b] = cblk_nbr(cb, lcs[k], hop_mu(b), hop_step(b));
+        if (nl[b] >= 0) mask |= 1u << b;
+      }
+      const unsigned* Du = reinterpret_cast<const unsigned*>(Dc + ys[k] * 9L * D * D);
+      mf_site_accumulate<D>(Du, mask, [&](int b, int j0, cplx<float>* v4) {
+        const cplx<float>* p = rho + (nl[b] * MF_NR + lr) * D + j0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v4[e] = p[e];
+      }, qr_[k], qi_[k]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * mt + 4 * lk + v;
+          const cplx<float> rh = rho[(sl * MF_NR + lr) * D + i];
+          cplx<float> q = mk(qr_[k][mt][v], qi_[k][mt][v]);
+          q += (i < D / 2 ? mu : -mu) * times_i(rh);
+          qr_[k][mt][v] = q.re;
+          qi_[k][mt][v] = q.im;
+          acc_norm2(sqq, q);
+          acc_dotc(sre, sim, q, rh);
+        }
+    }
+    // the four lanes of a right-hand side (lk = 0..3), then the waves
+    sqq += __shfl_xor(sqq, 16, 64);
+    sre += __shfl_xor(sre, 16, 64);
+    sim += __shfl_xor(sim, 16, 64);
+    sqq += __shfl_xor(sqq, 32, 64);
+    sre += __shfl_xor(sre, 32, 64);
+    sim += __shfl_xor(sim, 32, 64);
+    if (lk == 0) {
+      red[w][lr][0] = sqq;
+      red[w][lr][1] = sre;
+      red[w][lr][2] = sim;
+    }
+    __syncthreads();   // every wave's products and reads of rho are done
+    double dq = 0, dre = 0, dim = 0;
+#pragma unroll
+    for (int ww = 0; ww < SB_WAVES; ++ww) {
+      dq += red[ww][lr][0];
+      dre += red[ww][lr][1];
+      dim += red[ww][lr][2];
+    }
+    const cplx<float> alpha = dq > 0 ? mk((float)(dre / dq), (float)(dim / dq)) : mk(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < SB_SITES_PER_WAVE; ++k) {
+      if (ys[k] < 0) continue;
+      const int sl = w + SB_WAVES * k;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * mt + 4 * lk + v;
+          cplx<float>& rh = rho[(sl * MF_NR + lr) * D + i];
+          if (rv) cfma(z[r * VD + ys[k] * D + i], alpha, rh);
+          cfms(rh, alpha, mk(qr_[k][mt][v], qi_[k][mt][v]));
+        }
+    }
+    __syncthreads();   // rho updated before the next step reads it; red free again
+  }
+}
+
+// one launch per colour and sweep; false when the blocks do not fit (more
+// than 16 sites or the LDS)
+template <int D>
+static bool sap_block_mf(const CoarseGeom& g, const CBlk& cb, const bf16pair* Dc, const cplx<float>* eta,
+                         cplx<float>* z, int nrhs, const double* mu, const int* const bl[2], const int nb[2],
+                         int sweeps, int mr, hipStream_t st) {
+  // d = 64 needs more registers than a wave of this kernel has (it spills)
+  const size_t lds = (size_t)cb.nbs * MF_NR * D * sizeof(cplx<float>);
+  if (D > 48 || cb.nbs > SB_MAX_SITES || lds > 144 * 1024) return false;
+  static bool attr = false;
+  if (!attr) {
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sap1_block_mf<D>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024));
+    attr = true;
+  }
+  SapArgs a;
+  a.g = g;
+  a.cb = cb;
+  a.nrhs = nrhs;
+  const int ng = (nrhs + MF_NR - 1) / MF_NR;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int col = 0; col < 2; ++col) {
+      if (nb[col] == 0) continue;
+      a.bl = bl[col];
+      hipLaunchKernelGGL((k_sap1_block_mf<D>), dim3((unsigned)(nb[col] * ng)), dim3(SB_WAVES * 64), lds, st, a, Dc,
+                         eta, z, mu, mr);
+    }
+  return true;
 }
 
 template <int D, int MINB>
@@ -748,6 +1021,14 @@ static bool sap_mf(const CoarseGeom& g, const CBlk& cb, const SP<S>* Dc, const c
                    cplx<T>* const rho[2], cplx<T>* const q[2], double* const part[2], hipStream_t st) {
   if constexpr (mf_ok<T, S, D>()) {
     const int tv = tune_get(TUNE_SAP1, D, g.V, nrhs);
+    // variant 3: one workgroup per SAP block, the whole colour in one launch
+    // (the rule's choice from 2 right-hand sides on where the blocks fit;
+    // 32^3 x 64, one sweep: 12 RHS 0.54 ms against 1.32 ms for variant 2,
+    // 2 RHS 0.50 ms against 0.86 ms on the vector ALU, 1 RHS 0.50 against 0.44)
+    if ((tv >= 0 ? tv == 3 : nrhs >= 2) && sap_block_mf<D>(g, cb, Dc, eta, z, nrhs, mu, bl, nb, sweeps, mr, st)) {
+      tune_used(TUNE_SAP1, 3);
+      return true;
+    }
     if (tv >= 0 ? tv >= 1 : nrhs >= 8) {
       // variant 2: register budget for four workgroups per CU (the rule
       // takes it from 4096 coarse sites on)

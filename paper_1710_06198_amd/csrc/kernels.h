@@ -229,7 +229,8 @@ void launch_store_from64(const cplx<double>* in, typename Store<S>::pair* out, l
 // TMAMG_TUNE_* in the public header).  Keys are (a, b, c) per family:
 //   TUNE_COARSE_APPLY (d, coarse sites, nrhs): 0 vector ALU, 1 matrix cores
 //   TUNE_SAP1         (d, coarse sites, nrhs): 0 vector ALU, 1 matrix cores,
-//                     2 matrix cores with a register budget for four workgroups per CU
+//                     2 matrix cores with a register budget for four workgroups per CU,
+//                     3 matrix cores, one workgroup per SAP block (blocks of at most 16 sites)
 //   TUNE_RESTRICT0 / TUNE_PROLONG0 (nv, fine sites, nrhs): 0 vector ALU, 1 matrix cores
 //   TUNE_SAP0         (block sites, fine sites, nrhs): register budget for 0 one, 1 three workgroups per CU;
 //                     2: two right-hand sides per workgroup (lane pairs share every link and clover load)
@@ -237,7 +238,7 @@ void launch_store_from64(const cplx<double>* in, typename Store<S>::pair* out, l
 // rule, and records the variant it ran with tune_used.
 enum { TUNE_COARSE_APPLY = 0, TUNE_SAP1, TUNE_RESTRICT0, TUNE_PROLONG0, TUNE_SAP0, TUNE_NFAM };
 constexpr int TUNE_MAX_VARIANTS = 4;
-inline int tune_variants(int family) { return family == TUNE_SAP1 || family == TUNE_SAP0 ? 3 : 2; }
+inline int tune_variants(int family) { return family == TUNE_SAP1 ? 4 : family == TUNE_SAP0 ? 3 : 2; }
 int tune_get(int family, long a, long b, long c);
 void tune_put(int family, long a, long b, long c, int variant, const double* ms, int nms);
 void tune_used(int family, int variant);

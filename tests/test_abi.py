@@ -258,8 +258,11 @@ def test_variant_table_round_trip(tm, tmp_path):
         tm.tune_set(tm.TUNE_SAP1, 48, 8192, 12, 2)   # the level-1 SAP has a third variant
         assert tm.tune_get(tm.TUNE_SAP1, 48, 8192, 12) == 2
         tm.tune_set(tm.TUNE_SAP1, 48, 8192, 12, -1)
+        tm.tune_set(tm.TUNE_SAP1, 48, 8192, 12, 3)   # and a fourth (one workgroup per SAP block)
+        assert tm.tune_get(tm.TUNE_SAP1, 48, 8192, 12) == 3
+        tm.tune_set(tm.TUNE_SAP1, 48, 8192, 12, -1)
         with pytest.raises(tm.TmamgError, match="variant"):
-            tm.tune_set(tm.TUNE_SAP1, 1, 1, 1, 3)
+            tm.tune_set(tm.TUNE_SAP1, 1, 1, 1, 4)
         with pytest.raises(tm.TmamgError, match="variant"):
             tm.tune_set(tm.TUNE_COARSE_APPLY, 1, 1, 1, 2)
         assert tm.binding.load().tmamg_autotune(None, None, 0, 1, None) == -1
