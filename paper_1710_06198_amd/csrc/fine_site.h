@@ -48,13 +48,18 @@ TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, uns
   hop_bwd<MU>(ub, pn, acc);
 }
 
-// (D(mu) in)(s) for one right-hand side
+// (D(mu) in)(s) for one right-hand side; own (optional) receives in(s)
 template <typename T>
-TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc) {
+TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc,
+                      cplx<T>* own = nullptr) {
   int c[4];
   fine_coords(op.g, s, c);
   cplx<T> psi[12];
   load_spinor(in, s, op.g.V, psi);
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) own[k] = psi[k];
+  }
   site_diag(op, s, mu, psi, acc);
   // one direction at a time: without these compiler fences every
   // neighbour's loads are hoisted to the top (> 256 live VGPRs, occupancy 1)
@@ -188,10 +193,12 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   const cplx<T>* zr = z + (long)r * 12 * V;
   int c[4];
   fine_coords(g, s, c);
+  // e accumulates the block's new iterate from z's own value (the final
+  // write needs no second read of z)
   cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
   {
-    cplx<T> dz[12];
-    site_dslash(op, zr, s, mu, dz);
+    cplx<T> dz[12], zs[12];
+    site_dslash(op, zr, s, mu, dz, zs);
     if constexpr (CPL) {
       const cplx<T>* zo = z + (long)(r ^ 1) * 12 * V + tsite(s, 12);
 #pragma unroll
@@ -201,8 +208,8 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       rho[k] = er[k * FT] - dz[k];
-      if constexpr (ELDS) el[k * bv + loc] = mk<T>(0, 0);
-      else e[k] = mk<T>(0, 0);
+      if constexpr (ELDS) el[k * bv + loc] = zs[k];
+      else e[k] = zs[k];
     }
   }
   for (int it = 0; it < mr_steps; ++it) {
@@ -250,6 +257,6 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   if (!writes) return;
   cplx<T>* zo = z + (long)r * 12 * V + tsite(s, 12);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) zo[k * FT] += ELDS ? el[k * bv + loc] : e[k];
+  for (int k = 0; k < 12; ++k) zo[k * FT] = ELDS ? el[k * bv + loc] : e[k];
 }
 
