@@ -78,17 +78,6 @@ template <typename T> TM_HD void acc_dotc(T& sre, T& sim, cplx<T> a, cplx<T> b) 
 template <typename T> TM_HD cplx<T> times_i(cplx<T> a) { return mk(-a.im, a.re); }
 template <typename T> TM_HD T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
 
-// Load/store at element i of a wave-uniform base pointer with a 32-bit
-// per-lane offset: the backend then addresses through a scalar base and one
-// 32-bit VGPR instead of a 64-bit VGPR address per access.  Requires
-// i * sizeof(X) < 2^32.
-template <typename X> TM_D X ldu(const X* __restrict__ base, unsigned i) {
-  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + (size_t)(i * (unsigned)sizeof(X)));
-}
-template <typename X> TM_D void stu(X* base, unsigned i, X v) {
-  *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + (size_t)(i * (unsigned)sizeof(X))) = v;
-}
-
 // ------------------------------------------------------------------ storage
 // A complex number stored in precision S and computed with in precision T.
 template <typename S> struct Store;
