@@ -32,6 +32,8 @@ TM_D void site_diag(const FineOp<T>& op, unsigned s, T mu, const cplx<T>* psi, c
   }
 }
 
+// Both hops of direction MU, gathered from memory (used where one direction
+// at a time keeps the register count down)
 template <int MU, typename T>
 TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
                         cplx<T>* acc) {
@@ -48,29 +50,74 @@ TM_D void site_hops_dir(const FineOp<T>& op, const cplx<T>* __restrict__ in, uns
   hop_bwd<MU>(ub, pn, acc);
 }
 
-// (D(mu) in)(s) for one right-hand side; own (optional) receives in(s)
+// One hop's operands gathered from memory: the neighbouring spinor and the
+// link.  Hop H is direction H / 2, forward for even H, backward for odd.
 template <typename T>
-TM_D void site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu, cplx<T>* acc,
-                      cplx<T>* own = nullptr) {
+struct HopRegs {
+  cplx<T> p[12];
+  M3<T> u;
+};
+template <int H, typename T>
+TM_D void gather_hop(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
+                     HopRegs<T>& r) {
+  constexpr int MU = H >> 1;
+  const long V = op.g.V;
+  if constexpr ((H & 1) == 0) {
+    load_spinor(in, (unsigned)fine_neighbour(op.g, s, c, MU, +1), V, r.p);
+    r.u = load_link_u<MU>(op.links, s, V);
+  } else {
+    const unsigned sb = (unsigned)fine_neighbour(op.g, s, c, MU, -1);
+    load_spinor(in, sb, V, r.p);
+    r.u = load_link_u<MU>(op.links, sb, V);
+  }
+}
+template <int H, typename T>
+TM_D void apply_hop(const HopRegs<T>& r, cplx<T>* acc) {
+  if constexpr ((H & 1) == 0) hop_fwd<(H >> 1)>(r.u, r.p, acc);
+  else hop_bwd<(H >> 1)>(r.u, r.p, acc);
+}
+TM_D void memory_fence_compiler() { __asm__ __volatile__("" ::: "memory"); }
+
+// Two hops of the gather in flight: the loads of hop H + 1 are issued before
+// the arithmetic of hop H (register sets a and b alternate).
+template <int H, typename T>
+TM_D void hops_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, const int c[4],
+                         HopRegs<T>& a, HopRegs<T>& b, cplx<T>* acc) {
+  if constexpr (H < 7) {
+    gather_hop<H + 1>(op, in, s, c, b);
+    memory_fence_compiler();
+    apply_hop<H>(a, acc);
+    compiler_fence(acc);
+    hops_pipelined<H + 1>(op, in, s, c, b, a, acc);
+  } else {
+    apply_hop<H>(a, acc);
+  }
+}
+
+// (D(mu) in)(s) for one right-hand side, the gather pipelined (hops first,
+// then the clover and twisted-mass term on the site's own value); own
+// receives in(s)
+template <typename T>
+TM_D void site_dslash_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__ in, unsigned s, T mu,
+                                cplx<T>* acc, cplx<T>* own) {
   int c[4];
   fine_coords(op.g, s, c);
-  cplx<T> psi[12];
-  load_spinor(in, s, op.g.V, psi);
-  if (own) {
+  const long V = op.g.V;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) own[k] = psi[k];
+  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
+  HopRegs<T> a, b;
+  gather_hop<0>(op, in, s, c, a);
+  memory_fence_compiler();
+  hops_pipelined<0>(op, in, s, c, a, b, acc);
+  compiler_fence(acc);
+  load_spinor(in, s, V, own);
+  clover_block_mv<T>(op.clover, s, V, own, acc);
+  clover_block_mv<T>(op.clover + 36 * V, s, V, own + 6, acc + 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    acc[k] += mu * times_i(own[k]);
+    acc[6 + k] -= mu * times_i(own[6 + k]);
   }
-  site_diag(op, s, mu, psi, acc);
-  // one direction at a time: without these compiler fences every
-  // neighbour's loads are hoisted to the top (> 256 live VGPRs, occupancy 1)
-  compiler_fence(acc);
-  site_hops_dir<0>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<1>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<2>(op, in, s, c, acc);
-  compiler_fence(acc);
-  site_hops_dir<3>(op, in, s, c, acc);
 }
 
 // ------------------------------------------------------------------ SAP (K3)
@@ -198,7 +245,7 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
   {
     cplx<T> dz[12], zs[12];
-    site_dslash(op, zr, s, mu, dz, zs);
+    site_dslash_pipelined(op, zr, s, mu, dz, zs);
     if constexpr (CPL) {
       const cplx<T>* zo = z + (long)(r ^ 1) * 12 * V + tsite(s, 12);
 #pragma unroll
