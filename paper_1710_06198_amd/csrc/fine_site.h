@@ -156,6 +156,83 @@ TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, in
   }
 }
 
+// In-block neighbour of hop H (direction H / 2, forward for even H) as a
+// block-local index, or -1 where the hop leaves the block.
+template <int H>
+TM_D int block_nbr(const FineGeom& g, int loc, const int c[4]) {
+  constexpr int MU = H >> 1;
+  const int lc = c[MU] % g.B[MU];
+  const bool whole = g.NB[MU] == 1;    // block spans the periodic direction
+  if constexpr ((H & 1) == 0) {
+    if (lc < g.B[MU] - 1) return loc + g.lstride[MU];
+    return whole ? loc - (g.B[MU] - 1) * g.lstride[MU] : -1;
+  } else {
+    if (lc > 0) return loc - g.lstride[MU];
+    return whole ? loc + (g.B[MU] - 1) * g.lstride[MU] : -1;
+  }
+}
+
+// Hop H of the block residual's gather: the neighbour's value from the
+// block's staged copy in LDS where the neighbour is in the block, from
+// memory where it is not; the link from memory.
+template <int H, typename T>
+TM_D void gather_hop_block(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
+                           int loc, const int c[4], HopRegs<T>& r) {
+  constexpr int MU = H >> 1;
+  const long V = op.g.V;
+  const int bv = op.g.bvol;
+  const int nl = block_nbr<H>(op.g, loc, c);
+  const unsigned sn = (unsigned)fine_neighbour(op.g, s, c, MU, (H & 1) ? -1 : +1);
+  if (nl >= 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r.p[k] = zl[k * bv + nl];
+  } else {
+    load_spinor(in, sn, V, r.p);
+  }
+  r.u = load_link_u<MU>(op.links, (H & 1) ? sn : s, V);
+}
+template <int H, typename T>
+TM_D void block_hops_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
+                               int loc, const int c[4], HopRegs<T>& a, HopRegs<T>& b, cplx<T>* acc) {
+  if constexpr (H < 7) {
+    gather_hop_block<H + 1>(op, in, zl, s, loc, c, b);
+    memory_fence_compiler();
+    apply_hop<H>(a, acc);
+    compiler_fence(acc);
+    block_hops_pipelined<H + 1>(op, in, zl, s, loc, c, b, a, acc);
+  } else {
+    apply_hop<H>(a, acc);
+  }
+}
+
+// (D(mu) z)(s) for a site of a block whose own values zl[k * bvol + loc]
+// are staged in LDS (the workgroup has passed a barrier since): in-block
+// neighbours from LDS, the others and the links from memory, two hops in
+// flight; then the clover and twisted-mass term on the site's own value.
+template <typename T>
+TM_D void block_site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
+                            int loc, const int c[4], T mu, cplx<T>* acc) {
+  const long V = op.g.V;
+  const int bv = op.g.bvol;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
+  HopRegs<T> a, b;
+  gather_hop_block<0>(op, in, zl, s, loc, c, a);
+  memory_fence_compiler();
+  block_hops_pipelined<0>(op, in, zl, s, loc, c, a, b, acc);
+  compiler_fence(acc);
+  cplx<T> own[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) own[k] = zl[k * bv + loc];
+  clover_block_mv<T>(op.clover, s, V, own, acc);
+  clover_block_mv<T>(op.clover + 36 * V, s, V, own + 6, acc + 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    acc[k] += mu * times_i(own[k]);
+    acc[6 + k] -= mu * times_i(own[6 + k]);
+  }
+}
+
 // Workgroup sums of three values, one barrier: the wave sums go to slot
 // `slot` of red (two slots of 3 x 8 values).  Alternate the slot between
 // calls: a slot is written again only two calls later, after every wave
@@ -243,9 +320,22 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   // e accumulates the block's new iterate from z's own value (the final
   // write needs no second read of z)
   cplx<T> rho[12], q[12], e[ELDS ? 1 : 12];
+  // one RHS in FP32: the block's own z is staged in LDS (the MR vector's
+  // slot, free until the first step) and the residual's in-block
+  // neighbours are read from there (at the batches' register budget this
+  // form spills)
+  constexpr bool LDS_RESIDUAL = MINB == 1 && !PAIR && sizeof(T) == 4;
   {
     cplx<T> dz[12], zs[12];
-    site_dslash_pipelined(op, zr, s, mu, dz, zs);
+    if constexpr (LDS_RESIDUAL) {
+      load_spinor(zr, s, V, zs);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) lds[k * bv + loc] = zs[k];
+      __syncthreads();
+      block_site_dslash(op, zr, lds, s, loc, c, mu, dz);
+    } else {
+      site_dslash_pipelined(op, zr, s, mu, dz, zs);
+    }
     if constexpr (CPL) {
       const cplx<T>* zo = z + (long)(r ^ 1) * 12 * V + tsite(s, 12);
 #pragma unroll
@@ -256,8 +346,12 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
     for (int k = 0; k < 12; ++k) {
       rho[k] = er[k * FT] - dz[k];
       if constexpr (ELDS) el[k * bv + loc] = zs[k];
+      else if constexpr (LDS_RESIDUAL) e[k] = lds[k * bv + loc];
       else e[k] = zs[k];
     }
+    // every neighbour read of the staged z is done before the first MR
+    // step overwrites it
+    if constexpr (LDS_RESIDUAL) __syncthreads();
   }
   for (int it = 0; it < mr_steps; ++it) {
 #pragma unroll
