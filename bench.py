@@ -341,7 +341,7 @@ def bench_batched(args):
     import paper_1710_06198_amd as tm
     from lattice_inputs import workload, gauge_links, point_sources, gaussian_spinor, rational_shifts, load_m0
     w = workload("c3")
-    m0 = load_m0()[w.name]
+    m0 = args.m0 if args.m0 is not None else load_m0()[w.name]
     kappa = 1.0 / (2 * m0 + 8)
     dev = torch.device("cuda:0")
     V = w.volume
@@ -639,6 +639,70 @@ def kernels_only(args):
     return 0
 
 
+def conditioning(args, iters=30):
+    """The conditioning of the workload's problem: the smallest singular
+    value of D(m0, mu = 0) on the workload's own lattice, by inverse
+    iteration on D^dag D.  Each step is two solves at mu = 0 through the
+    library, (D^dag D)^-1 x = D^-1 g5 D^-1 g5 x (D^dag = g5 D g5 at mu = 0);
+    1 / (x^dag (D^dag D)^-1 x) for unit x converges to sigma_min^2 from
+    above.  With the twisted mass, D(mu)^dag D(mu) = D(0)^dag D(0) + mu^2,
+    so sigma_min(D(mu)) = sqrt(sigma_min^2 + mu^2): the problem sits in the
+    twisted-mass-dominated regime of the paper's physical point when
+    sigma_min is not much larger than mu."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, gaussian_spinor, load_m0
+    w = workload(args.workload)
+    m0 = args.m0 if args.m0 is not None else load_m0()[w.name]
+    dev = torch.device("cuda:0")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    s = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED), stream=torch.cuda.Stream(device=dev))
+    s.setup(U, 1.0 / (2 * m0 + 8), w.csw, w.mu)
+    x = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"] + 7, n=1)).to(dev)
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+
+    def g5(v):
+        v[..., 2:, :] *= -1
+        return v
+
+    est, its = [], []
+    for k in range(iters):
+        i1 = s.solve(g5(x.clone()), y, mu_rhs=[0.0], tol=1e-8)
+        i2 = s.solve(g5(y), z, mu_rhs=[0.0], tol=1e-8)
+        rq = torch.vdot(x.flatten(), z.flatten()).real.item()
+        est.append(1.0 / rq)
+        its.append(i1.outer_iters + i2.outer_iters)
+        x = z / torch.linalg.vector_norm(z)
+        log(f"[cond] step {k}: sigma_min^2 <= {est[-1]:.4e} ({its[-1]} outer iterations)")
+    smin = est[-1] ** 0.5
+    # the eigenvalue of D(m0, 0) of smallest modulus, by inverse iteration on
+    # D with its Rayleigh quotient; D(m0 + d) = D(m0) + d shifts every
+    # eigenvalue by d, so m0 - Re(lambda) puts that eigenvalue on the
+    # imaginary axis: the critical mass on this lattice by the same recipe
+    # the workloads' m0 follow on the smaller proxy lattice
+    x = torch.as_tensor(gaussian_spinor(w.dims, w.seeds["source"] + 8, n=1)).to(dev)
+    x /= torch.linalg.vector_norm(x)
+    dx = torch.empty_like(x)
+    lams = []
+    for k in range(iters):
+        s.solve(x, y, mu_rhs=[0.0], tol=1e-8)
+        x = y / torch.linalg.vector_norm(y)
+        s.apply(tm.OP_D64, 0, x, dx, mu_rhs=[0.0])
+        lam = torch.vdot(x.flatten(), dx.flatten()).item()
+        lams.append([lam.real, lam.imag])
+        eres = (torch.linalg.vector_norm(dx - lam * x) / abs(lam)).item()
+        log(f"[cond] step {k}: lambda = {lam.real:.5e} {lam.imag:+.5e}i, |D x - lambda x| / |lambda| = {eres:.2e}")
+    out = {"workload": w.name, "lattice": list(w.dims), "m0": m0, "mu": w.mu, "csw": w.csw,
+           "sigma_min_D0": smin, "sigma_min_D0_sq_by_step": est, "outer_iters_by_step": its,
+           "sigma_min_D_mu": (est[-1] + w.mu ** 2) ** 0.5, "sigma_min_over_mu": smin / w.mu,
+           "lambda_min_modulus_D0": lams[-1], "lambda_by_step": lams, "lambda_eigen_residual": eres, "m0_critical_this_lattice": m0 - lams[-1][0]}
+    s.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -654,6 +718,12 @@ def main():
     ap.add_argument("--tune", type=int, choices=(0, 1), default=1,
                     help="autotune the kernel variants on the workload's hierarchy before timing")
     ap.add_argument("--tune-cache", default=None, help="variant table JSON to load if present, else to write")
+    ap.add_argument("--m0", type=float, default=None,
+                    help="c3 and --conditioning: this bare mass instead of the workload's (a measurement beside "
+                         "the default line, e.g. at the critical mass of the workload's own lattice)")
+    ap.add_argument("--conditioning", action="store_true",
+                    help="estimate the smallest singular value of D(m0, mu=0) on the workload's lattice "
+                         "(inverse iteration through the solver) instead of the benchmark")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the timing loops of the fine stencil, the fine SAP (12 right-hand sides) and "
                          "the copy kernel on a context without a multigrid setup (for profiler passes)")
@@ -671,6 +741,8 @@ def main():
 
     if args.kernels_only:
         return kernels_only(args)
+    if args.conditioning:
+        return conditioning(args)
     if args.workload == "c3":
         return bench_batched(args)
     if args.workload == "c4":

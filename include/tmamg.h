@@ -28,7 +28,11 @@
  *
  * Ordering.  All work is ordered on the stream given at creation; every
  * call returns after synchronising that stream (status and info are host
- * values).  A context is not thread-safe.
+ * values).  Inputs are read on that stream: device data written on another
+ * stream must be complete, or ordered before the call (an event that the
+ * context's stream waits on); the Python binding orders the context's
+ * stream after the caller's current stream on every call.  A context is not
+ * thread-safe.
  *
  * Errors.  Negative status: outputs undefined, tmamg_last_error() holds a
  * message.  TMAMG_NOT_CONVERGED: x holds the best iterate and

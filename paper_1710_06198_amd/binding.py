@@ -282,6 +282,25 @@ class Solver:
         self.h = h
         _live.add(self)
 
+    def _ordered(self, fn):
+        """fn with the library's stream ordered after the caller's current
+        stream (the inputs written there are complete before the library
+        reads them) and the caller's stream after the library's (the outputs
+        are complete before the caller's next work reads them)."""
+        import torch
+
+        def call(*args):
+            cur = torch.cuda.current_stream(self.device)
+            other = cur.cuda_stream != self._stream.cuda_stream
+            if other:
+                self._stream.wait_stream(cur)
+            try:
+                return fn(*args)
+            finally:
+                if other:
+                    cur.wait_stream(self._stream)
+        return call
+
     @property
     def volume(self):
         v = 1
@@ -317,12 +336,12 @@ class Solver:
 
     def setup(self, U, kappa, csw, mu):
         self._links("U", U)
-        _check(self.lib.tmamg_setup(self.h, _ptr(U), float(kappa), float(csw), float(mu)))
+        _check(self._ordered(self.lib.tmamg_setup)(self.h, _ptr(U), float(kappa), float(csw), float(mu)))
         self.links_version += 1
 
     def setup_update(self, U, iters=1):
         self._links("U", U)
-        _check(self.lib.tmamg_setup_update(self.h, _ptr(U), int(iters)))
+        _check(self._ordered(self.lib.tmamg_setup_update)(self.h, _ptr(U), int(iters)))
         self.links_version += 1
 
     def solve(self, b, x, mu_rhs=None, tol=1e-10, guess=False):
@@ -331,7 +350,7 @@ class Solver:
         self._spinors("x", x, n)
         check_values("mu_rhs", mu_rhs, n)
         info = Info()
-        fn = self.lib.tmamg_solve_guess if guess else self.lib.tmamg_solve
+        fn = self._ordered(self.lib.tmamg_solve_guess if guess else self.lib.tmamg_solve)
         st = fn(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol), ctypes.byref(info))
         _check(st)
         return info
@@ -343,7 +362,8 @@ class Solver:
         self._spinors("x", x, n)
         check_values("mu_rhs", mu_rhs, n)
         info = Info()
-        st = self.lib.tmamg_solve_eo(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol), ctypes.byref(info))
+        st = self._ordered(self.lib.tmamg_solve_eo)(self.h, _ptr(b), _ptr(x), n, _dvec(mu_rhs), float(tol),
+                                                     ctypes.byref(info))
         _check(st)
         return info
 
@@ -354,7 +374,8 @@ class Solver:
             raise ValueError("sigma: one shift per right-hand side is required")
         check_values("sigma", sigma, n)
         info = Info()
-        st = self.lib.tmamg_solve_shifted(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol), ctypes.byref(info))
+        st = self._ordered(self.lib.tmamg_solve_shifted)(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol),
+                                                          ctypes.byref(info))
         _check(st)
         return info
 
@@ -367,8 +388,8 @@ class Solver:
             raise ValueError("sigma: one shift per solution is required")
         check_values("sigma", sigma, n)
         info = Info()
-        st = self.lib.tmamg_solve_multishift(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol),
-                                             ctypes.byref(info))
+        fn = self._ordered(self.lib.tmamg_solve_multishift)
+        st = fn(self.h, _ptr(b), _ptr(x), n, _dvec(sigma), float(tol), ctypes.byref(info))
         _check(st)
         return info
 
@@ -379,8 +400,8 @@ class Solver:
         self._spinors("b", b, 2)
         self._spinors("x", x, 2)
         info = Info()
-        st = self.lib.tmamg_solve_nd(self.h, _ptr(b), _ptr(x), float(mubar), float(epsbar), float(tol),
-                                     ctypes.byref(info))
+        fn = self._ordered(self.lib.tmamg_solve_nd)
+        st = fn(self.h, _ptr(b), _ptr(x), float(mubar), float(epsbar), float(tol), ctypes.byref(info))
         _check(st)
         return info
 
@@ -389,7 +410,8 @@ class Solver:
         self._links("F", F)
         info = Info()
         S = ctypes.c_double()
-        _check(self.lib.tmamg_force(self.h, _ptr(phi), _ptr(F), ctypes.byref(S), float(tol), ctypes.byref(info)))
+        _check(self._ordered(self.lib.tmamg_force)(self.h, _ptr(phi), _ptr(F), ctypes.byref(S), float(tol),
+                                                    ctypes.byref(info)))
         return S.value, info
 
     def force_at(self, phi, mu, F, tol=1e-12):
@@ -398,8 +420,8 @@ class Solver:
         self._links("F", F)
         info = Info()
         S = ctypes.c_double()
-        _check(self.lib.tmamg_force_at(self.h, _ptr(phi), float(mu), _ptr(F), ctypes.byref(S), float(tol),
-                                       ctypes.byref(info)))
+        fn = self._ordered(self.lib.tmamg_force_at)
+        _check(fn(self.h, _ptr(phi), float(mu), _ptr(F), ctypes.byref(S), float(tol), ctypes.byref(info)))
         return S.value, info
 
     def gauge_force(self, U, beta, F):
@@ -407,30 +429,30 @@ class Solver:
         self._links("U", U)
         self._links("F", F)
         S = ctypes.c_double()
-        _check(self.lib.tmamg_gauge_force(self.h, _ptr(U), float(beta), _ptr(F), ctypes.byref(S)))
+        _check(self._ordered(self.lib.tmamg_gauge_force)(self.h, _ptr(U), float(beta), _ptr(F), ctypes.byref(S)))
         return S.value
 
     def md_update_links(self, U, P, eps):
         self._links("U", U)
         self._links("P", P)
-        _check(self.lib.tmamg_md_update_links(self.h, _ptr(U), _ptr(P), float(eps)))
+        _check(self._ordered(self.lib.tmamg_md_update_links)(self.h, _ptr(U), _ptr(P), float(eps)))
 
     def md_update_momenta(self, P, F, coef):
         self._links("P", P)
         self._links("F", F)
-        _check(self.lib.tmamg_md_update_momenta(self.h, _ptr(P), _ptr(F), float(coef)))
+        _check(self._ordered(self.lib.tmamg_md_update_momenta)(self.h, _ptr(P), _ptr(F), float(coef)))
 
     def md_kinetic(self, P):
         self._links("P", P)
         K = ctypes.c_double()
-        _check(self.lib.tmamg_md_kinetic(self.h, _ptr(P), ctypes.byref(K)))
+        _check(self._ordered(self.lib.tmamg_md_kinetic)(self.h, _ptr(P), ctypes.byref(K)))
         return K.value
 
     def force_from_fields(self, X, Y, F):
         self._spinors("X", X, 1)
         self._spinors("Y", Y, 1)
         self._links("F", F)
-        _check(self.lib.tmamg_force_from_fields(self.h, _ptr(X), _ptr(Y), _ptr(F)))
+        _check(self._ordered(self.lib.tmamg_force_from_fields)(self.h, _ptr(X), _ptr(Y), _ptr(F)))
 
     def force_from_fields_noalloc(self, X, Y, F):
         """force_from_fields without any device allocation: the library's
@@ -439,12 +461,12 @@ class Solver:
         self._spinors("X", X, 1)
         self._spinors("Y", Y, 1)
         self._links("F", F)
-        _check(self.lib.tmamg_force_from_fields_noalloc(self.h, _ptr(X), _ptr(Y), _ptr(F)))
+        _check(self._ordered(self.lib.tmamg_force_from_fields_noalloc)(self.h, _ptr(X), _ptr(Y), _ptr(F)))
 
     def force_link_gradient(self, F, G, scale=1.0):
         self._links("F", F)
         self._links("G", G)
-        _check(self.lib.tmamg_force_link_gradient(self.h, _ptr(F), _ptr(G), float(scale)))
+        _check(self._ordered(self.lib.tmamg_force_link_gradient)(self.h, _ptr(F), _ptr(G), float(scale)))
 
     def apply(self, op, level, inp, out, mu_rhs=None):
         n = inp.shape[0]
@@ -461,7 +483,7 @@ class Solver:
             check_values("mu_rhs", mu_rhs, n)
         elif mu_rhs is None or len(mu_rhs) != 2 or n != 2:
             raise ValueError("doublet operators: two flavours and mu_rhs = (mubar, epsbar)")
-        _check(self.lib.tmamg_apply(self.h, int(op), int(level), _ptr(inp), _ptr(out), n, _dvec(mu_rhs)))
+        _check(self._ordered(self.lib.tmamg_apply)(self.h, int(op), int(level), _ptr(inp), _ptr(out), n, _dvec(mu_rhs)))
 
     def set_test_vectors(self, level, v):
         if level == 0:
@@ -469,7 +491,7 @@ class Solver:
         else:
             s1, d1 = self.level_info(1)
             check_field("v", v, self.params.nv[1] * s1 * d1, self.device)
-        _check(self.lib.tmamg_debug_set_test_vectors(self.h, int(level), _ptr(v)))
+        _check(self._ordered(self.lib.tmamg_debug_set_test_vectors)(self.h, int(level), _ptr(v)))
 
     def export(self, what, level, out):
         if what == 0:
@@ -478,24 +500,24 @@ class Solver:
         else:
             sc, dc = self.level_info(level)
             check_field("out", out, sc * 9 * dc * dc, self.device)
-        _check(self.lib.tmamg_debug_export(self.h, int(what), int(level), _ptr(out)))
+        _check(self._ordered(self.lib.tmamg_debug_export)(self.h, int(what), int(level), _ptr(out)))
 
     def inject_barrier_timeout(self):
         """Failure-path hook: the next solve reports TMAMG_EHIP and the
         context falls back to the generic coarse kernels."""
-        _check(self.lib.tmamg_debug_inject(self.h, 0))
+        _check(self._ordered(self.lib.tmamg_debug_inject)(self.h, 0))
 
     def time_kernel(self, kernel, nrhs=1, reps=20):
         ms = ctypes.c_double()
-        _check(self.lib.tmamg_time_kernel(self.h, int(kernel), int(nrhs), int(reps), ctypes.byref(ms)))
+        _check(self._ordered(self.lib.tmamg_time_kernel)(self.h, int(kernel), int(nrhs), int(reps), ctypes.byref(ms)))
         return ms.value
 
     def autotune(self, nrhs_list, reps=5, json_path=None):
         """Time both variants of every tunable kernel family at these
         right-hand-side counts and keep the faster in the variant table."""
         arr = (ctypes.c_int * len(nrhs_list))(*[int(n) for n in nrhs_list])
-        _check(self.lib.tmamg_autotune(self.h, arr, len(nrhs_list), int(reps),
-                                       None if json_path is None else os.fsencode(json_path)))
+        fn = self._ordered(self.lib.tmamg_autotune)
+        _check(fn(self.h, arr, len(nrhs_list), int(reps), None if json_path is None else os.fsencode(json_path)))
 
     def level_info(self, level):
         s, d = ctypes.c_long(), ctypes.c_int()

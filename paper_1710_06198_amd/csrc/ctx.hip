@@ -447,7 +447,7 @@ void Ctx::upload_mu(int nrhs, const double* mu_host) {
       check(std::isfinite(mu_host[r]), "non-finite twisted mass");
       m[r] = mu_host[r];
     }
-  HIPCHK(hipMemcpyAsync(mu_dev.p, m.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_set_doubles(mu_dev.p, m.data(), nrhs, st);
 }
 
 // b64 holds the right-hand sides (internal layout); x64 receives the solutions.
@@ -542,12 +542,12 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     int it;
     if (!mixed) {
       for (int r = 0; r < nk; ++r) at[r] = 0.9 * tol * bn[r];
-      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nk * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_set_doubles(abstol_dev.p, at.data(), nk, st);
       it = krylov_cycle<double>(k64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nk,
                                 std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
     } else {
       for (int r = 0; r < nk; ++r) at[r] = std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]);
-      HIPCHK(hipMemcpyAsync(abstol_dev.p, at.data(), nk * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_set_doubles(abstol_dev.p, at.data(), nk, st);
       launch_convert<double, float>(r64.p, r32.p, (long)nrhs * n, st);
       launch_fill_zero(e32.p, (size_t)nrhs * n * sizeof(cplx<float>), st);
       it = krylov_cycle<float>(k32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, nk,

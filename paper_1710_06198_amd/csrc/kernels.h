@@ -108,6 +108,10 @@ void launch_lincomb(const cplx<double>* a, const cplx<double>* b, cplx<double>* 
 // streaming copy of bytes (a multiple of 16)
 void launch_copy16(const void* in, void* out, size_t bytes, hipStream_t st);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// dst[i] = vals[i] for i < n, the values carried in the launch arguments:
+// the host array need not outlive the call (an asynchronous copy from it
+// would read it only when the stream reaches the copy)
+void launch_set_doubles(double* dst, const double* vals, int n, hipStream_t st);
 // workgroups of 256 for an elementwise launch over count elements: one
 // element per thread up to 2^28 elements, beyond that the kernels stride
 // by the grid (a launch holds fewer than 2^32 threads)

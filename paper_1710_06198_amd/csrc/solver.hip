@@ -23,6 +23,22 @@ __global__ void k_fill_double(double* p, double v, int n) {
   if (i < n) p[i] = v;
 }
 
+struct DoubleChunk {
+  double v[32];
+};
+__global__ void k_set_doubles(double* p, DoubleChunk c, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = c.v[i];
+}
+void launch_set_doubles(double* dst, const double* vals, int n, hipStream_t st) {
+  for (int o = 0; o < n; o += 32) {
+    DoubleChunk c{};
+    const int k = std::min(32, n - o);
+    for (int i = 0; i < k; ++i) c.v[i] = vals[o + i];
+    hipLaunchKernelGGL(k_set_doubles, dim3(1), dim3(32), 0, st, dst + o, c, k);
+  }
+}
+
 void PhaseTimer::report(const char* tag, hipStream_t st, const std::string& extra) {
   if (!on) return;
   HIPCHK(hipStreamSynchronize(st));

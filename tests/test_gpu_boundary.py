@@ -1,7 +1,8 @@
 """The C ABI's conventions on the GPU: internal buffers from the caller's
-allocator (torch's caching allocator), the D^dag operator hook, solves from
-an initial guess, the per-level iteration totals in tmamg_info, and the
-failure path of the persistent coarse kernels' bounded barrier wait."""
+allocator (torch's caching allocator), the ordering of the library's stream
+against the caller's, the D^dag operator hook, solves from an initial
+guess, the per-level iteration totals in tmamg_info, and the failure path
+of the persistent coarse kernels' bounded barrier wait."""
 import pytest
 import torch
 
@@ -88,6 +89,32 @@ def test_ddag_operator(c1):
     lhs = torch.vdot(ref[0].reshape(-1), field(chi).reshape(-1))
     rhs = torch.vdot(field(torch.as_tensor(psi[0])).reshape(-1), op.apply(field(chi), mus[0]).reshape(-1))
     assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+    s.close()
+
+
+def test_inputs_written_on_the_callers_stream(c1):
+    """The library runs on its own stream.  A right-hand side written on the
+    caller's current stream just before the call, with that stream still
+    busy, is complete when the library reads it, and the solution is
+    complete before the caller's next work on its stream reads it."""
+    w, m0, U, Ud, op = c1
+    say("stream ordering: input and output on a busy caller stream")
+    s = tm.Solver(w.dims, params(w, precision=tm.MIXED), stream=torch.cuda.Stream(device=DEV))
+    s.setup(Ud, kappa_of(m0), w.csw, w.mu)
+    b, bd = spinors(w.dims, 8811, 1)
+    filler = torch.ones(1 << 26, device=DEV)
+    torch.cuda.synchronize()
+    caller = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(caller):
+        for _ in range(8):
+            filler.mul_(1.0000001)   # 256 MiB of work ahead of the input
+        b2 = bd * 2.0
+        x = torch.empty_like(bd)
+        s.solve(b2, x, tol=1e-10)
+        y = x * 0.5
+    torch.cuda.synchronize()
+    res = op.apply(field(y.cpu()[0]), w.mu) - field(torch.as_tensor(b[0]))
+    assert norm(res) / norm(field(torch.as_tensor(b[0]))) < 1e-9
     s.close()
 
 
