@@ -501,14 +501,7 @@ __global__ void __launch_bounds__(256) k_restrict_coarse_mf(CoarseGeom g, int d,
     }
     const cplx<float> zv[4] = {mk(z01.x, z01.y), mk(z01.z, z01.w), mk(z23.x, z23.y), mk(z23.z, z23.w)};
     const MfSplit bb = mf_split(zv);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+    mf_cmac_conj(ar, ai, bb, accr, acci);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {

@@ -148,11 +148,11 @@ TM_D cplx<T> site_mv_row(const cplx<T>* red, int i) {
 // With 16 right-hand sides and a bf16 D_c the product of site_mv,
 //   out[q][i] = sum_{b in mask} sum_j D_b(i, j) v[q][b D + j],
 // is a complex (D x 9D) x (9D x 16) matrix product.  It runs as real
-// 16x16x16 bf16 MFMA products with FP32 accumulation:
+// bf16 MFMA products (16x16x32, mf_cmac) with FP32 accumulation:
 //   Re out = Re D Re v - Im D Im v,   Im out = Re D Im v + Im D Re v.
 // The D_c entries are exact in bf16.  Each FP32 vector entry is split as
 // v = v_hi + v_lo, v_hi = bf16(v), v_lo = bf16(v - v_hi), which keeps v to
-// 2^-18 of its size, so a 16x16 tile takes 8 products per 16 terms of the
+// 2^-18 of its size, so a 16x16 tile takes 4 products per 16 terms of the
 // sum.  Wave w takes the blocks b = w (mod 4) for all row tiles; the four
 // partial sums are left in the slots of blocks 1..4 of vst (the own-site
 // slot, block 0, keeps the input) and summed by the reader.
@@ -237,14 +237,7 @@ TM_D void site_mv_mfma_pre(const bf16pair* __restrict__ Dm, cplx<float>* vst, Mf
           ar[e] = (short)(ac[ks][mt][e] & 0xffffu);
           ai[e] = (short)(ac[ks][mt][e] >> 16);
         }
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci[mt], 0, 0, 0);
+        mf_cmac(ar, ai, bb, accr[mt], acci[mt]);
       }
     }
   }
@@ -755,14 +748,7 @@ TM_D void mf_site_accumulate(const unsigned* __restrict__ Du, unsigned mask, In 
           ar[e] = (short)(ac[ks][mt][e] & 0xffffu);
           ai[e] = (short)(ac[ks][mt][e] >> 16);
         }
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr[mt], 0, 0, 0);
-        accr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci[mt], 0, 0, 0);
-        acci[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci[mt], 0, 0, 0);
+        mf_cmac(ar, ai, bb, accr[mt], acci[mt]);
       }
     }
     b = nb;

@@ -22,7 +22,7 @@ constexpr int GPM_TS = 16;   // sites per LDS tile of the matrix-core products
 //   P:      out_r(x)_k     = sum_i P_i(x)_k e_r[(s(k), i)],
 //           a (3072 x N_v) x (N_v x 16) product.
 // P is exact in bf16; the FP32 vectors are split into two bf16 parts (kept
-// to 2^-18 of their size); 16x16x16 bf16 MFMA tiles, FP32 accumulation.
+// to 2^-18 of their size); 16x16x32 bf16 MFMA tiles, FP32 accumulation.
 constexpr int TR_NR = 16;
 
 TM_D bool tr_unit(const FineGeom& g, int nrhs, int& y, int& r0) {
@@ -73,14 +73,7 @@ __global__ void __launch_bounds__(256) k_restrict_mf(FineGeom g, const bf16pair*
     const cplx<float> zv[4] = {mk(z01.x, z01.y), mk(z01.z, z01.w), mk(z23.x, z23.y), mk(z23.z, z23.w)};
     const MfSplit bb = mf_split(zv);
     // Re(conj(P) z) = Re P Re z + Im P Im z, Im(conj(P) z) = Re P Im z - Im P Re z
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+    mf_cmac_conj(ar, ai, bb, accr, acci);
   }
   // C tile: lane l holds rows (vectors) 16 mt + 4 (l / 16) + v, column (rhs) l % 16
 #pragma unroll
@@ -125,14 +118,7 @@ __global__ void __launch_bounds__(256) k_prolong_mf(FineGeom g, const bf16pair* 
       }
       const MfSplit bb = mf_split(bv);
       // Re(P e) = Re P Re e - Im P Im e, Im(P e) = Re P Im e + Im P Re e
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nih, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nil, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rh, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.rl, acci, 0, 0, 0);
+      mf_cmac(ar, ai, bb, accr, acci);
     }
     // C: lane l holds sites 4 (l / 16) + v of the tile for rhs l % 16; staged
     // in LDS so that each lane stores four consecutive sites of one rhs
@@ -922,7 +908,7 @@ __global__ void __launch_bounds__(256) k_galerkin_proj4(FineGeom g, const SP<S>*
 // over K = sites x 6 components,
 //   Re = Re P . Re Z + Im P . Im Z,   Im = Re P . Im Z - Im P . Re Z,
 // with P exact in bf16 and Z split into two bf16 parts (Z to 2^-18 of its
-// size), run as 16x16x16 bf16 MFMA tiles with FP32 accumulation.  Wave w
+// size), run as 16x16x32 bf16 MFMA tiles with FP32 accumulation.  Wave w
 // owns chirality w / 2 and row tile w % 2 (vectors 16 (w % 2) ..), so the
 // waves need no reduction.  Tiles of 16 sites of P (raw bf16 pairs) and Z
 // in LDS, loaded as in k_galerkin_proj4.
@@ -987,14 +973,7 @@ __global__ void __launch_bounds__(256) k_galerkin_proj_mf(FineGeom g, const bf16
         zv[e] = z;
       }
       const MfSplit bb = mf_split(zv);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rh, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.rl, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.ih, accr, 0, 0, 0);
-      accr = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.il, accr, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.ih, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bb.il, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrh, acci, 0, 0, 0);
-      acci = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bb.nrl, acci, 0, 0, 0);
+      mf_cmac_conj(ar, ai, bb, accr, acci);
     }
     __syncthreads();
   }
