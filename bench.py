@@ -703,6 +703,31 @@ def conditioning(args, iters=30):
     return 0
 
 
+def coarse_kernels(args):
+    """Timing loops of the level-1 matrix-core kernels on the workload's own
+    mixed-precision hierarchy (for profiler and counter passes): the
+    level-1 operator with 16 right-hand sides and one level-1 SAP sweep
+    (both colours, residual and 4 MR steps) with 12, 10 timed launches each
+    after one warm launch, and the level-2 operator with 12."""
+    import torch
+    import paper_1710_06198_amd as tm
+    from lattice_inputs import workload, gauge_links, load_m0
+    w = workload(args.workload)
+    m0 = load_m0()[w.name]
+    dev = torch.device("cuda:0")
+    U = torch.as_tensor(gauge_links(w.dims, w.eps, w.seeds["links"])).to(dev)
+    s = tm.Solver(w.dims, solver_params(tm, w, tm.MIXED), stream=torch.cuda.Stream(device=dev))
+    s.setup(U, 1.0 / (2 * m0 + 8), w.csw, w.mu)
+    vc, d = s.level_info(1)
+    out = {"workload": w.name, "level1_sites": vc, "d": d,
+           "coarse_op_l1_16rhs_ms": s.time_kernel(tm.K_DC1, 16, 10),
+           "sap1_sweep_12rhs_ms": s.time_kernel(tm.K_SAP1, 12, 10),
+           "coarse_op_l2_12rhs_ms": s.time_kernel(tm.K_DC2, 12, 10)}
+    print(json.dumps(out), flush=True)
+    s.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -724,6 +749,9 @@ def main():
     ap.add_argument("--conditioning", action="store_true",
                     help="estimate the smallest singular value of D(m0, mu=0) on the workload's lattice "
                          "(inverse iteration through the solver) instead of the benchmark")
+    ap.add_argument("--coarse-kernels", action="store_true",
+                    help="only the timing loops of the level-1 and level-2 matrix-core kernels on the "
+                         "workload's hierarchy (for profiler passes)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the timing loops of the fine stencil, the fine SAP (12 right-hand sides) and "
                          "the copy kernel on a context without a multigrid setup (for profiler passes)")
@@ -743,6 +771,8 @@ def main():
         return kernels_only(args)
     if args.conditioning:
         return conditioning(args)
+    if args.coarse_kernels:
+        return coarse_kernels(args)
     if args.workload == "c3":
         return bench_batched(args)
     if args.workload == "c4":
