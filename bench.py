@@ -299,7 +299,7 @@ def sap_roofline(tm, solver, V, nrhs, reps, mr_steps=4, workload_name="c3"):
     bound by FP32 vector issue, not by HBM (about 24 flops per algorithmic
     byte, against the chip's 20 at the packed-FMA peak): achieved is the
     algorithmic flop rate against the FP32 vector peak; the non-packed FMA
-    rate (the instructions this build emits) is given beside it, and so is
+    rate (the instructions the compiled kernels use) is given beside it, and so is
     the HBM view (algorithmic bytes per site of the colour: links and
     clover once, 576 B, and per right-hand side the source, the iterate
     read and written and the neighbouring iterate, 4 x 96 B)."""
