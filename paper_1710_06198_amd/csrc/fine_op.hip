@@ -392,11 +392,11 @@ template void launch_gamma5_fine<double>(const FineGeom&, const cplx<double>*, c
 template void launch_gamma5_fine<float>(const FineGeom&, const cplx<float>*, cplx<float>*, int, hipStream_t);
 
 // ------------------------------------------------------------------ SAP (K3)
-template <typename T, int MINB>
+template <typename T, int MINB, int BV>
 __global__ void __launch_bounds__(256, MINB) k_sap_fine(FineOp<T> op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                                                   const double* __restrict__ mu_dev, const int* __restrict__ blist,
                                                   int nblk, int nrhs, int mr_steps) {
-  sap_block_solve<T, MINB, false>(op, eta, z, mu_dev, blist, nblk, nrhs, mr_steps);
+  sap_block_solve<T, MINB, false, false, BV>(op, eta, z, mu_dev, blist, nblk, nrhs, mr_steps);
 }
 
 template <typename T>
@@ -419,15 +419,25 @@ void launch_sap_fine(const FineOp<T>& op, const cplx<T>* eta, cplx<T>* z, int nr
     }
     if (tv >= 0 ? tv == 1 : nrhs > 1) {
       const size_t sh3 = sh + (size_t)12 * op.g.bvol * sizeof(cplx<T>);   // and e
-      hipLaunchKernelGGL((k_sap_fine<T, 3>), dim3(n8 * nrhs), dim3(op.g.bvol), sh3, st, op, eta, z, mu_dev,
-                         block_list, nblk, nrhs, mr_steps);
+      // 4^4 blocks: the block volume as a constant turns the LDS addresses
+      // of the 12 components into immediate offsets of one base
+      if (op.g.bvol == 256)
+        hipLaunchKernelGGL((k_sap_fine<T, 3, 256>), dim3(n8 * nrhs), dim3(op.g.bvol), sh3, st, op, eta, z, mu_dev,
+                           block_list, nblk, nrhs, mr_steps);
+      else
+        hipLaunchKernelGGL((k_sap_fine<T, 3, 0>), dim3(n8 * nrhs), dim3(op.g.bvol), sh3, st, op, eta, z, mu_dev,
+                           block_list, nblk, nrhs, mr_steps);
       tune_used(TUNE_SAP0, 1);
       return;
     }
   }
   tune_used(TUNE_SAP0, 0);
-  hipLaunchKernelGGL((k_sap_fine<T, 1>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
-                     block_list, nblk, nrhs, mr_steps);
+  if (op.g.bvol == 256)
+    hipLaunchKernelGGL((k_sap_fine<T, 1, 256>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
+                       block_list, nblk, nrhs, mr_steps);
+  else
+    hipLaunchKernelGGL((k_sap_fine<T, 1, 0>), dim3(n8 * nrhs), dim3(op.g.bvol), sh, st, op, eta, z, mu_dev,
+                       block_list, nblk, nrhs, mr_steps);
 }
 template void launch_sap_fine<double>(const FineOp<double>&, const cplx<double>*, cplx<double>*, int, const double*,
                                       const int*, int, int, hipStream_t, double);

@@ -126,10 +126,10 @@ TM_D void site_dslash_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__
 // on the block-restricted operator D_B (hops leaving B dropped) from e = 0,
 // then z_B += e.  Blocks of one colour only neighbour blocks of the other
 // colour, so blocks of one launch never read what another writes.
-template <int MU, typename T>
+template <int MU, typename T, int BV = 0>
 TM_D void block_hops_dir(const FineOp<T>& op, const cplx<T>* lds, unsigned s, int loc, const int c[4], cplx<T>* acc) {
   const FineGeom& g = op.g;
-  const int bv = g.bvol;
+  const int bv = BV ? BV : g.bvol;
   const int lc = c[MU] % g.B[MU];
   const bool whole = g.NB[MU] == 1;    // block spans the periodic direction
   cplx<T> pn[12];
@@ -175,12 +175,12 @@ TM_D int block_nbr(const FineGeom& g, int loc, const int c[4]) {
 // Hop H of the block residual's gather: the neighbour's value from the
 // block's staged copy in LDS where the neighbour is in the block, from
 // memory where it is not; the link from memory.
-template <int H, typename T>
+template <int H, typename T, int BV = 0>
 TM_D void gather_hop_block(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
                            int loc, const int c[4], HopRegs<T>& r) {
   constexpr int MU = H >> 1;
   const long V = op.g.V;
-  const int bv = op.g.bvol;
+  const int bv = BV ? BV : op.g.bvol;
   const int nl = block_nbr<H>(op.g, loc, c);
   const unsigned sn = (unsigned)fine_neighbour(op.g, s, c, MU, (H & 1) ? -1 : +1);
   if (nl >= 0) {
@@ -191,15 +191,15 @@ TM_D void gather_hop_block(const FineOp<T>& op, const cplx<T>* __restrict__ in, 
   }
   r.u = load_link_u<MU>(op.links, (H & 1) ? sn : s, V);
 }
-template <int H, typename T>
+template <int H, typename T, int BV = 0>
 TM_D void block_hops_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
                                int loc, const int c[4], HopRegs<T>& a, HopRegs<T>& b, cplx<T>* acc) {
   if constexpr (H < 7) {
-    gather_hop_block<H + 1>(op, in, zl, s, loc, c, b);
+    gather_hop_block<H + 1, T, BV>(op, in, zl, s, loc, c, b);
     memory_fence_compiler();
     apply_hop<H>(a, acc);
     compiler_fence(acc);
-    block_hops_pipelined<H + 1>(op, in, zl, s, loc, c, b, a, acc);
+    block_hops_pipelined<H + 1, T, BV>(op, in, zl, s, loc, c, b, a, acc);
   } else {
     apply_hop<H>(a, acc);
   }
@@ -209,17 +209,17 @@ TM_D void block_hops_pipelined(const FineOp<T>& op, const cplx<T>* __restrict__ 
 // are staged in LDS (the workgroup has passed a barrier since): in-block
 // neighbours from LDS, the others and the links from memory, two hops in
 // flight; then the clover and twisted-mass term on the site's own value.
-template <typename T>
+template <typename T, int BV = 0>
 TM_D void block_site_dslash(const FineOp<T>& op, const cplx<T>* __restrict__ in, const cplx<T>* zl, unsigned s,
                             int loc, const int c[4], T mu, cplx<T>* acc) {
   const long V = op.g.V;
-  const int bv = op.g.bvol;
+  const int bv = BV ? BV : op.g.bvol;
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = mk<T>(0, 0);
   HopRegs<T> a, b;
-  gather_hop_block<0>(op, in, zl, s, loc, c, a);
+  gather_hop_block<0, T, BV>(op, in, zl, s, loc, c, a);
   memory_fence_compiler();
-  block_hops_pipelined<0>(op, in, zl, s, loc, c, a, b, acc);
+  block_hops_pipelined<0, T, BV>(op, in, zl, s, loc, c, a, b, acc);
   compiler_fence(acc);
   cplx<T> own[12];
 #pragma unroll
@@ -283,7 +283,7 @@ TM_D void block_reduce3_halves(T& a, T& b, T& c, T* red, int slot) {
 // flavour's D_B(+-mubar) plus -epsbar times the other flavour at the same
 // site, one MR step on both flavours together (one alpha from sums over
 // both halves).
-template <typename T, int MINB, bool PAIR, bool CPL = false>
+template <typename T, int MINB, bool PAIR, bool CPL = false, int BV = 0>
 TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, cplx<T>* z,
                           const double* __restrict__ mu_dev, const int* __restrict__ blist, int nblk, int nrhs,
                           int mr_steps, T epsbar = 0) {
@@ -291,7 +291,7 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
   extern __shared__ unsigned char smem_raw[];
   const FineGeom& g = op.g;
   const long V = g.V;
-  const int bv = g.bvol;
+  const int bv = BV ? BV : g.bvol;
   // batches (MINB 3): the block solution e lives in LDS next to the MR
   // vector, each thread touching only its own site (no barrier), which
   // frees the 24 registers that otherwise spill at three workgroups per CU
@@ -332,7 +332,7 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
 #pragma unroll
       for (int k = 0; k < 12; ++k) lds[k * bv + loc] = zs[k];
       __syncthreads();
-      block_site_dslash(op, zr, lds, s, loc, c, mu, dz);
+      block_site_dslash<T, BV>(op, zr, lds, s, loc, c, mu, dz);
     } else {
       site_dslash_pipelined(op, zr, s, mu, dz, zs);
     }
@@ -359,13 +359,13 @@ TM_D void sap_block_solve(const FineOp<T>& op, const cplx<T>* __restrict__ eta, 
     __syncthreads();
     site_diag(op, s, mu, rho, q);
     compiler_fence(q);
-    block_hops_dir<0>(op, lds, s, loc, c, q);
+    block_hops_dir<0, T, BV>(op, lds, s, loc, c, q);
     compiler_fence(q);
-    block_hops_dir<1>(op, lds, s, loc, c, q);
+    block_hops_dir<1, T, BV>(op, lds, s, loc, c, q);
     compiler_fence(q);
-    block_hops_dir<2>(op, lds, s, loc, c, q);
+    block_hops_dir<2, T, BV>(op, lds, s, loc, c, q);
     compiler_fence(q);
-    block_hops_dir<3>(op, lds, s, loc, c, q);
+    block_hops_dir<3, T, BV>(op, lds, s, loc, c, q);
     if constexpr (CPL) {
       // the other flavour's rho at this site, staged by the other half
       const cplx<T>* lo = reinterpret_cast<cplx<T>*>(smem_raw) + (half ^ 1) * 12 * bv;
