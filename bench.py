@@ -312,7 +312,7 @@ def sap_roofline(tm, solver, V, nrhs, reps, mr_steps=4, workload_name="c3"):
     return {"bound": "alu", "achieved": tfs, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
             "frac": tfs / FP32_VECTOR_PEAK_TFS,
             "traffic": kernel_traffic(SAP_TRAFFIC_RECORD, SAP_SOURCES, workload_name, "c3"),
-            "kernel": "k_sap_fine<float, 3> (fine SAP, one colour, 4 MR steps per block)",
+            "kernel": "k_sap_fine<float, 3, 256> (fine SAP, one colour, 4 MR steps per 4^4 block)",
             "rhs": nrhs, "sites_per_launch": sites, "flops_per_launch": flops,
             "flops_per_site_rhs": SAP_FLOPS_RESIDUAL + mr_steps * SAP_FLOPS_MR_STEP,
             "peak_nonpacked_fp32": FP32_NONPACKED_PEAK_TFS, "frac_nonpacked": tfs / FP32_NONPACKED_PEAK_TFS,
