@@ -414,6 +414,7 @@ void Ctx::ensure(int nrhs) {
   r64.alloc((size_t)cap * n);
   t64.alloc((size_t)cap * n);
   mu_dev.alloc(cap);
+  mu_cdev.alloc(cap);
   abstol_dev.alloc(cap);
   red_partial.alloc(1024 * (size_t)cap);
   red_out.alloc(2 * (size_t)cap);   // room for one complex result per right-hand side
@@ -448,6 +449,7 @@ void Ctx::upload_mu(int nrhs, const double* mu_host) {
       m[r] = mu_host[r];
     }
   launch_set_doubles(mu_dev.p, m.data(), nrhs, st);
+  mu_now = m;
 }
 
 // b64 holds the right-hand sides (internal layout); x64 receives the solutions.
@@ -500,20 +502,24 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     launch_fill_zero(x64.p, (size_t)nrhs * n * sizeof(cplx<double>), st);
     HIPCHK(hipMemcpyAsync(r64.p, b64.p, (size_t)nrhs * n * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
   }
+  // the right-hand sides of the current cycle (all of them, or the ones
+  // still above tol gathered into the first slots) and their twisted masses
+  int cur_n = nrhs;
+  const double* cur_mu = mu_d;
   OpFn<double> A64 = [&](const cplx<double>* in, cplx<double>* out) {
     hipEvent_t e0 = timer.begin(st);
-    launch_dslash<double>(o64, in, out, nrhs, mu_d, st);
+    launch_dslash<double>(o64, in, out, cur_n, cur_mu, st);
     if (nd) launch_flavour_couple<double>(in, out, -eps, n, st);
     timer.end(PhaseTimer::OUTER_OP, e0, st);
   };
   OpFn<float> A32 = [&](const cplx<float>* in, cplx<float>* out) {
     hipEvent_t e0 = timer.begin(st);
-    launch_dslash<float>(o32, in, out, nrhs, mu_d, st);
+    launch_dslash<float>(o32, in, out, cur_n, cur_mu, st);
     if (nd) launch_flavour_couple<float>(in, out, -eps, n, st);
     timer.end(PhaseTimer::OUTER_OP, e0, st);
   };
-  OpFn<double> M64 = [&](const cplx<double>* in, cplx<double>* out) { hier->precond_d(in, out, nrhs, mu_d); };
-  OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, nrhs, mu_d); };
+  OpFn<double> M64 = [&](const cplx<double>* in, cplx<double>* out) { hier->precond_d(in, out, cur_n, cur_mu); };
+  OpFn<float> M32 = [&](const cplx<float>* in, cplx<float>* out) { hier->precond_f(in, out, cur_n, cur_mu); };
   Krylov<double>& k64 = nd ? KN64 : K64;
   Krylov<float>& k32 = nd ? KN32 : K32;
   // the coarse levels of a doublet's cycle carry the flavour coupling
@@ -539,21 +545,69 @@ tmamg_status Ctx::solve_core(int nrhs, const double* mu_host, double tol, tmamg_
     }
     if (all) { status = TMAMG_OK; break; }
     if (iters >= par.max_iter) break;
+    // this cycle's absolute targets
+    for (int r = 0; r < nk; ++r)
+      at[r] = mixed ? std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]) : 0.9 * tol * bn[r];
+    // a right-hand side already at its target would sit idle in the cycle
+    // (the Krylov steps skip it) while the operator and the multigrid cycle
+    // still work on it: it stays out, the others are gathered into the first
+    // slots, and their corrections are scattered back
+    std::vector<int> act;
+    if (!nd)
+      for (int r = 0; r < nk; ++r)
+        if (rn[r] > at[r]) act.push_back(r);
+    const bool compact = !nd && !act.empty() && (int)act.size() < nk;
+    const int na = compact ? (int)act.size() : nk;
+    cur_n = compact ? na : nrhs;
+    cur_mu = mu_d;
+    if (compact) {
+      std::vector<double> mc(na);
+      for (int i = 0; i < na; ++i) mc[i] = mu_now[act[i]];
+      launch_set_doubles(mu_cdev.p, mc.data(), na, st);
+      cur_mu = mu_cdev.p;
+    }
+    auto set_abstol = [&]() {
+      std::vector<double> ac(na);
+      for (int i = 0; i < na; ++i) ac[i] = at[compact ? act[i] : i];
+      launch_set_doubles(abstol_dev.p, ac.data(), na, st);
+    };
     int it;
     if (!mixed) {
-      for (int r = 0; r < nk; ++r) at[r] = 0.9 * tol * bn[r];
-      launch_set_doubles(abstol_dev.p, at.data(), nk, st);
-      it = krylov_cycle<double>(k64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nk,
-                                std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
+      set_abstol();
+      if (compact) {
+        c64.alloc(std::max(c64.n, (size_t)na * n));
+        for (int i = 0; i < na; ++i)
+          HIPCHK(hipMemcpyAsync(t64.p + (size_t)i * n, r64.p + (size_t)act[i] * n, n * sizeof(cplx<double>),
+                                hipMemcpyDeviceToDevice, st));
+        launch_fill_zero(c64.p, (size_t)na * n * sizeof(cplx<double>), st);
+        it = krylov_cycle<double>(k64, A64, use_m ? &M64 : nullptr, t64.p, c64.p, na,
+                                  std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags,
+                                  st);
+        for (int i = 0; i < na; ++i)
+          launch_axpby<double>(c64.p + (size_t)i * n, x64.p + (size_t)act[i] * n, 1.0, 1.0, n, st);
+      } else {
+        it = krylov_cycle<double>(k64, A64, use_m ? &M64 : nullptr, r64.p, x64.p, nk,
+                                  std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags,
+                                  st);
+      }
     } else {
-      for (int r = 0; r < nk; ++r) at[r] = std::max(par.inner_tol * rn[r], 0.5 * tol * bn[r]);
-      launch_set_doubles(abstol_dev.p, at.data(), nk, st);
-      launch_convert<double, float>(r64.p, r32.p, (long)nrhs * n, st);
-      launch_fill_zero(e32.p, (size_t)nrhs * n * sizeof(cplx<float>), st);
-      it = krylov_cycle<float>(k32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, nk,
+      set_abstol();
+      if (compact)
+        for (int i = 0; i < na; ++i)
+          launch_convert<double, float>(r64.p + (size_t)act[i] * n, r32.p + (size_t)i * n, n, st);
+      else
+        launch_convert<double, float>(r64.p, r32.p, (long)nrhs * n, st);
+      launch_fill_zero(e32.p, (size_t)cur_n * n * sizeof(cplx<float>), st);
+      it = krylov_cycle<float>(k32, A32, use_m ? &M32 : nullptr, r32.p, e32.p, na,
                                std::min(par.restart, par.max_iter - iters), 0.0, abstol_dev.p, true, host_flags, st);
-      launch_add_to64<float>(e32.p, x64.p, (long)nrhs * n, st);
+      if (compact)
+        for (int i = 0; i < na; ++i)
+          launch_add_to64<float>(e32.p + (size_t)i * n, x64.p + (size_t)act[i] * n, n, st);
+      else
+        launch_add_to64<float>(e32.p, x64.p, (long)nrhs * n, st);
     }
+    cur_n = nrhs;
+    cur_mu = mu_d;
     iters += it;
     cycles += 1;
     // reliable update: r = b - D x in FP64

@@ -271,6 +271,11 @@ struct Ctx {
   DevArr<cplx<double>> b64, x64, r64, t64;
   DevArr<cplx<float>> r32, e32;
   DevArr<double> mu_dev, abstol_dev, red_partial, red_out;
+  // the twisted masses of the current solve (host), and the device copy
+  // for the right-hand sides of a compacted cycle
+  std::vector<double> mu_now;
+  DevArr<double> mu_cdev;
+  DevArr<cplx<double>> c64;   // FP64 corrections of a compacted cycle (allocated on first use)
   int* host_flags = nullptr;
   PhaseTimer timer;
   double t_setup = 0;
